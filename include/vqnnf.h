@@ -1,0 +1,208 @@
+/*
+ * vqnnf.h - C ABI of the MI355X (gfx950) VQ-NNF template-matching library.
+ *
+ * The library implements the data-parallel hot path of
+ *   Gupta & Sintorn, "Efficient High-Resolution Template Matching with Vector
+ *   Quantized Nearest Neighbour Fields" (arXiv 2306.15010):
+ *     codebook + NNF creation (Sec. 3.1, Alg. 1), one-hot integral images
+ *     (Sec. 3.1, Supp. S.2), coarse filters on integral images (Sec. 3.2,
+ *     eq. 1, Alg. 2), similarity (Sec. 3.3, eq. 2), localisation (Sec. 4).
+ *
+ * Problem statement (Sec. 3): a template tau of w x h x c and a query I of
+ * W x H x c; a similarity score for every w x h sub-window of I, and the best
+ * one.  Here c is called D (feature dimension).
+ *
+ * Conventions shared by every call:
+ *  - Feature maps are HWC: element (y, x, d) of a map sits at
+ *    data[(y*W + x)*pixel_stride + d], pixel_stride >= D elements.
+ *  - Pointers documented as "device" are HIP device pointers (e.g. a torch
+ *    tensor's data_ptr()); "host" pointers are ordinary CPU memory.
+ *  - The caller owns every input and output buffer.  The library owns its
+ *    handles and its scratch memory (capped by scratch_cap_bytes).
+ *  - Every GPU call is enqueued on the context's HIP stream and returns
+ *    before the work completes, except where a host output (best location,
+ *    flagged count) is requested: those calls synchronise the stream.
+ *  - Argument validation happens before any HIP call.  On error the call
+ *    returns a non-zero status, leaves no work enqueued, and
+ *    vqnnf_last_error() describes the problem (thread-local string).  Output
+ *    buffers are unspecified after an error.
+ *  - All floating-point inputs must be finite.
+ */
+#ifndef VQNNF_H
+#define VQNNF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VQNNF_OK = 0,
+  VQNNF_EINVAL = 1,   /* invalid argument (null pointer, bad size, bad enum) */
+  VQNNF_ENOMEM = 2,   /* scratch cap exceeded or device allocation failed   */
+  VQNNF_EHIP = 3,     /* a HIP runtime call failed                          */
+  VQNNF_ENOTSUP = 4,  /* device is not gfx950, or combination not supported  */
+  VQNNF_EHANDLE = 5   /* null or already-freed handle                       */
+} vqnnf_status;
+
+/* Storage type of a feature map. */
+typedef enum {
+  VQNNF_F32 = 0,      /* IEEE binary32                                      */
+  VQNNF_BF16 = 1,     /* bfloat16 bit patterns (uint16)                     */
+  VQNNF_FP8_E4M3 = 2  /* OCP E4M3FN codes (uint8) times a per-channel scale */
+} vqnnf_dtype;
+
+/* Arithmetic used for the nearest-codeword search. */
+typedef enum {
+  /* FP32 matrix-core distances ||c||^2 - 2 q.c and a plain argmin.  No
+   * refinement: a label may differ from the exact FP64 nearest neighbour
+   * when two codewords are nearly equidistant. */
+  VQNNF_PREC_FP32_PLAIN = 0,
+  /* BF16 matrix-core distances with FP32 accumulation (codebook split into
+   * BF16 hi + lo terms; FP32-stored queries split too), a per-pixel error
+   * bound, and an FP64 re-score of every pixel whose best-to-second gap is
+   * inside the bound.  Labels equal the FP64 nearest neighbour computed in
+   * the fixed order d = sum_t (q_t - c_t)^2 (sequential in t, no FMA),
+   * lowest index on ties. */
+  VQNNF_PREC_BF16_REFINED = 1
+} vqnnf_prec;
+
+/* A feature map (query or template). */
+typedef struct {
+  const void* data;            /* see each call for host/device            */
+  int32_t dtype;               /* vqnnf_dtype                               */
+  int32_t H, W, D;             /* rows, columns, feature dimension          */
+  int64_t pixel_stride;        /* elements between pixels; 0 means D        */
+  const float* channel_scale;  /* FP8 only: host float[D]; else NULL        */
+} vqnnf_fmap;
+
+/* One entry of the filter bank (Sec. 3.2): the region [x0,x1) x [y0,y1) of
+ * the template, split into a gx x gy grid with bin edges
+ * x0 + floor(a*(x1-x0)/gx), y0 + floor(b*(y1-y0)/gy).
+ *  - bin_weight == NULL: every bin is its own indicator filter (a k-channel
+ *    histogram); its score weight is weight / (gx*gy*area(bin)).
+ *  - bin_weight != NULL: not supported by this version (VQNNF_ENOTSUP). */
+typedef struct {
+  int32_t x0, y0, x1, y1;
+  int32_t gx, gy;
+  const float* bin_weight;     /* host, gy*gx row-major, or NULL            */
+  float weight;
+} vqnnf_filter_desc;
+
+typedef struct vqnnf_ctx vqnnf_ctx;
+typedef struct vqnnf_template vqnnf_template;
+
+/* Creates a context bound to the current HIP device and `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  scratch_cap_bytes bounds the
+ * device scratch the context may hold (0 = 16 GiB).  Returns ENOTSUP if the
+ * current device is not gfx950. */
+vqnnf_status vqnnf_ctx_create(void* hip_stream, uint64_t scratch_cap_bytes, vqnnf_ctx** out);
+
+/* Creates a context with no device.  Templates are prepared on the host
+ * (k-means, template NNF, counts and every getter work); every GPU call
+ * validates its arguments and the scratch cap, then returns VQNNF_ENOTSUP.
+ * Useful for host-only tools and for checking argument handling. */
+vqnnf_status vqnnf_ctx_create_host(uint64_t scratch_cap_bytes, vqnnf_ctx** out);
+void vqnnf_ctx_destroy(vqnnf_ctx* ctx);
+
+/* Template preparation (Sec. 3.1, Sec. 4 "K-means computation"): k-means of
+ * the template's w*h feature vectors (row-major order), seeded k-means++
+ * (splitmix64 stream from `seed`) then exactly `lloyd_iters` Lloyd
+ * iterations in FP64, rounded to FP32; then the template's NNF (same FP64
+ * rule as VQNNF_PREC_BF16_REFINED) and its representation R(tau): the
+ * counts of every filter of `bank` over the template (Sec. 3.3).
+ *  tmpl: HOST map, dtype VQNNF_F32, H = h, W = w.
+ *  k in [1, 256]; bank: host array of n_desc >= 1 entries, each region
+ *  inside [0,w) x [0,h) with non-empty bins.
+ * Runs on the host; uploads the handle's tables to the device. */
+vqnnf_status vqnnf_codebook(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, int32_t k, int32_t lloyd_iters,
+                            uint64_t seed, const vqnnf_filter_desc* bank, int32_t n_desc,
+                            vqnnf_template** out);
+
+/* Same as vqnnf_codebook but with a caller-supplied codebook (host float
+ * [k][D], FP32) instead of k-means: used to restore an exported template and
+ * to run every stage against an independently computed codebook. */
+vqnnf_status vqnnf_template_from_codebook(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl,
+                                          const float* codebook, int32_t k,
+                                          const vqnnf_filter_desc* bank, int32_t n_desc,
+                                          vqnnf_template** out);
+void vqnnf_template_free(vqnnf_template* t);
+
+/* Template getters (host outputs).  info: w, h, D, k, number of expanded
+ * filters.  codebook: float[k][D].  labels: uint8[h][w].  counts: int32
+ * [n_filters][k] (R(tau)).  weights: float[n_filters]. */
+vqnnf_status vqnnf_template_info(const vqnnf_template* t, int32_t* w, int32_t* h, int32_t* D,
+                                 int32_t* k, int32_t* n_filters);
+vqnnf_status vqnnf_template_codebook(const vqnnf_template* t, float* out);
+vqnnf_status vqnnf_template_labels(const vqnnf_template* t, uint8_t* out);
+vqnnf_status vqnnf_template_counts(const vqnnf_template* t, int32_t* out);
+vqnnf_status vqnnf_template_weights(const vqnnf_template* t, float* out);
+
+/* NNF of a query map (Alg. 1): labels[y*W + x] = index of the nearest
+ * codeword of pixel (y, x) (squared L2, lowest index on ties).
+ *  query: DEVICE map, dtype F32 or BF16, query->D == template D.
+ *  labels: DEVICE uint8[H*W].
+ *  n_flagged: HOST, may be NULL; receives the number of pixels re-scored in
+ *  FP64 (0 for VQNNF_PREC_FP32_PLAIN).  Non-NULL synchronises. */
+vqnnf_status vqnnf_assign(vqnnf_ctx* ctx, const vqnnf_template* t, const vqnnf_fmap* query,
+                          int32_t prec, uint8_t* labels, int64_t* n_flagged);
+
+/* One-hot integral image of a label map (Sec. 3.1, Supp. S.2):
+ *   integral[(y*(W+1) + x)*k + j] = #{(x', y') : y' < y, x' < x,
+ *                                      labels[y'*W + x'] == j}
+ * for 0 <= y <= H, 0 <= x <= W (exclusive and zero padded, channel-last,
+ * exact int32; the paper's inclusive value at (x, y) is entry (y+1, x+1)).
+ *  labels: DEVICE uint8[H*W], every value < k.  integral: DEVICE int32
+ *  [(H+1)*(W+1)*k].  Requires (H+1)*(W+1)*k < 2^62 and H*W < 2^31. */
+vqnnf_status vqnnf_filter(vqnnf_ctx* ctx, const vqnnf_template* t, const uint8_t* labels,
+                          int32_t H, int32_t W, int32_t* integral);
+
+/* Similarity heatmap from a label map (Sec. 3.2-3.3, eq. 2, Sec. 4):
+ *   heatmap[y*(W-w+1) + x] = -sum_f weight_f * sum_j |R_f,j(tau) - C_f,j(x,y)|
+ * where C_f,j(x,y) counts label j in filter f's box shifted to the window
+ * whose top-left is (x, y); only windows inside the map are scored.  The
+ * per-filter L1 is exact integer arithmetic; the weighted sum is FP32 in
+ * filter order.  best_xy/best_score: HOST, may be NULL; the first maximum in
+ * row-major order (non-NULL synchronises).
+ *  labels: DEVICE uint8[H*W]; heatmap: DEVICE float[(H-h+1)*(W-w+1)];
+ *  requires w <= W, h <= H. */
+vqnnf_status vqnnf_score(vqnnf_ctx* ctx, const vqnnf_template* t, const uint8_t* labels,
+                         int32_t H, int32_t W, float* heatmap, int32_t* best_xy,
+                         float* best_score);
+
+/* Same heatmap computed from a one-hot integral image produced by
+ * vqnnf_filter (the taps of Alg. 2's dilation filters read directly from
+ * `integral`, DEVICE int32[(H+1)*(W+1)*k]). */
+vqnnf_status vqnnf_score_integral(vqnnf_ctx* ctx, const vqnnf_template* t,
+                                  const int32_t* integral, int32_t H, int32_t W, float* heatmap,
+                                  int32_t* best_xy, float* best_score);
+
+/* The whole hot path for one (template, query) pair: vqnnf_assign, then the
+ * filter bank and eq. 2 on the resulting NNF (integral images built tile by
+ * tile on chip), then localisation.  Arguments as in vqnnf_assign and
+ * vqnnf_score; the label map lives in library scratch. */
+vqnnf_status vqnnf_match(vqnnf_ctx* ctx, const vqnnf_template* t, const vqnnf_fmap* query,
+                         int32_t prec, float* heatmap, int32_t* best_xy, float* best_score);
+
+/* Per-kernel timing.  When enabled, the library brackets every kernel it
+ * launches with HIP events on the context stream.  vqnnf_ctx_kernel_times
+ * synchronises, then reports for each kernel name (up to max_entries)
+ * the number of launches and their total duration in milliseconds since the
+ * last reset.  names receives pointers to static strings. */
+vqnnf_status vqnnf_ctx_set_timing(vqnnf_ctx* ctx, int32_t enable);
+vqnnf_status vqnnf_ctx_kernel_times(vqnnf_ctx* ctx, int32_t max_entries, const char** names,
+                                    int64_t* launches, double* total_ms, int32_t* n_entries);
+vqnnf_status vqnnf_ctx_reset_times(vqnnf_ctx* ctx);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* vqnnf_last_error(void);
+
+/* Library version string. */
+const char* vqnnf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VQNNF_H */

@@ -1,0 +1,297 @@
+"""Thin Python binding of the vqnnf C ABI (include/vqnnf.h).
+
+Argument marshalling only: every step of the hot path runs in the gfx950
+kernels of libvqnnf.so.  Device buffers are torch tensors (their data_ptr()
+is passed through); host arrays are numpy arrays.  Loading fails loudly when
+the library has not been built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvqnnf.so")
+
+VQNNF_OK, VQNNF_EINVAL, VQNNF_ENOMEM, VQNNF_EHIP, VQNNF_ENOTSUP, VQNNF_EHANDLE = range(6)
+VQNNF_F32, VQNNF_BF16, VQNNF_FP8_E4M3 = 0, 1, 2
+VQNNF_PREC_FP32_PLAIN, VQNNF_PREC_BF16_REFINED = 0, 1
+
+EXPORTED = [
+    "vqnnf_ctx_create", "vqnnf_ctx_create_host", "vqnnf_ctx_destroy", "vqnnf_codebook",
+    "vqnnf_template_from_codebook", "vqnnf_template_free", "vqnnf_template_info",
+    "vqnnf_template_codebook", "vqnnf_template_labels", "vqnnf_template_counts",
+    "vqnnf_template_weights", "vqnnf_assign", "vqnnf_filter", "vqnnf_score",
+    "vqnnf_score_integral", "vqnnf_match", "vqnnf_ctx_set_timing", "vqnnf_ctx_kernel_times",
+    "vqnnf_ctx_reset_times", "vqnnf_last_error", "vqnnf_version",
+]
+
+
+class VqnnfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"vqnnf status {status}: {msg}")
+        self.status = status
+
+
+class FMap(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("H", C.c_int32), ("W", C.c_int32),
+                ("D", C.c_int32), ("pixel_stride", C.c_int64), ("channel_scale", C.c_void_p)]
+
+
+class FilterDesc(C.Structure):
+    _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("x1", C.c_int32), ("y1", C.c_int32),
+                ("gx", C.c_int32), ("gy", C.c_int32), ("bin_weight", C.c_void_p),
+                ("weight", C.c_float)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(no fallback implementation exists)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u64, st = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_int
+    P = C.POINTER
+    sig = {
+        "vqnnf_ctx_create": (st, [vp, u64, P(vp)]),
+        "vqnnf_ctx_create_host": (st, [u64, P(vp)]),
+        "vqnnf_ctx_destroy": (None, [vp]),
+        "vqnnf_codebook": (st, [vp, P(FMap), i32, i32, u64, P(FilterDesc), i32, P(vp)]),
+        "vqnnf_template_from_codebook": (st, [vp, P(FMap), vp, i32, P(FilterDesc), i32, P(vp)]),
+        "vqnnf_template_free": (None, [vp]),
+        "vqnnf_template_info": (st, [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]),
+        "vqnnf_template_codebook": (st, [vp, vp]),
+        "vqnnf_template_labels": (st, [vp, vp]),
+        "vqnnf_template_counts": (st, [vp, vp]),
+        "vqnnf_template_weights": (st, [vp, vp]),
+        "vqnnf_assign": (st, [vp, vp, P(FMap), i32, vp, P(i64)]),
+        "vqnnf_filter": (st, [vp, vp, vp, i32, i32, vp]),
+        "vqnnf_score": (st, [vp, vp, vp, i32, i32, vp, P(i32), P(C.c_float)]),
+        "vqnnf_score_integral": (st, [vp, vp, vp, i32, i32, vp, P(i32), P(C.c_float)]),
+        "vqnnf_match": (st, [vp, vp, P(FMap), i32, vp, P(i32), P(C.c_float)]),
+        "vqnnf_ctx_set_timing": (st, [vp, i32]),
+        "vqnnf_ctx_kernel_times": (st, [vp, i32, P(C.c_char_p), P(i64), P(C.c_double), P(i32)]),
+        "vqnnf_ctx_reset_times": (st, [vp]),
+        "vqnnf_last_error": (C.c_char_p, []),
+        "vqnnf_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != VQNNF_OK:
+        raise VqnnfError(status, lib().vqnnf_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().vqnnf_last_error().decode()
+
+
+# ------------------------------------------------------------------ maps
+
+_DT = {"f32": VQNNF_F32, "bf16": VQNNF_BF16, "fp8": VQNNF_FP8_E4M3}
+
+
+def host_fmap(arr: np.ndarray) -> Tuple[FMap, np.ndarray]:
+    """FP32 host map [H][W][D] (the array is kept alive by the caller)."""
+    a = np.ascontiguousarray(arr, dtype=np.float32)
+    H, W, D = a.shape
+    return FMap(a.ctypes.data, VQNNF_F32, H, W, D, D, None), a
+
+
+def device_fmap(t, dtype: str, channel_scale: Optional[np.ndarray] = None) -> FMap:
+    """Device map from a torch tensor [H][W][D(+pad)] (float32 / uint16 bits /
+    bfloat16 / uint8 codes); the last dimension may exceed D via `stride`."""
+    H, W, S = t.shape[0], t.shape[1], t.shape[2]
+    assert t.is_contiguous()
+    scale = None
+    if channel_scale is not None:
+        channel_scale = np.ascontiguousarray(channel_scale, dtype=np.float32)
+        scale = channel_scale.ctypes.data
+    return FMap(t.data_ptr(), _DT[dtype], H, W, S, S, scale)
+
+
+def bank_descs(bank: Sequence[Tuple[int, int, int, int, int, int, float]]):
+    arr = (FilterDesc * len(bank))()
+    for i, (x0, y0, x1, y1, gx, gy, w) in enumerate(bank):
+        arr[i] = FilterDesc(x0, y0, x1, y1, gx, gy, None, w)
+    return arr
+
+
+def default_bank(w: int, h: int, g: int):
+    """Full window plus a g x g grid over it, each with weight 1."""
+    return [(0, 0, w, h, 1, 1, 1.0), (0, 0, w, h, g, g, 1.0)]
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# ------------------------------------------------------------------ handles
+
+class Context:
+    def __init__(self, stream=None, scratch_cap: int = 0, host: bool = False):
+        h = C.c_void_p()
+        if host:
+            _check(lib().vqnnf_ctx_create_host(scratch_cap, C.byref(h)))
+        else:
+            _check(lib().vqnnf_ctx_create(_stream_ptr(stream), scratch_cap, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().vqnnf_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, on: bool):
+        _check(lib().vqnnf_ctx_set_timing(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        n = 32
+        names = (C.c_char_p * n)()
+        launches = (C.c_int64 * n)()
+        ms = (C.c_double * n)()
+        cnt = C.c_int32()
+        _check(lib().vqnnf_ctx_kernel_times(self.h, n, names, launches, ms, C.byref(cnt)))
+        return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(min(n, cnt.value))}
+
+    def reset_times(self):
+        _check(lib().vqnnf_ctx_reset_times(self.h))
+
+
+class Template:
+    def __init__(self, ctx: Context, handle: C.c_void_p):
+        self.ctx = ctx
+        self.h = handle
+        w, h, D, k, nf = (C.c_int32() for _ in range(5))
+        _check(lib().vqnnf_template_info(handle, C.byref(w), C.byref(h), C.byref(D), C.byref(k),
+                                         C.byref(nf)))
+        self.w, self.h_, self.D, self.k, self.n_filters = w.value, h.value, D.value, k.value, nf.value
+
+    @property
+    def height(self):
+        return self.h_
+
+    def free(self):
+        if self.h:
+            lib().vqnnf_template_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def codebook(self) -> np.ndarray:
+        out = np.empty((self.k, self.D), dtype=np.float32)
+        _check(lib().vqnnf_template_codebook(self.h, out.ctypes.data))
+        return out
+
+    def labels(self) -> np.ndarray:
+        out = np.empty((self.h_, self.w), dtype=np.uint8)
+        _check(lib().vqnnf_template_labels(self.h, out.ctypes.data))
+        return out
+
+    def counts(self) -> np.ndarray:
+        out = np.empty((self.n_filters, self.k), dtype=np.int32)
+        _check(lib().vqnnf_template_counts(self.h, out.ctypes.data))
+        return out
+
+    def weights(self) -> np.ndarray:
+        out = np.empty(self.n_filters, dtype=np.float32)
+        _check(lib().vqnnf_template_weights(self.h, out.ctypes.data))
+        return out
+
+
+# ------------------------------------------------------------------ calls (C names)
+
+def vqnnf_codebook(ctx: Context, template: np.ndarray, k: int, lloyd_iters: int, seed: int,
+                   bank) -> Template:
+    fm, keep = host_fmap(template)
+    descs = bank_descs(bank)
+    h = C.c_void_p()
+    _check(lib().vqnnf_codebook(ctx.h, C.byref(fm), k, lloyd_iters, seed, descs, len(bank),
+                                C.byref(h)))
+    return Template(ctx, h)
+
+
+def vqnnf_template_from_codebook(ctx: Context, template: np.ndarray, codebook: np.ndarray,
+                                 bank) -> Template:
+    fm, keep = host_fmap(template)
+    cb = np.ascontiguousarray(codebook, dtype=np.float32)
+    descs = bank_descs(bank)
+    h = C.c_void_p()
+    _check(lib().vqnnf_template_from_codebook(ctx.h, C.byref(fm), cb.ctypes.data, cb.shape[0],
+                                              descs, len(bank), C.byref(h)))
+    return Template(ctx, h)
+
+
+def vqnnf_assign(ctx: Context, tpl: Template, query: FMap, prec: int, labels) -> int:
+    n = C.c_int64()
+    _check(lib().vqnnf_assign(ctx.h, tpl.h, C.byref(query), prec, C.c_void_p(labels.data_ptr()),
+                              C.byref(n)))
+    return int(n.value)
+
+
+def vqnnf_filter(ctx: Context, tpl: Template, labels, H: int, W: int, integral) -> None:
+    _check(lib().vqnnf_filter(ctx.h, tpl.h, C.c_void_p(labels.data_ptr()), H, W,
+                              C.c_void_p(integral.data_ptr())))
+
+
+def _best_out(st, xy, sc):
+    _check(st)
+    return (int(xy[0]), int(xy[1])), float(sc.value)
+
+
+def vqnnf_score(ctx: Context, tpl: Template, labels, H: int, W: int, heatmap):
+    xy = (C.c_int32 * 2)()
+    sc = C.c_float()
+    st = lib().vqnnf_score(ctx.h, tpl.h, C.c_void_p(labels.data_ptr()), H, W,
+                           C.c_void_p(heatmap.data_ptr()), xy, C.byref(sc))
+    return _best_out(st, xy, sc)
+
+
+def vqnnf_score_integral(ctx: Context, tpl: Template, integral, H: int, W: int, heatmap):
+    xy = (C.c_int32 * 2)()
+    sc = C.c_float()
+    st = lib().vqnnf_score_integral(ctx.h, tpl.h, C.c_void_p(integral.data_ptr()), H, W,
+                                    C.c_void_p(heatmap.data_ptr()), xy, C.byref(sc))
+    return _best_out(st, xy, sc)
+
+
+def vqnnf_match(ctx: Context, tpl: Template, query: FMap, prec: int, heatmap, want_best=True):
+    if not want_best:
+        _check(lib().vqnnf_match(ctx.h, tpl.h, C.byref(query), prec,
+                                 C.c_void_p(heatmap.data_ptr()), None, None))
+        return None
+    xy = (C.c_int32 * 2)()
+    sc = C.c_float()
+    st = lib().vqnnf_match(ctx.h, tpl.h, C.byref(query), prec, C.c_void_p(heatmap.data_ptr()),
+                           xy, C.byref(sc))
+    return _best_out(st, xy, sc)
+
+
+def vqnnf_version() -> str:
+    return lib().vqnnf_version().decode()

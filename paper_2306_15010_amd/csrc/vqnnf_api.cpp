@@ -1,0 +1,748 @@
+// C ABI of the VQ-NNF library: contexts, templates, validation, scratch
+// management, timing and the orchestration of the gfx950 kernels.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "vqnnf_internal.h"
+
+using namespace vqnnf;
+
+namespace {
+
+thread_local std::string g_err;
+
+vqnnf_status fail(vqnnf_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+vqnnf_status ok() { return VQNNF_OK; }
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(VQNNF_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));                \
+  } while (0)
+
+constexpr int kCtxMagic = 0x51CE7001;
+constexpr int kTplMagic = 0x7E3B1A7E;
+
+struct Buffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct TimingRecord {
+  int id;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct vqnnf_ctx {
+  int magic = kCtxMagic;
+  bool has_device = false;
+  int device = -1;
+  int n_cu = 256;
+  hipStream_t stream = nullptr;
+  uint64_t cap = 0;
+  uint64_t used = 0;
+  // scratch
+  Buffer control;      // [0]: u64 best, [8]: u32 worklist count
+  Buffer labels;       // uint8 [n_pix]
+  Buffer wl_pix;       // u32 [n_pix]
+  Buffer wl_mask;      // u32 [n_pix][mask_words]
+  Buffer int_side;     // integral side arrays
+  Buffer int_p;        // integral image for the integral score path
+  // timing
+  bool timing = false;
+  std::vector<TimingRecord> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t launches[K_COUNT] = {};
+  double total_ms[K_COUNT] = {};
+};
+
+struct vqnnf_template {
+  int magic = kTplMagic;
+  vqnnf_ctx* ctx = nullptr;
+  DeviceTemplate t;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- timing
+void hook_begin(void* user, int id) {
+  auto* c = (vqnnf_ctx*)user;
+  TimingRecord r{id, nullptr, nullptr};
+  if (c->pool.size() >= 2) {
+    r.a = c->pool.back(); c->pool.pop_back();
+    r.b = c->pool.back(); c->pool.pop_back();
+  } else {
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+  }
+  hipEventRecord(r.a, c->stream);
+  c->pending.push_back(r);
+}
+void hook_end(void* user, int id) {
+  auto* c = (vqnnf_ctx*)user;
+  if (c->pending.empty() || c->pending.back().id != id) return;
+  hipEventRecord(c->pending.back().b, c->stream);
+}
+
+struct HookScope {
+  bool on;
+  explicit HookScope(vqnnf_ctx* c) : on(c->timing) {
+    if (on) {
+      TimingHook h{hook_begin, hook_end, c};
+      set_timing_hook(&h);
+    }
+  }
+  ~HookScope() {
+    if (on) set_timing_hook(nullptr);
+  }
+};
+
+vqnnf_status collect_times(vqnnf_ctx* c) {
+  if (c->pending.empty()) return ok();
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto& r : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->launches[r.id] += 1;
+      c->total_ms[r.id] += ms;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->pending.clear();
+  return ok();
+}
+
+// ---------------------------------------------------------------- scratch
+vqnnf_status ensure(vqnnf_ctx* c, Buffer& b, size_t bytes, const char* what) {
+  if (bytes <= b.bytes) return ok();
+  size_t grow = std::max(bytes, b.bytes + b.bytes / 4);
+  grow = (grow + 255) & ~size_t(255);
+  uint64_t after = c->used - b.bytes + grow;
+  if (after > c->cap) {
+    grow = (bytes + 255) & ~size_t(255);
+    after = c->used - b.bytes + grow;
+    if (after > c->cap)
+      return fail(VQNNF_ENOMEM, "%s needs %zu bytes of scratch; the context cap is %llu bytes "
+                  "(%llu in use)", what, bytes, (unsigned long long)c->cap,
+                  (unsigned long long)(c->used - b.bytes));
+  }
+  if (!c->has_device)
+    return fail(VQNNF_ENOTSUP, "context has no device (created with vqnnf_ctx_create_host)");
+  if (b.p) {
+    // the stream may still use the old buffer
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(b.p));
+    c->used -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, grow);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(VQNNF_ENOMEM, "hipMalloc(%zu) for %s failed: %s", grow, what, hipGetErrorString(e));
+  }
+  b.bytes = grow;
+  c->used += grow;
+  return ok();
+}
+
+// Checks scratch needs against the cap before anything is enqueued.
+vqnnf_status check_cap(vqnnf_ctx* c, std::initializer_list<std::pair<const Buffer*, size_t>> need) {
+  uint64_t total = c->used;
+  for (auto& n : need)
+    if (n.second > n.first->bytes) total = total - n.first->bytes + ((n.second + 255) & ~size_t(255));
+  if (total > c->cap)
+    return fail(VQNNF_ENOMEM, "call needs %llu bytes of scratch in total; the context cap is %llu",
+                (unsigned long long)total, (unsigned long long)c->cap);
+  return ok();
+}
+
+// ---------------------------------------------------------------- validation
+vqnnf_status check_ctx(const vqnnf_ctx* c) {
+  if (!c) return fail(VQNNF_EHANDLE, "null context");
+  if (c->magic != kCtxMagic) return fail(VQNNF_EHANDLE, "invalid or destroyed context");
+  return ok();
+}
+
+vqnnf_status check_tpl(const vqnnf_ctx* c, const vqnnf_template* t) {
+  if (!t) return fail(VQNNF_EHANDLE, "null template");
+  if (t->magic != kTplMagic) return fail(VQNNF_EHANDLE, "invalid or freed template");
+  if (c && t->ctx != c) return fail(VQNNF_EINVAL, "template belongs to another context");
+  return ok();
+}
+
+size_t dtype_size(int dt) {
+  switch (dt) {
+    case VQNNF_F32: return 4;
+    case VQNNF_BF16: return 2;
+    case VQNNF_FP8_E4M3: return 1;
+  }
+  return 0;
+}
+
+vqnnf_status check_map(const vqnnf_fmap* m, const char* what) {
+  if (!m) return fail(VQNNF_EINVAL, "%s: null map", what);
+  if (!m->data) return fail(VQNNF_EINVAL, "%s: null data pointer", what);
+  if (dtype_size(m->dtype) == 0) return fail(VQNNF_EINVAL, "%s: unknown dtype %d", what, m->dtype);
+  if (m->H < 1 || m->W < 1) return fail(VQNNF_EINVAL, "%s: H and W must be >= 1 (got %d x %d)", what, m->H, m->W);
+  if (m->D < 1) return fail(VQNNF_EINVAL, "%s: D must be >= 1 (got %d)", what, m->D);
+  int64_t st = m->pixel_stride ? m->pixel_stride : m->D;
+  if (st < m->D) return fail(VQNNF_EINVAL, "%s: pixel_stride %lld < D %d", what, (long long)st, m->D);
+  if ((int64_t)m->H * m->W >= (1ll << 31)) return fail(VQNNF_EINVAL, "%s: H*W must be < 2^31", what);
+  if (m->dtype == VQNNF_FP8_E4M3 && !m->channel_scale)
+    return fail(VQNNF_EINVAL, "%s: FP8 map needs channel_scale", what);
+  return ok();
+}
+
+vqnnf_status expand_bank(const vqnnf_filter_desc* bank, int n_desc, int w, int h,
+                         DeviceTemplate& t) {
+  if (!bank || n_desc < 1) return fail(VQNNF_EINVAL, "filter bank: need n_desc >= 1 and a bank pointer");
+  t.boxes.clear();
+  t.weights.clear();
+  for (int i = 0; i < n_desc; ++i) {
+    const vqnnf_filter_desc& d = bank[i];
+    if (d.x0 < 0 || d.y0 < 0 || d.x1 > w || d.y1 > h || d.x0 >= d.x1 || d.y0 >= d.y1)
+      return fail(VQNNF_EINVAL, "filter %d: region [%d,%d)x[%d,%d) not inside the %dx%d template",
+                  i, d.x0, d.x1, d.y0, d.y1, w, h);
+    if (d.gx < 1 || d.gy < 1 || d.gx > d.x1 - d.x0 || d.gy > d.y1 - d.y0)
+      return fail(VQNNF_EINVAL, "filter %d: grid %dx%d leaves empty bins", i, d.gx, d.gy);
+    if (d.bin_weight)
+      return fail(VQNNF_ENOTSUP, "filter %d: weighted bins are not supported", i);
+    if (!std::isfinite(d.weight)) return fail(VQNNF_EINVAL, "filter %d: weight not finite", i);
+    for (int b = 0; b < d.gy; ++b)
+      for (int a = 0; a < d.gx; ++a) {
+        int bx0 = d.x0 + (int)((int64_t)a * (d.x1 - d.x0) / d.gx);
+        int bx1 = d.x0 + (int)((int64_t)(a + 1) * (d.x1 - d.x0) / d.gx);
+        int by0 = d.y0 + (int)((int64_t)b * (d.y1 - d.y0) / d.gy);
+        int by1 = d.y0 + (int)((int64_t)(b + 1) * (d.y1 - d.y0) / d.gy);
+        double area = (double)(bx1 - bx0) * (double)(by1 - by0);
+        double wt = (double)d.weight / ((double)d.gx * d.gy * area);
+        t.boxes.insert(t.boxes.end(), {bx0, by0, bx1, by1});
+        t.weights.push_back((float)wt);
+      }
+  }
+  t.n_filters = (int)t.weights.size();
+  // Is it the full window plus one g x g grid over the full window?
+  GridBank gb{};
+  gb.valid = false;
+  if (n_desc == 2 && bank[0].x0 == 0 && bank[0].y0 == 0 && bank[0].x1 == w && bank[0].y1 == h &&
+      bank[0].gx == 1 && bank[0].gy == 1 && bank[1].x0 == 0 && bank[1].y0 == 0 &&
+      bank[1].x1 == w && bank[1].y1 == h && bank[1].gx == bank[1].gy && bank[1].gx >= 1 &&
+      bank[1].gx <= 4) {
+    gb.valid = true;
+    gb.g = bank[1].gx;
+    for (int a = 0; a <= gb.g; ++a) {
+      gb.xe[a] = (int)((int64_t)a * w / gb.g);
+      gb.ye[a] = (int)((int64_t)a * h / gb.g);
+    }
+  }
+  t.grid = gb;
+  return ok();
+}
+
+template <typename T>
+vqnnf_status upload(vqnnf_ctx* c, T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return ok();
+  HIP_TRY(hipMalloc((void**)dst, sizeof(T) * src.size()));
+  HIP_TRY(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+  return ok();
+}
+
+void free_device(DeviceTemplate& t) {
+  void* ps[] = {t.d_codebook, t.d_frag_bf16, t.d_frag_f32, t.d_cnorm, t.d_counts, t.d_counts16,
+                t.d_weights, t.d_boxes};
+  for (void* p : ps)
+    if (p) hipFree(p);
+  t.d_codebook = nullptr; t.d_frag_bf16 = nullptr; t.d_frag_f32 = nullptr; t.d_cnorm = nullptr;
+  t.d_counts = nullptr; t.d_counts16 = nullptr; t.d_weights = nullptr; t.d_boxes = nullptr;
+}
+
+vqnnf_status finish_template(vqnnf_ctx* ctx, vqnnf_template* tp, const vqnnf_fmap* tmpl) {
+  DeviceTemplate& t = tp->t;
+  const float* td = (const float*)tmpl->data;
+  int64_t st = tmpl->pixel_stride ? tmpl->pixel_stride : tmpl->D;
+  prepare_template_host(t, td, st);
+  HostTables ht;
+  build_tables(t, ht);
+  if (!ctx->has_device) return ok();
+  vqnnf_status s;
+  if ((s = upload(ctx, &t.d_codebook, t.codebook))) return s;
+  std::vector<uint4> fb(ht.frag_bf16.size() / 8);
+  std::memcpy(fb.data(), ht.frag_bf16.data(), ht.frag_bf16.size() * 2);
+  if ((s = upload(ctx, &t.d_frag_bf16, fb))) return s;
+  if ((s = upload(ctx, &t.d_frag_f32, ht.frag_f32))) return s;
+  if ((s = upload(ctx, &t.d_cnorm, ht.cnorm))) return s;
+  if ((s = upload(ctx, &t.d_counts, ht.counts))) return s;
+  if ((s = upload(ctx, &t.d_counts16, ht.counts16))) return s;
+  if ((s = upload(ctx, &t.d_weights, t.weights))) return s;
+  if ((s = upload(ctx, &t.d_boxes, t.boxes))) return s;
+  return ok();
+}
+
+vqnnf_status check_template_map(const vqnnf_fmap* tmpl) {
+  vqnnf_status s = check_map(tmpl, "template");
+  if (s) return s;
+  if (tmpl->dtype != VQNNF_F32) return fail(VQNNF_EINVAL, "template: dtype must be VQNNF_F32");
+  if (tmpl->H > 255 || tmpl->W > 255)
+    return fail(VQNNF_EINVAL, "template: sides must be <= 255 (window histograms are 16-bit)");
+  for (int64_t p = 0; p < (int64_t)tmpl->H * tmpl->W; ++p) {
+    const float* v = (const float*)tmpl->data + p * (tmpl->pixel_stride ? tmpl->pixel_stride : tmpl->D);
+    for (int d = 0; d < tmpl->D; ++d)
+      if (!std::isfinite(v[d])) return fail(VQNNF_EINVAL, "template: non-finite value at pixel %lld", (long long)p);
+  }
+  return ok();
+}
+
+vqnnf_status check_query(const vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap* q,
+                         int prec) {
+  vqnnf_status s = check_map(q, "query");
+  if (s) return s;
+  if (q->D != t->t.D) return fail(VQNNF_EINVAL, "query D=%d differs from template D=%d", q->D, t->t.D);
+  if (prec != VQNNF_PREC_FP32_PLAIN && prec != VQNNF_PREC_BF16_REFINED)
+    return fail(VQNNF_EINVAL, "unknown precision %d", prec);
+  if (q->dtype == VQNNF_FP8_E4M3)
+    return fail(VQNNF_ENOTSUP, "FP8 query maps are not supported by this version");
+  (void)c;
+  return ok();
+}
+
+vqnnf_status need_device(const vqnnf_ctx* c) {
+  if (!c->has_device)
+    return fail(VQNNF_ENOTSUP, "context has no device (created with vqnnf_ctx_create_host)");
+  return ok();
+}
+
+float unpack_score(unsigned long long key) {
+  uint32_t o = (uint32_t)(key >> 32);
+  uint32_t bits = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+  float f;
+  std::memcpy(&f, &bits, 4);
+  return f;
+}
+
+vqnnf_status read_best(vqnnf_ctx* c, int ow, int32_t* best_xy, float* best_score) {
+  if (!best_xy && !best_score) return ok();
+  unsigned long long key = 0;
+  HIP_TRY(hipMemcpyAsync(&key, c->control.p, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  uint32_t idx = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFu);
+  if (best_xy) {
+    best_xy[0] = (int32_t)(idx % (uint32_t)ow);
+    best_xy[1] = (int32_t)(idx / (uint32_t)ow);
+  }
+  if (best_score) *best_score = unpack_score(key);
+  return ok();
+}
+
+size_t mask_words(const DeviceTemplate& t) { return (size_t)(t.geom.kpad + 31) / 32; }
+
+vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap* q, int prec,
+                        uint8_t* labels, bool counter_zeroed) {
+  const DeviceTemplate& t = tp->t;
+  AssignArgs a{};
+  a.q = q->data;
+  a.stride = q->pixel_stride ? q->pixel_stride : q->D;
+  a.n_pix = (int64_t)q->H * q->W;
+  a.D = q->D;
+  a.dtype = q->dtype;
+  a.t = &t;
+  a.labels = labels;
+  if (prec == VQNNF_PREC_FP32_PLAIN) {
+    HIP_TRY(launch_assign_plain(a, c->stream, c->n_cu));
+    return ok();
+  }
+  a.wl_count = (uint32_t*)((char*)c->control.p + 8);
+  a.wl_pix = (uint32_t*)c->wl_pix.p;
+  a.wl_mask = (uint32_t*)c->wl_mask.p;
+  a.bound = (q->dtype == VQNNF_F32) ? t.bound_f32q : t.bound_bf16q;
+  if (!counter_zeroed) HIP_TRY(launch_fill_u32(a.wl_count, 0u, 1, c->stream));
+  HIP_TRY(launch_assign_refined(a, c->stream, c->n_cu));
+  HIP_TRY(launch_rescore(a, c->stream, c->n_cu));
+  return ok();
+}
+
+vqnnf_status assign_scratch(vqnnf_ctx* c, const vqnnf_template* tp, int64_t n_pix, int prec,
+                            bool own_labels) {
+  size_t lab = own_labels ? (size_t)n_pix : 0;
+  size_t wp = prec == VQNNF_PREC_BF16_REFINED ? (size_t)n_pix * 4 : 0;
+  size_t wm = prec == VQNNF_PREC_BF16_REFINED ? (size_t)n_pix * 4 * mask_words(tp->t) : 0;
+  vqnnf_status s = check_cap(c, {{&c->control, 64}, {&c->labels, lab}, {&c->wl_pix, wp},
+                                 {&c->wl_mask, wm}});
+  if (s) return s;
+  if ((s = need_device(c))) return s;
+  if ((s = ensure(c, c->control, 64, "control block"))) return s;
+  if (own_labels && (s = ensure(c, c->labels, lab, "label map"))) return s;
+  if (wp && (s = ensure(c, c->wl_pix, wp, "re-score worklist"))) return s;
+  if (wm && (s = ensure(c, c->wl_mask, wm, "re-score candidate masks"))) return s;
+  return ok();
+}
+
+vqnnf_status check_score_dims(const vqnnf_template* tp, int H, int W) {
+  const DeviceTemplate& t = tp->t;
+  if (H < 1 || W < 1) return fail(VQNNF_EINVAL, "H and W must be >= 1");
+  if ((int64_t)H * W >= (1ll << 31)) return fail(VQNNF_EINVAL, "H*W must be < 2^31");
+  if (t.w > W || t.h > H)
+    return fail(VQNNF_EINVAL, "template %dx%d larger than the %dx%d map", t.w, t.h, W, H);
+  return ok();
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* vqnnf_last_error(void) { return g_err.c_str(); }
+const char* vqnnf_version(void) { return "vqnnf-gfx950 0.1"; }
+
+vqnnf_status vqnnf_ctx_create(void* hip_stream, uint64_t scratch_cap_bytes, vqnnf_ctx** out) {
+  if (!out) return fail(VQNNF_EINVAL, "null output pointer");
+  *out = nullptr;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(VQNNF_ENOTSUP, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+  auto* c = new vqnnf_ctx();
+  c->has_device = true;
+  c->device = dev;
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->stream = (hipStream_t)hip_stream;
+  c->cap = scratch_cap_bytes ? scratch_cap_bytes : (16ull << 30);
+  *out = c;
+  return ok();
+}
+
+vqnnf_status vqnnf_ctx_create_host(uint64_t scratch_cap_bytes, vqnnf_ctx** out) {
+  if (!out) return fail(VQNNF_EINVAL, "null output pointer");
+  auto* c = new vqnnf_ctx();
+  c->has_device = false;
+  c->cap = scratch_cap_bytes ? scratch_cap_bytes : (16ull << 30);
+  *out = c;
+  return ok();
+}
+
+void vqnnf_ctx_destroy(vqnnf_ctx* c) {
+  if (!c || c->magic != kCtxMagic) return;
+  if (c->has_device) {
+    hipStreamSynchronize(c->stream);
+    Buffer* bs[] = {&c->control, &c->labels, &c->wl_pix, &c->wl_mask, &c->int_side, &c->int_p};
+    for (Buffer* b : bs)
+      if (b->p) hipFree(b->p);
+    for (auto& r : c->pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+    for (auto e : c->pool) hipEventDestroy(e);
+  }
+  c->magic = 0;
+  delete c;
+}
+
+static vqnnf_status make_template(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, const float* codebook,
+                                  int32_t k, int32_t iters, uint64_t seed,
+                                  const vqnnf_filter_desc* bank, int32_t n_desc,
+                                  vqnnf_template** out) {
+  vqnnf_status s;
+  if (!out) return fail(VQNNF_EINVAL, "null output pointer");
+  *out = nullptr;
+  if ((s = check_ctx(ctx))) return s;
+  if ((s = check_template_map(tmpl))) return s;
+  if (k < 1 || k > kMaxK) return fail(VQNNF_EINVAL, "k=%d outside [1, %d]", k, kMaxK);
+  if (iters < 0) return fail(VQNNF_EINVAL, "lloyd_iters must be >= 0");
+  auto* tp = new vqnnf_template();
+  tp->ctx = ctx;
+  DeviceTemplate& t = tp->t;
+  t.w = tmpl->W;
+  t.h = tmpl->H;
+  t.D = tmpl->D;
+  t.k = k;
+  if ((s = expand_bank(bank, n_desc, t.w, t.h, t))) { delete tp; return s; }
+  int64_t n = (int64_t)t.w * t.h;
+  int64_t st = tmpl->pixel_stride ? tmpl->pixel_stride : tmpl->D;
+  const float* td = (const float*)tmpl->data;
+  if (codebook) {
+    for (int64_t i = 0; i < (int64_t)k * t.D; ++i)
+      if (!std::isfinite(codebook[i])) { delete tp; return fail(VQNNF_EINVAL, "codebook: non-finite value"); }
+    t.codebook.assign(codebook, codebook + (size_t)k * t.D);
+  } else {
+    std::vector<double> x((size_t)n * t.D);
+    for (int64_t p = 0; p < n; ++p)
+      for (int d = 0; d < t.D; ++d) x[(size_t)p * t.D + d] = (double)td[p * st + d];
+    std::vector<double> c = kmeans_host(x, n, t.D, k, iters, seed);
+    t.codebook.resize(c.size());
+    for (size_t i = 0; i < c.size(); ++i) t.codebook[i] = (float)c[i];
+  }
+  if ((s = finish_template(ctx, tp, tmpl))) { free_device(t); delete tp; return s; }
+  *out = tp;
+  return ok();
+}
+
+vqnnf_status vqnnf_codebook(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, int32_t k, int32_t lloyd_iters,
+                            uint64_t seed, const vqnnf_filter_desc* bank, int32_t n_desc,
+                            vqnnf_template** out) {
+  return make_template(ctx, tmpl, nullptr, k, lloyd_iters, seed, bank, n_desc, out);
+}
+
+vqnnf_status vqnnf_template_from_codebook(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl,
+                                          const float* codebook, int32_t k,
+                                          const vqnnf_filter_desc* bank, int32_t n_desc,
+                                          vqnnf_template** out) {
+  if (!codebook) return fail(VQNNF_EINVAL, "null codebook");
+  return make_template(ctx, tmpl, codebook, k, 0, 0, bank, n_desc, out);
+}
+
+void vqnnf_template_free(vqnnf_template* t) {
+  if (!t || t->magic != kTplMagic) return;
+  if (t->ctx && t->ctx->has_device) {
+    hipStreamSynchronize(t->ctx->stream);
+    free_device(t->t);
+  }
+  t->magic = 0;
+  delete t;
+}
+
+vqnnf_status vqnnf_template_info(const vqnnf_template* t, int32_t* w, int32_t* h, int32_t* D,
+                                 int32_t* k, int32_t* n_filters) {
+  vqnnf_status s = check_tpl(nullptr, t);
+  if (s) return s;
+  if (w) *w = t->t.w;
+  if (h) *h = t->t.h;
+  if (D) *D = t->t.D;
+  if (k) *k = t->t.k;
+  if (n_filters) *n_filters = t->t.n_filters;
+  return ok();
+}
+
+vqnnf_status vqnnf_template_codebook(const vqnnf_template* t, float* out) {
+  vqnnf_status s = check_tpl(nullptr, t);
+  if (s) return s;
+  if (!out) return fail(VQNNF_EINVAL, "null output");
+  std::memcpy(out, t->t.codebook.data(), t->t.codebook.size() * sizeof(float));
+  return ok();
+}
+
+vqnnf_status vqnnf_template_labels(const vqnnf_template* t, uint8_t* out) {
+  vqnnf_status s = check_tpl(nullptr, t);
+  if (s) return s;
+  if (!out) return fail(VQNNF_EINVAL, "null output");
+  std::memcpy(out, t->t.labels.data(), t->t.labels.size());
+  return ok();
+}
+
+vqnnf_status vqnnf_template_counts(const vqnnf_template* t, int32_t* out) {
+  vqnnf_status s = check_tpl(nullptr, t);
+  if (s) return s;
+  if (!out) return fail(VQNNF_EINVAL, "null output");
+  std::memcpy(out, t->t.counts.data(), t->t.counts.size() * sizeof(int32_t));
+  return ok();
+}
+
+vqnnf_status vqnnf_template_weights(const vqnnf_template* t, float* out) {
+  vqnnf_status s = check_tpl(nullptr, t);
+  if (s) return s;
+  if (!out) return fail(VQNNF_EINVAL, "null output");
+  std::memcpy(out, t->t.weights.data(), t->t.weights.size() * sizeof(float));
+  return ok();
+}
+
+vqnnf_status vqnnf_assign(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap* q, int32_t prec,
+                          uint8_t* labels, int64_t* n_flagged) {
+  vqnnf_status s;
+  if ((s = check_ctx(c)) || (s = check_tpl(c, t)) || (s = check_query(c, t, q, prec))) return s;
+  if (!labels) return fail(VQNNF_EINVAL, "null labels");
+  int64_t n = (int64_t)q->H * q->W;
+  if ((s = assign_scratch(c, t, n, prec, false))) return s;
+  HookScope hs(c);
+  if ((s = run_assign(c, t, q, prec, labels, false))) return s;
+  if (n_flagged) {
+    uint32_t cnt = 0;
+    if (prec == VQNNF_PREC_BF16_REFINED) {
+      HIP_TRY(hipMemcpyAsync(&cnt, (char*)c->control.p + 8, 4, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    *n_flagged = cnt;
+  }
+  return ok();
+}
+
+vqnnf_status vqnnf_filter(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* labels, int32_t H,
+                          int32_t W, int32_t* integral) {
+  vqnnf_status s;
+  if ((s = check_ctx(c)) || (s = check_tpl(c, t))) return s;
+  if (!labels || !integral) return fail(VQNNF_EINVAL, "null labels or integral pointer");
+  if (H < 1 || W < 1) return fail(VQNNF_EINVAL, "H and W must be >= 1");
+  if ((int64_t)H * W >= (1ll << 31)) return fail(VQNNF_EINVAL, "H*W must be < 2^31");
+  const int k = t->t.k;
+  const int64_t R = (H + kIntTile - 1) / kIntTile, S = (W + kIntTile - 1) / kIntTile;
+  size_t side = (size_t)((int64_t)H * S + R * W + R * S) * k * 4;
+  if ((s = check_cap(c, {{&c->int_side, side}}))) return s;
+  if ((s = need_device(c))) return s;
+  if ((s = ensure(c, c->int_side, side, "integral-image side arrays"))) return s;
+  IntegralArgs a{};
+  a.labels = labels;
+  a.H = H;
+  a.W = W;
+  a.k = k;
+  a.P = integral;
+  a.rsh = (int32_t*)c->int_side.p;
+  a.cbh = a.rsh + (size_t)H * S * k;
+  a.th = a.cbh + (size_t)R * W * k;
+  HookScope hs(c);
+  HIP_TRY(launch_integral(a, c->stream));
+  return ok();
+}
+
+static vqnnf_status score_common(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* labels,
+                                 const int32_t* P, int32_t H, int32_t W, float* heatmap,
+                                 int32_t* best_xy, float* best_score, bool zeroed) {
+  ScoreArgs a{};
+  a.t = &t->t;
+  a.labels = labels;
+  a.P = P;
+  a.H = H;
+  a.W = W;
+  a.heatmap = heatmap;
+  a.best = (unsigned long long*)c->control.p;
+  if (!zeroed) HIP_TRY(launch_zero_u64(a.best, c->stream));
+  if (labels) {
+    size_t lds = 0;
+    HIP_TRY(launch_score_fused(a, c->stream, &lds));
+  } else {
+    HIP_TRY(launch_score_integral(a, c->stream));
+  }
+  return read_best(c, W - t->t.w + 1, best_xy, best_score);
+}
+
+vqnnf_status vqnnf_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* labels, int32_t H,
+                         int32_t W, float* heatmap, int32_t* best_xy, float* best_score) {
+  vqnnf_status s;
+  if ((s = check_ctx(c)) || (s = check_tpl(c, t))) return s;
+  if (!labels || !heatmap) return fail(VQNNF_EINVAL, "null labels or heatmap");
+  if ((s = check_score_dims(t, H, W))) return s;
+  if (!fused_supported(t->t))
+    return fail(VQNNF_ENOTSUP, "on-chip scoring needs the full-window + g x g grid bank (g <= 4) "
+                "within the LDS budget; use vqnnf_filter + vqnnf_score_integral");
+  if ((s = check_cap(c, {{&c->control, 64}}))) return s;
+  if ((s = need_device(c))) return s;
+  if ((s = ensure(c, c->control, 64, "control block"))) return s;
+  HookScope hs(c);
+  return score_common(c, t, labels, nullptr, H, W, heatmap, best_xy, best_score, false);
+}
+
+vqnnf_status vqnnf_score_integral(vqnnf_ctx* c, const vqnnf_template* t, const int32_t* integral,
+                                  int32_t H, int32_t W, float* heatmap, int32_t* best_xy,
+                                  float* best_score) {
+  vqnnf_status s;
+  if ((s = check_ctx(c)) || (s = check_tpl(c, t))) return s;
+  if (!integral || !heatmap) return fail(VQNNF_EINVAL, "null integral or heatmap");
+  if ((s = check_score_dims(t, H, W))) return s;
+  if ((s = check_cap(c, {{&c->control, 64}}))) return s;
+  if ((s = need_device(c))) return s;
+  if ((s = ensure(c, c->control, 64, "control block"))) return s;
+  HookScope hs(c);
+  return score_common(c, t, nullptr, integral, H, W, heatmap, best_xy, best_score, false);
+}
+
+vqnnf_status vqnnf_match(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap* q, int32_t prec,
+                         float* heatmap, int32_t* best_xy, float* best_score) {
+  vqnnf_status s;
+  if ((s = check_ctx(c)) || (s = check_tpl(c, t)) || (s = check_query(c, t, q, prec))) return s;
+  if (!heatmap) return fail(VQNNF_EINVAL, "null heatmap");
+  if ((s = check_score_dims(t, q->H, q->W))) return s;
+  const int64_t n = (int64_t)q->H * q->W;
+  const bool fused = fused_supported(t->t);
+  const int k = t->t.k;
+  const int64_t R = (q->H + kIntTile - 1) / kIntTile, S = (q->W + kIntTile - 1) / kIntTile;
+  size_t side = fused ? 0 : (size_t)((int64_t)q->H * S + R * q->W + R * S) * k * 4;
+  size_t pbytes = fused ? 0 : (size_t)(q->H + 1) * (q->W + 1) * k * 4;
+  if ((s = check_cap(c, {{&c->control, 64}, {&c->labels, (size_t)n},
+                         {&c->wl_pix, prec ? (size_t)n * 4 : 0},
+                         {&c->wl_mask, prec ? (size_t)n * 4 * mask_words(t->t) : 0},
+                         {&c->int_side, side}, {&c->int_p, pbytes}})))
+    return s;
+  if ((s = assign_scratch(c, t, n, prec, true))) return s;
+  if (!fused) {
+    if ((s = ensure(c, c->int_side, side, "integral-image side arrays"))) return s;
+    if ((s = ensure(c, c->int_p, pbytes, "integral image"))) return s;
+  }
+  HookScope hs(c);
+  // one fill clears the best-location key and the worklist counter
+  HIP_TRY(launch_fill_u32((uint32_t*)c->control.p, 0u, 4, c->stream));
+  uint8_t* lab = (uint8_t*)c->labels.p;
+  if ((s = run_assign(c, t, q, prec, lab, true))) return s;
+  if (fused) return score_common(c, t, lab, nullptr, q->H, q->W, heatmap, best_xy, best_score, true);
+  IntegralArgs a{};
+  a.labels = lab;
+  a.H = q->H;
+  a.W = q->W;
+  a.k = k;
+  a.P = (int32_t*)c->int_p.p;
+  a.rsh = (int32_t*)c->int_side.p;
+  a.cbh = a.rsh + (size_t)q->H * S * k;
+  a.th = a.cbh + (size_t)R * q->W * k;
+  HIP_TRY(launch_integral(a, c->stream));
+  return score_common(c, t, nullptr, a.P, q->H, q->W, heatmap, best_xy, best_score, true);
+}
+
+vqnnf_status vqnnf_ctx_set_timing(vqnnf_ctx* c, int32_t enable) {
+  vqnnf_status s = check_ctx(c);
+  if (s) return s;
+  if ((s = need_device(c))) return s;
+  if (!enable && c->timing) collect_times(c);
+  c->timing = enable != 0;
+  return ok();
+}
+
+vqnnf_status vqnnf_ctx_kernel_times(vqnnf_ctx* c, int32_t max_entries, const char** names,
+                                    int64_t* launches, double* total_ms, int32_t* n_entries) {
+  vqnnf_status s = check_ctx(c);
+  if (s) return s;
+  if ((s = need_device(c))) return s;
+  if ((s = collect_times(c))) return s;
+  int n = 0;
+  for (int i = 0; i < K_COUNT; ++i) {
+    if (c->launches[i] == 0) continue;
+    if (n < max_entries) {
+      if (names) names[n] = kernel_name(i);
+      if (launches) launches[n] = c->launches[i];
+      if (total_ms) total_ms[n] = c->total_ms[i];
+    }
+    ++n;
+  }
+  if (n_entries) *n_entries = n;
+  return ok();
+}
+
+vqnnf_status vqnnf_ctx_reset_times(vqnnf_ctx* c) {
+  vqnnf_status s = check_ctx(c);
+  if (s) return s;
+  if ((s = need_device(c))) return s;
+  if ((s = collect_times(c))) return s;
+  for (int i = 0; i < K_COUNT; ++i) {
+    c->launches[i] = 0;
+    c->total_ms[i] = 0;
+  }
+  return ok();
+}
+
+}  // extern "C"

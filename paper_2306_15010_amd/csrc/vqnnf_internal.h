@@ -1,0 +1,158 @@
+// Internal declarations shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/vqnnf.h"
+
+namespace vqnnf {
+
+// Largest codebook the kernels handle (labels are uint8).
+constexpr int kMaxK = 256;
+
+// Assignment tiling: the codebook is padded to KPAD = 16 * KB codewords; the
+// feature dimension is padded to a whole number of "load groups".  For the
+// BF16 matrix-core path a load group is 32*S elements: lane group g of a
+// 64-lane wave reads elements [8*S*g, 8*S*g + 8*S) of its pixel and feeds
+// elements [8*S*g + 8*s, +8) to K-step s of the group; the codebook
+// fragments are laid out on the host with the same element order.
+struct AssignGeom {
+  int kpad;        // codewords padded to a multiple of 16
+  int kb;          // kpad / 16
+  int s_bf16;      // K-steps (of 32 elements) per load group, 1, 2 or 4
+  int d_pad_bf16;  // D padded to a multiple of 32 * s_bf16
+  int e_f32;       // elements per lane per load group for the FP32 path (4 or 8)
+  int d_pad_f32;   // D padded to a multiple of 4 * e_f32
+};
+
+AssignGeom make_assign_geom(int k, int D);
+
+// Per-pixel error bound of the refined path: flag a pixel when
+// s(2) - s(1) <= a0 + ||q|| * (a1 + ||q|| * a2), ||q|| an upper bound of the
+// query pixel's norm; codeword j is a candidate when s_j - s(1) is within the
+// same threshold.  Constants are rounded up.
+struct BoundCoef {
+  float a0, a1, a2;
+};
+
+// Filter geometry for the on-chip score kernel: the bank must be the full
+// window plus one g x g grid over the full window (the benchmark bank).
+struct GridBank {
+  bool valid;
+  int g;
+  int xe[9];   // column edges X_0..X_g (X_0 = 0, X_g = w)
+  int ye[9];   // row edges
+};
+
+struct DeviceTemplate {
+  int w = 0, h = 0, D = 0, k = 0, n_filters = 0;
+  AssignGeom geom{};
+  // host copies
+  std::vector<float> codebook;       // [k][D]
+  std::vector<uint8_t> labels;       // [h][w]
+  std::vector<int32_t> counts;       // [n_filters][k]
+  std::vector<float> weights;        // [n_filters]
+  // expanded filter boxes (template coordinates), one per filter
+  std::vector<int32_t> boxes;        // [n_filters][4] x0,y0,x1,y1
+  GridBank grid{};
+  BoundCoef bound_bf16q{};           // BF16-stored query, codebook hi+lo
+  BoundCoef bound_f32q{};            // FP32-stored query, both split hi+lo
+  // device copies
+  float* d_codebook = nullptr;       // [k][D] FP32
+  uint4* d_frag_bf16 = nullptr;      // A fragments, BF16 hi/lo, scaled by -2
+  float* d_frag_f32 = nullptr;       // A fragments, FP32, scaled by -2
+  float* d_cnorm = nullptr;          // [kpad] ||c||^2 (pad: 3e38)
+  int32_t* d_counts = nullptr;       // [n_filters][kpad] (pad channels 0)
+  uint32_t* d_counts16 = nullptr;    // [n_filters][kpad/2] u16 pairs
+  float* d_weights = nullptr;        // [n_filters]
+  int32_t* d_boxes = nullptr;        // [n_filters][4]
+  int magic = 0;
+};
+
+// ---------------------------------------------------------------- host prep
+std::vector<double> kmeans_host(const std::vector<double>& x, int64_t n, int D, int k, int iters,
+                                uint64_t seed);
+std::vector<int> assign_host(const std::vector<double>& x, int64_t n, int D,
+                             const std::vector<double>& c, int k);
+void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_stride);
+
+// Device-ready tables of a template, built on the host.
+struct HostTables {
+  std::vector<uint16_t> frag_bf16;   // [steps][2][kb][64][8]
+  std::vector<float> frag_f32;       // [steps][kb][64]
+  std::vector<float> cnorm;          // [kpad]
+  std::vector<int32_t> counts;       // [nf][kpad]
+  std::vector<uint32_t> counts16;    // [nf][kpad/2]
+};
+void build_tables(DeviceTemplate& t, HostTables& ht);
+
+// ---------------------------------------------------------------- launches
+// All launchers enqueue on `stream` and return hipSuccess or the first error.
+
+struct AssignArgs {
+  const void* q;
+  int64_t stride;        // elements between pixels
+  int64_t n_pix;         // H * W
+  int D;
+  int dtype;             // vqnnf_dtype
+  const DeviceTemplate* t;
+  uint8_t* labels;
+  // refined path only
+  uint32_t* wl_count;    // worklist counter (must be 0 on entry)
+  uint32_t* wl_pix;      // [n_pix]
+  uint32_t* wl_mask;     // [n_pix][mask_words]
+  BoundCoef bound;
+};
+
+hipError_t launch_assign_plain(const AssignArgs& a, hipStream_t s, int n_cu);
+hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu);
+hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+
+struct IntegralArgs {
+  const uint8_t* labels;
+  int H, W, k;
+  int32_t* P;            // [(H+1)(W+1)k]
+  int32_t* rsh;          // [H][S][k]
+  int32_t* cbh;          // [R][W][k]
+  int32_t* th;           // [R][S][k]
+};
+constexpr int kIntTile = 64;
+hipError_t launch_integral(const IntegralArgs& a, hipStream_t s);
+
+struct ScoreArgs {
+  const DeviceTemplate* t;
+  const uint8_t* labels;       // on-chip path
+  const int32_t* P;            // integral path
+  int H, W;
+  float* heatmap;
+  unsigned long long* best;    // packed (orderable score, ~index), must be 0
+};
+hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out);
+hipError_t launch_score_integral(const ScoreArgs& a, hipStream_t s);
+// True when the on-chip score kernel can take this template's bank.
+bool fused_supported(const DeviceTemplate& t);
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
+
+// Kernel-name registry for timing.
+enum KernelId {
+  K_FILL = 0, K_ASSIGN_PLAIN, K_ASSIGN_REFINED, K_RESCORE, K_INT_EDGE, K_INT_PREFIX,
+  K_INT_MAIN, K_SCORE_FUSED, K_SCORE_INTEGRAL, K_COUNT
+};
+const char* kernel_name(int id);
+
+// Timing hook: the launchers call these around each kernel when timing is on.
+struct TimingHook {
+  void (*begin)(void* user, int kernel_id);
+  void (*end)(void* user, int kernel_id);
+  void* user;
+};
+void set_timing_hook(const TimingHook* h);   // thread-local
+void timing_begin(int id);
+void timing_end(int id);
+
+}  // namespace vqnnf

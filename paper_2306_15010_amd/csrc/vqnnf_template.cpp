@@ -1,0 +1,364 @@
+// Host-side template preparation: k-means codebook, template NNF, template
+// representation R(tau), and the device-ready tables (matrix-core fragments,
+// codeword norms, error-bound constants).
+//
+// Floating-point contract: every FP64 distance is sum_t (q_t - c_t)^2 taken
+// sequentially in t from 0, with separate subtract, multiply and add.  This
+// file is compiled with -ffp-contract=off so no FMA is formed.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "vqnnf_internal.h"
+
+namespace vqnnf {
+
+namespace {
+
+template <typename F>
+void parallel_for(int64_t n, F&& f) {
+  unsigned hw = std::thread::hardware_concurrency();
+  int nt = (int)std::max(1u, std::min(hw ? hw : 1u, 32u));
+  if (n < 4096 || nt == 1) {
+    f((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t per = (n + nt - 1) / nt;
+  for (int i = 0; i < nt; ++i) {
+    int64_t b = i * per, e = std::min(n, b + per);
+    if (b >= e) break;
+    th.emplace_back([&, b, e] { f(b, e); });
+  }
+  for (auto& t : th) t.join();
+}
+
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double u01() { return (double)(next() >> 11) * 0x1.0p-53; }
+};
+
+int uniform_index(double u, int64_t n) {
+  int64_t i = (int64_t)std::floor(u * (double)n);
+  return (int)std::min<int64_t>(i, n - 1);
+}
+
+// Sequential FP64 squared distance.
+inline double sqdist(const double* x, const double* c, int D) {
+  double acc = 0.0;
+  for (int t = 0; t < D; ++t) {
+    double d = x[t] - c[t];
+    double sq = d * d;
+    acc = acc + sq;
+  }
+  return acc;
+}
+
+// dist[p][j] for all points and centres; centres given as [k][D].
+void all_distances(const std::vector<double>& x, int64_t n, const std::vector<double>& c, int k,
+                   int D, std::vector<double>& out) {
+  out.resize((size_t)n * k);
+  // transpose centres to [D][k] so the inner loop runs over centres: every
+  // centre keeps its own sequential sum over t
+  std::vector<double> ct((size_t)D * k);
+  for (int j = 0; j < k; ++j)
+    for (int t = 0; t < D; ++t) ct[(size_t)t * k + j] = c[(size_t)j * D + t];
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    std::vector<double> acc(k);
+    for (int64_t p = b; p < e; ++p) {
+      const double* xp = &x[(size_t)p * D];
+      std::fill(acc.begin(), acc.end(), 0.0);
+      for (int t = 0; t < D; ++t) {
+        const double xv = xp[t];
+        const double* cr = &ct[(size_t)t * k];
+        for (int j = 0; j < k; ++j) {
+          double d = xv - cr[j];
+          double sq = d * d;
+          acc[j] = acc[j] + sq;
+        }
+      }
+      std::memcpy(&out[(size_t)p * k], acc.data(), sizeof(double) * k);
+    }
+  });
+}
+
+void argmin_rows(const std::vector<double>& d, int64_t n, int k, std::vector<int>& lab) {
+  lab.resize(n);
+  for (int64_t p = 0; p < n; ++p) {
+    const double* r = &d[(size_t)p * k];
+    int best = 0;
+    for (int j = 1; j < k; ++j)
+      if (r[j] < r[best]) best = j;
+    lab[p] = best;
+  }
+}
+
+}  // namespace
+
+// k-means++ seeding then `iters` Lloyd iterations (Sec. 3.1), FP64.
+std::vector<double> kmeans_host(const std::vector<double>& x, int64_t n, int D, int k, int iters,
+                                uint64_t seed) {
+  SplitMix64 rng{seed};
+  std::vector<double> c((size_t)k * D);
+  int first = uniform_index(rng.u01(), n);
+  std::copy(&x[(size_t)first * D], &x[(size_t)first * D] + D, &c[0]);
+  std::vector<double> d2(n), csum(n);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t p = b; p < e; ++p) d2[p] = sqdist(&x[(size_t)p * D], &c[0], D);
+  });
+  for (int i = 1; i < k; ++i) {
+    double run = 0.0;
+    for (int64_t p = 0; p < n; ++p) {
+      run = run + d2[p];
+      csum[p] = run;
+    }
+    double total = csum[n - 1];
+    double u = rng.u01();
+    int64_t idx;
+    if (total == 0.0) {
+      idx = uniform_index(u, n);
+    } else {
+      double target = u * total;
+      idx = -1;
+      for (int64_t p = 0; p < n; ++p)
+        if (csum[p] > target) { idx = p; break; }
+      if (idx < 0)
+        for (int64_t p = n - 1; p >= 0; --p)
+          if (d2[p] > 0.0) { idx = p; break; }
+    }
+    double* ci = &c[(size_t)i * D];
+    std::copy(&x[(size_t)idx * D], &x[(size_t)idx * D] + D, ci);
+    parallel_for(n, [&](int64_t b, int64_t e) {
+      for (int64_t p = b; p < e; ++p) {
+        double dn = sqdist(&x[(size_t)p * D], ci, D);
+        if (dn < d2[p]) d2[p] = dn;
+      }
+    });
+  }
+  std::vector<double> dist;
+  std::vector<int> lab;
+  std::vector<double> sum(D);
+  for (int it = 0; it < iters; ++it) {
+    all_distances(x, n, c, k, D, dist);
+    argmin_rows(dist, n, k, lab);
+    // per-cluster sequential sums in point order
+    std::vector<double> sums((size_t)k * D, 0.0);
+    std::vector<int64_t> cnt(k, 0);
+    for (int64_t p = 0; p < n; ++p) {
+      int j = lab[p];
+      double* s = &sums[(size_t)j * D];
+      const double* xp = &x[(size_t)p * D];
+      for (int t = 0; t < D; ++t) s[t] = s[t] + xp[t];
+      cnt[j] += 1;
+    }
+    for (int j = 0; j < k; ++j) {
+      if (cnt[j] == 0) continue;
+      double nj = (double)cnt[j];
+      for (int t = 0; t < D; ++t) c[(size_t)j * D + t] = sums[(size_t)j * D + t] / nj;
+    }
+  }
+  return c;
+}
+
+// FP64 nearest codeword (lowest index on ties) of every point.
+std::vector<int> assign_host(const std::vector<double>& x, int64_t n, int D,
+                             const std::vector<double>& c, int k) {
+  std::vector<double> dist;
+  std::vector<int> lab;
+  all_distances(x, n, c, k, D, dist);
+  argmin_rows(dist, n, k, lab);
+  return lab;
+}
+
+AssignGeom make_assign_geom(int k, int D) {
+  AssignGeom g{};
+  // codeword blocks of 16, rounded to the kernel instances (1, 2, 3, 4, 8, 16)
+  g.kb = (k + 15) / 16;
+  if (g.kb > 4 && g.kb <= 8) g.kb = 8;
+  if (g.kb > 8) g.kb = 16;
+  g.kpad = 16 * g.kb;
+  int d32 = ((D + 31) / 32) * 32;
+  g.s_bf16 = (d32 % 128 == 0) ? 4 : (d32 % 64 == 0) ? 2 : 1;
+  g.d_pad_bf16 = d32;
+  int d16 = ((D + 15) / 16) * 16;
+  g.e_f32 = (d16 % 32 == 0) ? 8 : 4;
+  g.d_pad_f32 = d16;
+  return g;
+}
+
+namespace {
+
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  uint32_t lsb = (u >> 16) & 1u;
+  return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+float bf16_to_f32(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+float round_up_f32(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = std::nextafter(f, INFINITY);
+  return f;
+}
+
+// Error-bound constants of the refined path (see BoundCoef).
+BoundCoef make_bound(const DeviceTemplate& t, const std::vector<float>& hi,
+                     const std::vector<float>& lo, const std::vector<float>& cn32, bool f32_query) {
+  const int D = t.D, k = t.k;
+  const double u = 0x1.0p-23;  // per-addend relative error allowed to the accumulator
+  const double n_add = (double)(f32_query ? 3 : 2) * t.geom.d_pad_bf16 + 1.0;
+  const double gam = n_add * u / (1.0 - n_add * u);
+  const double u64 = 0x1.0p-53;
+  const double gam64 = (D + 2) * u64 / (1.0 - (D + 2) * u64);
+  const double qfac = f32_query ? 1.0 + 0x1.0p-7 : 1.0;
+  const double lofac = f32_query ? 0x1.0p-8 * (1.0 + 0x1.0p-7) : 0.0;
+  const double rhofac = f32_query ? 0x1.0p-16 * (1.0 + 0x1.0p-6) : 0.0;
+  const double pfac = f32_query ? (1.0 + 0x1.0p-7) * (1.0 + 0x1.0p-7) : 1.0;
+  double A0 = 0.0, A1 = 0.0, cmax = 0.0;
+  for (int j = 0; j < k; ++j) {
+    double cn2 = 0.0, r2 = 0.0, a2 = 0.0, lo2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+      double c = t.codebook[(size_t)j * D + d];
+      double h = hi[(size_t)j * D + d], l = lo[(size_t)j * D + d];
+      double r = c - h - l;
+      cn2 = cn2 + c * c;
+      r2 = r2 + r * r;
+      double a = std::fabs(h) + std::fabs(l);
+      a2 = a2 + a * a;
+      lo2 = lo2 + l * l;
+    }
+    const double slack = 1.0 + 0x1.0p-40;
+    double cn = std::sqrt(cn2) * slack, rn = std::sqrt(r2) * slack;
+    double an = std::sqrt(a2) * slack, lon = std::sqrt(lo2) * slack;
+    double e_norm = std::fabs((double)cn32[j] - cn2) + (D + 2) * 0x1.0p-52 * cn2;
+    double a0j = e_norm + gam * std::fabs((double)cn32[j]);
+    double a1j = 2.0 * (qfac * rn + lofac * lon + rhofac * cn) + 2.0 * gam * pfac * an;
+    A0 = std::max(A0, a0j);
+    A1 = std::max(A1, a1j);
+    cmax = std::max(cmax, cn);
+  }
+  // values below the normal range may be flushed by the matrix cores: an
+  // absolute floor far above any such effect for finite inputs
+  A0 += 1e-30;
+  BoundCoef b;
+  const double s = 1.0 + 0x1.0p-10;
+  b.a0 = round_up_f32(s * (2.0 * A0 + 2.0 * gam64 * cmax * cmax));
+  b.a1 = round_up_f32(s * (2.0 * A1 + 4.0 * gam64 * cmax));
+  b.a2 = round_up_f32(s * (2.0 * gam64));
+  return b;
+}
+
+}  // namespace
+
+// Builds every host table of a template from its FP32 codebook.
+void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_stride) {
+  const int D = t.D, k = t.k;
+  t.geom = make_assign_geom(k, D);
+  // template NNF with the exact FP64 rule
+  int64_t n = (int64_t)t.w * t.h;
+  std::vector<double> x((size_t)n * D), c((size_t)k * D);
+  for (int64_t p = 0; p < n; ++p)
+    for (int d = 0; d < D; ++d) x[(size_t)p * D + d] = (double)tmpl[p * tmpl_stride + d];
+  for (size_t i = 0; i < c.size(); ++i) c[i] = (double)t.codebook[i];
+  std::vector<int> lab = assign_host(x, n, D, c, k);
+  t.labels.resize(n);
+  for (int64_t p = 0; p < n; ++p) t.labels[p] = (uint8_t)lab[p];
+  // R(tau): per-filter counts over the template
+  t.counts.assign((size_t)t.n_filters * k, 0);
+  for (int f = 0; f < t.n_filters; ++f) {
+    const int32_t* b = &t.boxes[(size_t)f * 4];
+    for (int y = b[1]; y < b[3]; ++y)
+      for (int xx = b[0]; xx < b[2]; ++xx) t.counts[(size_t)f * k + t.labels[(size_t)y * t.w + xx]]++;
+  }
+}
+
+void build_tables(DeviceTemplate& t, HostTables& ht) {
+  const int D = t.D, k = t.k;
+  const AssignGeom& g = t.geom;
+  std::vector<float> hi((size_t)k * D), lo((size_t)k * D);
+  for (size_t i = 0; i < hi.size(); ++i) {
+    float c = t.codebook[i];
+    uint16_t hb = bf16_rne(c);
+    float hf = bf16_to_f32(hb);
+    float r = c - hf;  // exact (Sterbenz)
+    uint16_t lb = bf16_rne(r);
+    hi[i] = hf;
+    lo[i] = bf16_to_f32(lb);
+  }
+  // ||c||^2: FP64 sequential sum of squares, rounded to FP32
+  ht.cnorm.assign(g.kpad, 3.0e38f);
+  for (int j = 0; j < k; ++j) {
+    double s = 0.0;
+    for (int d = 0; d < D; ++d) {
+      double v = t.codebook[(size_t)j * D + d];
+      s = s + v * v;
+    }
+    ht.cnorm[j] = (float)s;
+  }
+  // BF16 fragments
+  const int S = g.s_bf16, KB = g.kb;
+  const int steps = g.d_pad_bf16 / 32;
+  ht.frag_bf16.assign((size_t)steps * 2 * KB * 64 * 8, 0);
+  for (int st = 0; st < steps; ++st) {
+    int gi = st / S, sp = st % S;
+    for (int term = 0; term < 2; ++term)
+      for (int mb = 0; mb < KB; ++mb)
+        for (int l = 0; l < 64; ++l) {
+          int m = l % 16, lg = l / 16;
+          int j = 16 * mb + m;
+          size_t base = ((((size_t)st * 2 + term) * KB + mb) * 64 + l) * 8;
+          for (int i = 0; i < 8; ++i) {
+            int d = 32 * S * gi + 8 * S * lg + 8 * sp + i;
+            float v = 0.0f;
+            if (j < k && d < D) v = -2.0f * (term == 0 ? hi : lo)[(size_t)j * D + d];
+            ht.frag_bf16[base + i] = bf16_rne(v);
+          }
+        }
+  }
+  // FP32 fragments
+  const int E = g.e_f32;
+  const int fsteps = g.d_pad_f32 / 4;
+  ht.frag_f32.assign((size_t)fsteps * KB * 64, 0.0f);
+  for (int st = 0; st < fsteps; ++st) {
+    int gi = st / E, sp = st % E;
+    for (int mb = 0; mb < KB; ++mb)
+      for (int l = 0; l < 64; ++l) {
+        int m = l % 16, lg = l / 16;
+        int j = 16 * mb + m;
+        int d = 4 * E * gi + E * lg + sp;
+        float v = 0.0f;
+        if (j < k && d < D) v = -2.0f * t.codebook[(size_t)j * D + d];
+        ht.frag_f32[((size_t)st * KB + mb) * 64 + l] = v;
+      }
+  }
+  // counts padded to kpad
+  ht.counts.assign((size_t)t.n_filters * g.kpad, 0);
+  ht.counts16.assign((size_t)t.n_filters * g.kpad / 2, 0);
+  for (int f = 0; f < t.n_filters; ++f)
+    for (int j = 0; j < k; ++j) {
+      int32_t v = t.counts[(size_t)f * k + j];
+      ht.counts[(size_t)f * g.kpad + j] = v;
+      ht.counts16[(size_t)f * g.kpad / 2 + j / 2] |= ((uint32_t)v & 0xFFFFu) << (16 * (j & 1));
+    }
+  t.bound_bf16q = make_bound(t, hi, lo, ht.cnorm, false);
+  t.bound_f32q = make_bound(t, hi, lo, ht.cnorm, true);
+}
+
+}  // namespace vqnnf

@@ -1,0 +1,254 @@
+"""GPU parity of every stage against the FP64 oracle, through the C ABI.
+
+Labels and integral images must match bit for bit; heatmaps within
+|gpu - oracle| <= 1e-5 * |oracle| + 2^-24 * S_max, where S_max = 4 is the
+largest magnitude the default bank's similarity can reach (two groups of
+distribution L1 terms, each at most 2).  The absolute floor covers windows
+whose exact score is 0 (perfect matches)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import vqnnf_oracle as O
+from paper_2306_15010_amd import binding as B
+from paper_2306_15010_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL, ABS = 1e-5, 4 * 2.0 ** -24
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    c = B.Context(stream=torch.cuda.current_stream())
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def to_dev(qm: synth.QueryMap):
+    if qm.dtype == "f32":
+        return torch.from_numpy(np.ascontiguousarray(qm.data)).cuda()
+    if qm.dtype == "bf16":
+        return torch.from_numpy(qm.data.view(np.int16)).cuda()
+    raise ValueError(qm.dtype)
+
+
+def fmap(t, qm):
+    return B.device_fmap(t, qm.dtype)
+
+
+def oracle_labels(qm, cb, rows=None, cols=None, pix=None):
+    q = O.decode(qm.dtype, qm.data, qm.scale)
+    cb64 = np.asarray(cb, np.float32).astype(np.float64)
+    if pix is not None:
+        flat = q.reshape(-1, q.shape[-1])[pix]
+        return O.assign(flat, cb64)
+    sub = q[rows[0]:rows[1], cols[0]:cols[1]]
+    return O.assign_map(sub, cb64)
+
+
+def check_heat(gpu, ref, what):
+    gpu = np.asarray(gpu, np.float64)
+    err = np.abs(gpu - ref)
+    tol = REL * np.abs(ref) + ABS
+    bad = err > tol
+    log(f"{what}: max abs err {err.max():.3e}, max rel {np.max(err / np.maximum(np.abs(ref), 1e-30)):.3e}")
+    assert not bad.any(), f"{what}: {bad.sum()} windows outside tolerance, worst {err[bad].max()}"
+
+
+# ---------------------------------------------------------------- assign
+
+ASSIGN_CASES = [
+    # H, W, D, dtype, k, seed
+    (64, 64, 27, "f32", 8, 1),
+    (37, 53, 27, "f32", 5, 2),
+    (50, 70, 64, "f32", 32, 3),
+    (33, 47, 100, "bf16", 17, 4),
+    (40, 41, 256, "bf16", 64, 5),
+    (31, 67, 512, "bf16", 128, 6),
+    (16, 16, 45, "bf16", 1, 7),
+    (23, 29, 70, "f32", 200, 8),
+    (19, 33, 96, "bf16", 256, 9),
+    (1, 1, 8, "f32", 3, 10),
+]
+
+
+@pytest.mark.parametrize("H,W,D,dt,k,seed", ASSIGN_CASES)
+def test_assign_refined_bit_exact(ctx, H, W, D, dt, k, seed):
+    log(f"assign case H={H} W={W} D={D} {dt} k={k} seed={seed}")
+    qm = synth.random_map(H, W, D, dt, seed=seed, M=max(2, k // 2 + 3))
+    side = min(H, W, 12)
+    tmpl = O.decode(qm.dtype, qm.data, qm.scale)[:side, :side].astype(np.float32)
+    rng = np.random.default_rng(seed)
+    # codebook: template pixels jittered (independent of any GPU output)
+    src = tmpl.reshape(-1, D)
+    cb = (src[rng.integers(0, len(src), size=k)]
+          + 0.05 * rng.standard_normal((k, D))).astype(np.float32)
+    tpl = B.vqnnf_template_from_codebook(ctx, tmpl, cb, B.default_bank(side, side, 1))
+    qd = to_dev(qm)
+    lab = torch.empty(H * W, dtype=torch.uint8, device="cuda")
+    nf = B.vqnnf_assign(ctx, tpl, fmap(qd, qm), B.VQNNF_PREC_BF16_REFINED, lab)
+    ref = oracle_labels(qm, cb, rows=(0, H), cols=(0, W)).reshape(-1)
+    got = lab.cpu().numpy().astype(np.int64)
+    log(f"  flagged {nf} of {H * W}; mismatches {(got != ref).sum()}")
+    assert np.array_equal(got, ref)
+    lab2 = torch.empty_like(lab)
+    B.vqnnf_assign(ctx, tpl, fmap(qd, qm), B.VQNNF_PREC_FP32_PLAIN, lab2)
+    mism = int((lab2.cpu().numpy().astype(np.int64) != ref).sum())
+    log(f"  fp32 plain mismatches {mism}")
+    assert mism <= max(2, H * W // 100)
+
+
+def test_assign_exact_ties_and_duplicates(ctx):
+    """Query pixels on exact dyadic midpoints of two codewords and codebooks
+    with duplicated rows: the FP64 distances tie exactly and the lower index
+    must win; only the re-score can decide these."""
+    rng = np.random.default_rng(11)
+    k, D = 12, 40
+    cb = (rng.integers(-64, 64, size=(k, D)) / 32.0).astype(np.float32)
+    cb[7] = cb[2]
+    cb[11] = cb[5]
+    pts = []
+    for _ in range(600):
+        a, b = sorted(rng.choice(k, size=2, replace=False))
+        pts.append((cb[a].astype(np.float64) + cb[b]) / 2)
+    for j in range(k):
+        pts.append(cb[j].astype(np.float64))
+    q = np.array(pts, dtype=np.float32)
+    n = len(q)
+    H, W = 1, n
+    qmap = q.reshape(H, W, D)
+    for dt in ("f32", "bf16"):
+        if dt == "bf16":
+            bits = synth.f32_to_bf16_bits(qmap)
+            assert np.array_equal(synth.bf16_bits_to_f32(bits), qmap)   # dyadic: exact
+            qm = synth.QueryMap(H, W, D, "bf16", bits, None)
+        else:
+            qm = synth.QueryMap(H, W, D, "f32", qmap, None)
+        tpl = B.vqnnf_template_from_codebook(ctx, qmap[:, :8].reshape(1, 8, D), cb,
+                                             [(0, 0, 8, 1, 1, 1, 1.0)])
+        lab = torch.empty(n, dtype=torch.uint8, device="cuda")
+        nf = B.vqnnf_assign(ctx, tpl, fmap(to_dev(qm), qm), B.VQNNF_PREC_BF16_REFINED, lab)
+        ref = O.assign(O.decode(qm.dtype, qm.data).reshape(n, D), cb.astype(np.float64))
+        got = lab.cpu().numpy().astype(np.int64)
+        log(f"ties {dt}: flagged {nf}, mismatches {(got != ref).sum()}")
+        assert nf >= 600
+        assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------- integral
+
+@pytest.mark.parametrize("H,W,k", [(1, 1, 1), (64, 64, 8), (70, 130, 7), (129, 65, 128),
+                                   (200, 3, 33), (3, 300, 256), (65, 129, 16)])
+def test_integral_bit_exact(ctx, H, W, k):
+    log(f"integral case H={H} W={W} k={k}")
+    rng = np.random.default_rng(H * 1000 + W + k)
+    labels = rng.integers(0, k, size=(H, W)).astype(np.uint8)
+    t = np.random.default_rng(0).standard_normal((1, 1, 4)).astype(np.float32)
+    cb = np.random.default_rng(1).standard_normal((k, 4)).astype(np.float32)
+    tpl = B.vqnnf_template_from_codebook(ctx, t, cb, [(0, 0, 1, 1, 1, 1, 1.0)])
+    ld = torch.from_numpy(labels.reshape(-1)).cuda()
+    P = torch.full(((H + 1) * (W + 1) * k,), -7, dtype=torch.int32, device="cuda")
+    B.vqnnf_filter(ctx, tpl, ld, H, W, P)
+    got = P.cpu().numpy().reshape(H + 1, W + 1, k)
+    ref = O.integral_image(labels, k)
+    assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------- score
+
+SCORE_CASES = [
+    # H, W, w, h, g, k
+    (64, 64, 16, 16, 2, 8),
+    (100, 140, 25, 25, 3, 32),
+    (150, 90, 48, 48, 3, 128),
+    (60, 260, 33, 21, 4, 17),
+    (40, 40, 40, 40, 2, 5),
+    (129, 300, 30, 30, 1, 64),
+    (96, 96, 96, 31, 3, 200),
+]
+
+
+@pytest.mark.parametrize("H,W,w,h,g,k", SCORE_CASES)
+def test_score_matches_oracle(ctx, H, W, w, h, g, k):
+    log(f"score case H={H} W={W} w={w} h={h} g={g} k={k}")
+    rng = np.random.default_rng(H + 7 * W + k)
+    # smooth-ish labels: blocks of a random coarse field
+    coarse = rng.integers(0, k, size=(H // 3 + 2, W // 3 + 2))
+    ql = np.kron(coarse, np.ones((3, 3), dtype=np.int64))[:H, :W]
+    noise = rng.random((H, W)) < 0.3
+    ql = np.where(noise, rng.integers(0, k, size=(H, W)), ql)
+    y0, x0 = int(rng.integers(0, H - h + 1)), int(rng.integers(0, W - w + 1))
+    tl = ql[y0:y0 + h, x0:x0 + w]
+    # a template whose FP64 labels are exactly tl: codewords are one-hot
+    # directions and template pixels sit on them
+    D = k
+    cb = np.eye(k, dtype=np.float32)
+    tmpl = cb[tl]
+    bank = B.default_bank(w, h, g)
+    tpl = B.vqnnf_template_from_codebook(ctx, tmpl, cb, bank)
+    assert np.array_equal(tpl.labels().astype(np.int64), tl)
+    filters = O.expand_bank(O.default_bank(w, h, g))
+    rt = O.template_representation(tl, k, filters)
+    ref = O.similarity_map_fast(ql, k, w, h, filters, rt)
+    ld = torch.from_numpy(ql.astype(np.uint8).reshape(-1)).cuda()
+    heat = torch.full(((H - h + 1) * (W - w + 1),), float("nan"), device="cuda")
+    (bx, by), bs = B.vqnnf_score(ctx, tpl, ld, H, W, heat)
+    hm = heat.cpu().numpy().reshape(H - h + 1, W - w + 1)
+    check_heat(hm, ref, "fused")
+    ox, oy, osc = O.localise(hm.astype(np.float64))
+    assert (bx, by) == (ox, oy) and bs == np.float32(osc)
+    assert ref[y0, x0] == 0.0 and hm[y0, x0] == 0.0
+    # integral-image path on the same labels
+    P = torch.empty(((H + 1) * (W + 1) * k,), dtype=torch.int32, device="cuda")
+    B.vqnnf_filter(ctx, tpl, ld, H, W, P)
+    heat2 = torch.full_like(heat, float("nan"))
+    (bx2, by2), bs2 = B.vqnnf_score_integral(ctx, tpl, P, H, W, heat2)
+    check_heat(heat2.cpu().numpy().reshape(hm.shape), ref, "integral")
+    assert (bx2, by2) == O.localise(heat2.cpu().numpy().reshape(hm.shape).astype(np.float64))[:2]
+
+
+# ---------------------------------------------------------------- end to end
+
+def _match_case(ctx, name, seed, prec):
+    wl = synth.make_config(name, seed=seed)
+    qm, t = wl.maps[0], wl.templates[0][0]
+    cb = O.kmeans_codebook(t.data, t.k, 20, seed=0)
+    bank = B.default_bank(t.data.shape[1], t.data.shape[0], t.grid)
+    tpl = B.vqnnf_template_from_codebook(ctx, t.data, cb, bank)
+    res = O.match(t.data, O.decode(qm.dtype, qm.data, qm.scale), t.k,
+                  O.default_bank(t.data.shape[1], t.data.shape[0], t.grid), codebook=cb)
+    qd = to_dev(qm)
+    oh, ow = res.sim.shape
+    heat = torch.full((oh * ow,), float("nan"), device="cuda")
+    (bx, by), bs = B.vqnnf_match(ctx, tpl, fmap(qd, qm), prec, heat)
+    return wl, t, res, heat.cpu().numpy().reshape(oh, ow), (bx, by), bs
+
+
+@pytest.mark.parametrize("seed_off", [0, 1, 2])
+def test_match_small_end_to_end(ctx, seed_off):
+    log(f"match 64x64 seed_off={seed_off}")
+    wl, t, res, hm, (bx, by), bs = _match_case(ctx, "c1", synth.MASTER_SEED + seed_off,
+                                               B.VQNNF_PREC_BF16_REFINED)
+    check_heat(hm, res.sim, "match c1")
+    assert (bx, by) == res.best[:2]
+    assert hm.shape == (49, 49)
+
+
+def test_match_512_end_to_end(ctx):
+    log("match 512x512 D=64 k=32")
+    wl, t, res, hm, (bx, by), bs = _match_case(ctx, "c2", None, B.VQNNF_PREC_BF16_REFINED)
+    check_heat(hm, res.sim, "match c2")
+    assert (bx, by) == res.best[:2]
+    log(f"c2 best {bx, by} planted {t.x0, t.y0} rot {t.rot}")
