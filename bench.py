@@ -50,7 +50,7 @@ def kernel_roofline(name, avg_ms, n_pix, D, qbytes, k, terms, n_win, n_f):
         return {"bound": "hbm", "achieved": by / s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": by / s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": by,
                 "mfma_tflops": 2.0 * n_pix * k * D * terms / s / 1e12}
-    if name == "score_fused":
+    if name == "score_partial":
         # per window, filter and channel: |T - C| and its accumulation (2 ops)
         # plus the box count from the integral-image taps (3 ops)
         ops = n_win * n_f * k * 5

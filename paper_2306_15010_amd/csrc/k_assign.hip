@@ -27,8 +27,8 @@ namespace {
 thread_local TimingHook g_hook{nullptr, nullptr, nullptr};
 const char* const kNames[K_COUNT] = {
     "fill",           "assign_fp32_plain", "assign_bf16_refined", "rescore_fp64",
-    "integral_edges", "integral_prefix",   "integral_main",       "score_fused",
-    "score_integral"};
+    "integral_edges", "integral_prefix",   "integral_main",       "score_partial",
+    "score_combine",  "score_integral"};
 }  // namespace
 
 void set_timing_hook(const TimingHook* h) {
@@ -151,133 +151,170 @@ __device__ __forceinline__ void merge_top2(float& v1, int& j1, float& v2, float 
 // ============================================================ BF16 refined
 // Template parameters: KB codeword blocks of 16, NB pixel blocks of 16 per
 // wave, S K-steps (of 32 elements) per load group, QF32: FP32-stored query
-// (hi/lo split in registers), VEC: 16-byte aligned rows, WPB waves per block.
-template <int KB, int NB, int S, bool QF32, bool VEC, int WPB>
-__global__ __launch_bounds__(WPB * 64) void assign_refined_kernel(KParams p) {
+// (hi/lo split in registers), VEC: 16-byte aligned rows.
+//
+// A block of 8 waves owns tiles of 8*NB*16 pixels and walks the load groups
+// of D.  The codebook fragments of group g+1 are fetched into registers and
+// the query elements of group g+1 are requested while group g is multiplied;
+// the fragments are written to the other half of a double-buffered LDS
+// stage, so one barrier per group suffices.  Blocks are persistent over
+// tiles, and the prefetch runs across tile boundaries.
+constexpr int kWPB = 8;
+
+// Work of one block is a flat stream of (tile, group) steps; the query
+// elements of step s+2 are requested while step s is multiplied, alternating
+// between two register buffers (even and odd steps).
+struct StepCursor {
+  int64_t tile;
+  int gi;
+};
+
+template <int KB, int NB, int S, bool QF32, bool VEC>
+__global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
   extern __shared__ uint4 lds[];
-  constexpr int GROUP_FRAGS = S * 2 * KB * 64;     // uint4 per load group
+  constexpr int NT = kWPB * 64;
+  constexpr int GF = S * 2 * KB * 64;              // uint4 per load group
+  constexpr int CPT = (GF + NT - 1) / NT;          // staged per thread
   constexpr int NEL = 8 * S;                       // elements per lane per group
+  constexpr int QW = QF32 ? NEL : NEL / 2;         // 32-bit words per lane per group
   constexpr int MW = (KB + 1) / 2;                 // candidate mask words
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int n = lane & 15, g = lane >> 4;
   const uint4* frag = (const uint4*)p.frag;
+  const int ngr = p.n_groups;
+  constexpr int64_t TILE = kWPB * NB * 16;
+  if ((int64_t)blockIdx.x >= p.n_tiles) return;
 
-  if (p.resident) {
-    const int total = p.n_groups * GROUP_FRAGS;
-    for (int i = threadIdx.x; i < total; i += WPB * 64) lds[i] = frag[i];
-    __syncthreads();
-  }
-
-  for (int64_t tile = blockIdx.x; tile < p.n_tiles; tile += gridDim.x) {
-    const int64_t pix0 = tile * (WPB * NB * 16) + (int64_t)wave * NB * 16;
-    f32x4_t acc[KB][NB];
-#pragma unroll
-    for (int mb = 0; mb < KB; ++mb) {
-      f32x4_t c0 = *(const f32x4_t*)(p.cnorm + 16 * mb + 4 * g);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = c0;
+  auto advance = [&](StepCursor c) {
+    if (++c.gi == ngr) {
+      c.gi = 0;
+      c.tile += gridDim.x;
     }
-    float qn2[NB];
-    int64_t off[NB];
+    return c;
+  };
+  auto pix_off = [&](int64_t tl, int nb) {
+    int64_t pix = tl * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
+    if (pix >= p.n_pix) pix = p.n_pix - 1;
+    return pix * p.stride;
+  };
+  uint4 cbr[CPT];
+  uint32_t qa[NB][QW], qb[NB][QW];
+  auto load_cb = [&](int gi) {
+    const uint4* src = frag + (int64_t)gi * GF;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      qn2[nb] = 0.f;
-      int64_t pix = pix0 + 16 * nb + n;
-      if (pix >= p.n_pix) pix = p.n_pix - 1;
-      off[nb] = pix * p.stride;
+    for (int i = 0; i < CPT; ++i) {
+      const int idx = threadIdx.x + i * NT;
+      if (idx < GF) cbr[i] = src[idx];
     }
+  };
+  auto load_q = [&](StepCursor c, uint32_t (&dst)[NB][QW]) {
+    if (c.tile >= p.n_tiles) return;
+    const int d0 = c.gi * 32 * S + NEL * g;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) load_query<QF32, VEC, NEL>(p.q, pix_off(c.tile, nb), d0, p.D, dst[nb]);
+  };
 
-    for (int gi = 0; gi < p.n_groups; ++gi) {
-      const uint4* a_src;
-      if (!p.resident) {
-        __syncthreads();
-        const uint4* src = frag + (int64_t)gi * GROUP_FRAGS;
-        for (int i = threadIdx.x; i < GROUP_FRAGS; i += WPB * 64) lds[i] = src[i];
-        __syncthreads();
-        a_src = lds;
-      } else {
-        a_src = lds + gi * GROUP_FRAGS;
+  f32x4_t acc[KB][NB];
+  float qn2[NB];
+  auto reset = [&]() {  // new tile
+#pragma unroll
+    for (int mb = 0; mb < KB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) qn2[nb] = 0.f;
+  };
+
+  // multiply-accumulate of one group from the LDS stage and a query buffer
+  auto compute = [&](const uint4* stage, uint32_t (&cur)[NB][QW]) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      uint4 bhi[NB], blo[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        if (QF32) {
+          uint32_t h[8], l[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const float x = __uint_as_float(cur[nb][8 * s + i]);
+            qn2[nb] = fmaf(x, x, qn2[nb]);
+            const uint32_t hb = f32_to_bf16_rne(x);
+            const float r = x - bf16_bits_to_f32(hb);
+            h[i] = hb;
+            l[i] = f32_to_bf16_rne(r);
+          }
+          bhi[nb] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                               h[6] | (h[7] << 16));
+          blo[nb] = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16),
+                               l[6] | (l[7] << 16));
+        } else {
+          const uint32_t w0 = cur[nb][4 * s], w1 = cur[nb][4 * s + 1];
+          const uint32_t w2 = cur[nb][4 * s + 2], w3 = cur[nb][4 * s + 3];
+          bhi[nb] = make_uint4(w0, w1, w2, w3);
+          const uint32_t ws[4] = {w0, w1, w2, w3};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float lo = __uint_as_float(ws[i] << 16), hi = __uint_as_float(ws[i] & 0xFFFF0000u);
+            qn2[nb] = fmaf(lo, lo, qn2[nb]);
+            qn2[nb] = fmaf(hi, hi, qn2[nb]);
+          }
+        }
       }
-      const int d0 = gi * 32 * S + NEL * g;
-      uint32_t qraw[NB][QF32 ? NEL : NEL / 2];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) load_query<QF32, VEC, NEL>(p.q, off[nb], d0, p.D, qraw[nb]);
-
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        uint4 bhi[NB], blo[NB];
+      for (int mb = 0; mb < KB; ++mb) {
+        const uint4 ahi = stage[((s * 2 + 0) * KB + mb) * 64 + lane];
+        const uint4 alo = stage[((s * 2 + 1) * KB + mb) * 64 + lane];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          if (QF32) {
-            uint32_t h[8], l[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              float x = __uint_as_float(qraw[nb][8 * s + i]);
-              qn2[nb] = fmaf(x, x, qn2[nb]);
-              uint32_t hb = f32_to_bf16_rne(x);
-              float r = x - bf16_bits_to_f32(hb);
-              h[i] = hb;
-              l[i] = f32_to_bf16_rne(r);
-            }
-            bhi[nb] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
-                                 h[6] | (h[7] << 16));
-            blo[nb] = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16),
-                                 l[6] | (l[7] << 16));
-          } else {
-            uint32_t w0 = qraw[nb][4 * s], w1 = qraw[nb][4 * s + 1];
-            uint32_t w2 = qraw[nb][4 * s + 2], w3 = qraw[nb][4 * s + 3];
-            bhi[nb] = make_uint4(w0, w1, w2, w3);
-            uint32_t ws[4] = {w0, w1, w2, w3};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              float lo = __uint_as_float(ws[i] << 16), hi = __uint_as_float(ws[i] & 0xFFFF0000u);
-              qn2[nb] = fmaf(lo, lo, qn2[nb]);
-              qn2[nb] = fmaf(hi, hi, qn2[nb]);
-            }
-          }
-        }
-#pragma unroll
-        for (int mb = 0; mb < KB; ++mb) {
-          const uint4 ahi = a_src[((s * 2 + 0) * KB + mb) * 64 + lane];
-          const uint4 alo = a_src[((s * 2 + 1) * KB + mb) * 64 + lane];
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            acc[mb][nb] = mfma_bf16(ahi, bhi[nb], acc[mb][nb]);
-            acc[mb][nb] = mfma_bf16(alo, bhi[nb], acc[mb][nb]);
-            if (QF32) acc[mb][nb] = mfma_bf16(ahi, blo[nb], acc[mb][nb]);
-          }
+          acc[mb][nb] = mfma_bf16(ahi, bhi[nb], acc[mb][nb]);
+          acc[mb][nb] = mfma_bf16(alo, bhi[nb], acc[mb][nb]);
+          if (QF32) acc[mb][nb] = mfma_bf16(ahi, blo[nb], acc[mb][nb]);
         }
       }
     }
+  };
 
-    // ---------------------------------------------------------- epilogue
+  // epilogue of a finished tile: s_j = ||c_j||^2 + (-2 q.c_j), the norm
+  // added once after the products were accumulated from zero
+  auto finish = [&](int64_t tile) {
+    float cn[KB][4];
+#pragma unroll
+    for (int mb = 0; mb < KB; ++mb) {
+      const f32x4_t c0 = *(const f32x4_t*)(p.cnorm + 16 * mb + 4 * g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cn[mb][i] = c0[i];
+    }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+      for (int mb = 0; mb < KB; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[mb][nb][i] = cn[mb][i] + acc[mb][nb][i];
       float v1 = 3.4e38f, v2 = 3.4e38f;
       int j1 = 0;
 #pragma unroll
       for (int mb = 0; mb < KB; ++mb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          float v = acc[mb][nb][i];
-          int j = 16 * mb + 4 * g + i;
+          const float v = acc[mb][nb][i];
+          const int j = 16 * mb + 4 * g + i;
           if (v < v1) { v2 = v1; v1 = v; j1 = j; }
           else if (v < v2) { v2 = v; }
         }
       float q2 = qn2[nb];
 #pragma unroll
       for (int m = 16; m <= 32; m <<= 1) {
-        float o1 = __shfl_xor(v1, m), o2 = __shfl_xor(v2, m);
-        int oj = __shfl_xor(j1, m);
+        const float o1 = __shfl_xor(v1, m), o2 = __shfl_xor(v2, m);
+        const int oj = __shfl_xor(j1, m);
         merge_top2(v1, j1, v2, o1, oj, o2);
         q2 += __shfl_xor(q2, m);
       }
       // upper bound of ||q||: FP32 sum of squares error, then sqrt rounding
-      float nq = sqrtf(q2 * (1.0f + (float)(p.D + 8) * 0x1.0p-23f)) * (1.0f + 0x1.0p-20f);
-      float thr = (p.a0 + nq * (p.a1 + nq * p.a2)) * (1.0f + 0x1.0p-18f);
-      bool flagged = (v2 - v1) <= thr;
-      const int64_t pix = pix0 + 16 * nb + n;
+      const float nq = sqrtf(q2 * (1.0f + (float)(p.D + 8) * 0x1.0p-23f)) * (1.0f + 0x1.0p-20f);
+      const float thr = (p.a0 + nq * (p.a1 + nq * p.a2)) * (1.0f + 0x1.0p-18f);
+      const bool flagged = (v2 - v1) <= thr;
+      const int64_t pix = tile * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
       const bool owner = (g == 0) && (pix < p.n_pix);
       if (owner) p.labels[pix] = (uint8_t)j1;
       const bool fl = owner && flagged;
@@ -300,77 +337,130 @@ __global__ __launch_bounds__(WPB * 64) void assign_refined_kernel(KParams p) {
         if (lane == 0) base = atomicAdd(p.wl_count, (uint32_t)__popcll(bal));
         base = __shfl(base, 0);
         if (fl) {
-          uint32_t slot = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+          const uint32_t slot = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
           p.wl_pix[slot] = (uint32_t)pix;
 #pragma unroll
           for (int w = 0; w < MW; ++w) p.wl_mask[(int64_t)slot * MW + w] = mw[w];
         }
       }
     }
+  };
+
+  // groups per tile are even (D is padded to a multiple of 64), so buffer
+  // qa always holds even groups and qb odd groups, across tiles too
+  StepCursor c0{(int64_t)blockIdx.x, 0};
+  load_cb(0);
+  load_q(c0, qa);
+  load_q(advance(c0), qb);
+  int buf = 0;
+  for (int64_t tile = blockIdx.x; tile < p.n_tiles; tile += gridDim.x) {
+    reset();
+    for (int gi = 0; gi < ngr; gi += 2) {
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const StepCursor cur{tile, gi + half};
+        uint4* stage = lds + buf * GF;
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) {
+          const int idx = threadIdx.x + i * NT;
+          if (idx < GF) stage[idx] = cbr[i];
+        }
+        __syncthreads();
+        const StepCursor nx = advance(cur);
+        if (nx.tile < p.n_tiles) load_cb(nx.gi);
+        if (half == 0) {
+          compute(stage, qa);
+          load_q(advance(nx), qa);
+        } else {
+          compute(stage, qb);
+          load_q(advance(nx), qb);
+        }
+        buf ^= 1;
+      }
+    }
+    finish(tile);
   }
 }
 
 // ============================================================ FP32 plain
 // v_mfma_f32_16x16x4_f32: per K-step every lane supplies one element.  A load
 // group is 4*E elements; lane group g reads elements [E*g, E*g + E) and K-step
-// s of the group uses element E*g + s.
-template <int KB, int NB, int E, bool QF32, bool VEC, int WPB>
-__global__ __launch_bounds__(WPB * 64) void assign_plain_kernel(KParams p) {
-  extern __shared__ float ldsf[];
-  constexpr int GROUP = E * KB * 64;   // floats per load group
+// s of the group uses element E*g + s.  Same pipeline as the refined kernel:
+// 8 waves, codebook groups double-buffered in LDS, query prefetched one group
+// ahead, persistent blocks.
+template <int KB, int NB, int E, bool QF32, bool VEC>
+__global__ __launch_bounds__(kWPB * 64) void assign_plain_kernel(KParams p) {
+  extern __shared__ float4 ldsf[];
+  constexpr int NT = kWPB * 64;
+  constexpr int GF = E * KB * 64 / 4;              // float4 per load group
+  constexpr int CPT = (GF + NT - 1) / NT;
+  constexpr int QW = QF32 ? E : E / 2;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int n = lane & 15, g = lane >> 4;
-  const float* frag = (const float*)p.frag;
+  const float4* frag = (const float4*)p.frag;
+  const int ngr = p.n_groups;
+  constexpr int64_t TILE = kWPB * NB * 16;
+  int64_t tile = blockIdx.x;
+  if (tile >= p.n_tiles) return;
 
-  if (p.resident) {
-    const int total = p.n_groups * GROUP;
-    for (int i = threadIdx.x; i < total; i += WPB * 64) ldsf[i] = frag[i];
-    __syncthreads();
-  }
-  for (int64_t tile = blockIdx.x; tile < p.n_tiles; tile += gridDim.x) {
-    const int64_t pix0 = tile * (WPB * NB * 16) + (int64_t)wave * NB * 16;
+  auto pix_off = [&](int64_t tl, int nb) {
+    int64_t pix = tl * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
+    if (pix >= p.n_pix) pix = p.n_pix - 1;
+    return pix * p.stride;
+  };
+  float4 cbr[CPT];
+  uint32_t cur[NB][QW], nxt[NB][QW];
+  auto load_cb = [&](int gi) {
+    const float4* src = frag + (int64_t)gi * GF;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int idx = threadIdx.x + i * NT;
+      if (idx < GF) cbr[i] = src[idx];
+    }
+  };
+  auto load_q = [&](int64_t tl, int gi, uint32_t (&dst)[NB][QW]) {
+    const int d0 = gi * 4 * E + E * g;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) load_query<QF32, VEC, E>(p.q, pix_off(tl, nb), d0, p.D, dst[nb]);
+  };
+  load_cb(0);
+  load_q(tile, 0, cur);
+  int buf = 0;
+  for (;;) {
     f32x4_t acc[KB][NB];
 #pragma unroll
-    for (int mb = 0; mb < KB; ++mb) {
-      f32x4_t c0 = *(const f32x4_t*)(p.cnorm + 16 * mb + 4 * g);
+    for (int mb = 0; mb < KB; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = c0;
-    }
-    int64_t off[NB];
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int gi = 0; gi < ngr; ++gi) {
+      float4* stage4 = ldsf + buf * GF;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      int64_t pix = pix0 + 16 * nb + n;
-      if (pix >= p.n_pix) pix = p.n_pix - 1;
-      off[nb] = pix * p.stride;
-    }
-    for (int gi = 0; gi < p.n_groups; ++gi) {
-      const float* a_src;
-      if (!p.resident) {
-        __syncthreads();
-        const float* src = frag + (int64_t)gi * GROUP;
-        for (int i = threadIdx.x; i < GROUP; i += WPB * 64) ldsf[i] = src[i];
-        __syncthreads();
-        a_src = ldsf;
-      } else {
-        a_src = ldsf + gi * GROUP;
+      for (int i = 0; i < CPT; ++i) {
+        const int idx = threadIdx.x + i * NT;
+        if (idx < GF) stage4[idx] = cbr[i];
       }
-      const int d0 = gi * 4 * E + E * g;
+      __syncthreads();
+      const bool more_g = gi + 1 < ngr;
+      const int64_t ntile = more_g ? tile : tile + gridDim.x;
+      const int ngi = more_g ? gi + 1 : 0;
+      const bool have_next = ntile < p.n_tiles;
+      if (have_next) {
+        load_cb(ngi);
+        load_q(ntile, ngi, nxt);
+      }
+      const float* stage = (const float*)stage4;
       float x[NB][E];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         if (QF32) {
-          uint32_t r[E];
-          load_query<true, VEC, E>(p.q, off[nb], d0, p.D, r);
 #pragma unroll
-          for (int i = 0; i < E; ++i) x[nb][i] = __uint_as_float(r[i]);
+          for (int i = 0; i < E; ++i) x[nb][i] = __uint_as_float(cur[nb][i]);
         } else {
-          uint32_t r[E / 2];
-          load_query<false, VEC, E>(p.q, off[nb], d0, p.D, r);
 #pragma unroll
           for (int i = 0; i < E / 2; ++i) {
-            x[nb][2 * i] = __uint_as_float(r[i] << 16);
-            x[nb][2 * i + 1] = __uint_as_float(r[i] & 0xFFFF0000u);
+            x[nb][2 * i] = __uint_as_float(cur[nb][i] << 16);
+            x[nb][2 * i + 1] = __uint_as_float(cur[nb][i] & 0xFFFF0000u);
           }
         }
       }
@@ -378,44 +468,56 @@ __global__ __launch_bounds__(WPB * 64) void assign_plain_kernel(KParams p) {
       for (int s = 0; s < E; ++s)
 #pragma unroll
         for (int mb = 0; mb < KB; ++mb) {
-          const float a = a_src[(s * KB + mb) * 64 + lane];
+          const float a = stage[(s * KB + mb) * 64 + lane];
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
             acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x[nb][s], acc[mb][nb], 0, 0, 0);
         }
+      buf ^= 1;
+      if (have_next) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int i = 0; i < QW; ++i) cur[nb][i] = nxt[nb][i];
+      }
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       float v1 = 3.4e38f;
       int j1 = 0;
 #pragma unroll
-      for (int mb = 0; mb < KB; ++mb)
+      for (int mb = 0; mb < KB; ++mb) {
+        const f32x4_t c0 = *(const f32x4_t*)(p.cnorm + 16 * mb + 4 * g);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          float v = acc[mb][nb][i];
+          const float v = c0[i] + acc[mb][nb][i];
           if (v < v1) { v1 = v; j1 = 16 * mb + 4 * g + i; }
         }
+      }
 #pragma unroll
       for (int m = 16; m <= 32; m <<= 1) {
-        float o = __shfl_xor(v1, m);
-        int oj = __shfl_xor(j1, m);
+        const float o = __shfl_xor(v1, m);
+        const int oj = __shfl_xor(j1, m);
         if (o < v1 || (o == v1 && oj < j1)) { v1 = o; j1 = oj; }
       }
-      const int64_t pix = pix0 + 16 * nb + n;
+      const int64_t pix = tile * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
       if (g == 0 && pix < p.n_pix) p.labels[pix] = (uint8_t)j1;
     }
+    tile += gridDim.x;
+    if (tile >= p.n_tiles) break;
   }
 }
 
 // ============================================================ FP64 re-score
 // One thread per flagged pixel: FP64 distances to every candidate codeword in
 // the fixed order d = sum_t (q_t - c_t)^2, sequential in t from 0, separate
-// subtract, multiply and add; strict < over ascending indices keeps the
-// lowest index on ties.
+// subtract, multiply and add.  Candidates are taken four at a time, in
+// ascending index, as four independent sequential sums; a strict < over
+// ascending indices keeps the lowest index on ties.
 struct RParams {
   const void* q;
   int64_t stride;
-  int D, k, mask_words, qf32;
+  int D, k, mask_words;
   const float* codebook;
   const uint32_t* wl_count;
   const uint32_t* wl_pix;
@@ -423,40 +525,109 @@ struct RParams {
   uint8_t* labels;
 };
 
-__global__ __launch_bounds__(256) void rescore_kernel(RParams p) {
+template <bool QF32>
+__device__ __forceinline__ double q_elem(const void* q, int64_t off, int t) {
+  if (QF32) return (double)((const float*)q)[off + t];
+  return (double)bf16_bits_to_f32(((const uint16_t*)q)[off + t]);
+}
+
+// Sequential FP64 distances of one pixel to n <= 4 codewords.  VEC: 8-element
+// vector loads (query row and codebook rows 16-byte aligned).
+template <bool QF32, bool VEC>
+__device__ void dist4(const void* q, int64_t off, const float* cb, const int* js, int n, int D,
+                      double* acc) {
 #pragma clang fp contract(off)
+  const float* c0 = cb + (int64_t)js[0] * D;
+  const float* c1 = cb + (int64_t)js[n > 1 ? 1 : 0] * D;
+  const float* c2 = cb + (int64_t)js[n > 2 ? 2 : 0] * D;
+  const float* c3 = cb + (int64_t)js[n > 3 ? 3 : 0] * D;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int t = 0;
+  if (VEC) {
+    for (; t + 8 <= D; t += 8) {
+      double qd[8];
+      if (QF32) {
+        const float4* qp = (const float4*)((const float*)q + off + t);
+        float4 x0 = qp[0], x1 = qp[1];
+        qd[0] = x0.x; qd[1] = x0.y; qd[2] = x0.z; qd[3] = x0.w;
+        qd[4] = x1.x; qd[5] = x1.y; qd[6] = x1.z; qd[7] = x1.w;
+      } else {
+        uint4 w = *(const uint4*)((const uint16_t*)q + off + t);
+        uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          qd[2 * i] = (double)__uint_as_float(ws[i] << 16);
+          qd[2 * i + 1] = (double)__uint_as_float(ws[i] & 0xFFFF0000u);
+        }
+      }
+      const float4* r0 = (const float4*)(c0 + t);
+      const float4* r1 = (const float4*)(c1 + t);
+      const float4* r2 = (const float4*)(c2 + t);
+      const float4* r3 = (const float4*)(c3 + t);
+      float4 u0 = r0[0], u1 = r0[1], v0 = r1[0], v1 = r1[1];
+      float4 w0 = r2[0], w1 = r2[1], z0 = r3[0], z1 = r3[1];
+      const float cA[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+      const float cB[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+      const float cC[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+      const float cD[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        double d0 = qd[i] - (double)cA[i];
+        double d1 = qd[i] - (double)cB[i];
+        double d2 = qd[i] - (double)cC[i];
+        double d3 = qd[i] - (double)cD[i];
+        double s0 = d0 * d0, s1 = d1 * d1, s2 = d2 * d2, s3 = d3 * d3;
+        a0 = a0 + s0;
+        a1 = a1 + s1;
+        a2 = a2 + s2;
+        a3 = a3 + s3;
+      }
+    }
+  }
+  for (; t < D; ++t) {
+    const double qv = q_elem<QF32>(q, off, t);
+    double d0 = qv - (double)c0[t], d1 = qv - (double)c1[t];
+    double d2 = qv - (double)c2[t], d3 = qv - (double)c3[t];
+    double s0 = d0 * d0, s1 = d1 * d1, s2 = d2 * d2, s3 = d3 * d3;
+    a0 = a0 + s0;
+    a1 = a1 + s1;
+    a2 = a2 + s2;
+    a3 = a3 + s3;
+  }
+  acc[0] = a0;
+  acc[1] = a1;
+  acc[2] = a2;
+  acc[3] = a3;
+}
+
+template <bool QF32, bool VEC>
+__global__ __launch_bounds__(256) void rescore_kernel(RParams p) {
   const uint32_t count = *p.wl_count;
   for (uint32_t it = blockIdx.x * blockDim.x + threadIdx.x; it < count;
        it += gridDim.x * blockDim.x) {
     const uint32_t pix = p.wl_pix[it];
     const uint32_t* mask = p.wl_mask + (int64_t)it * p.mask_words;
+    const int64_t off = (int64_t)pix * p.stride;
     double best = 0.0;
     int bj = -1;
-    for (int w = 0; w < p.mask_words; ++w) {
-      uint32_t bits = mask[w];
-      while (bits) {
-        int b = __ffs(bits) - 1;
-        bits &= bits - 1u;
-        int j = 32 * w + b;
-        if (j >= p.k) continue;
-        const float* c = p.codebook + (int64_t)j * p.D;
-        double acc = 0.0;
-        if (p.qf32) {
-          const float* q = (const float*)p.q + (int64_t)pix * p.stride;
-          for (int t = 0; t < p.D; ++t) {
-            double d = (double)q[t] - (double)c[t];
-            double sq = d * d;
-            acc = acc + sq;
-          }
-        } else {
-          const uint16_t* q = (const uint16_t*)p.q + (int64_t)pix * p.stride;
-          for (int t = 0; t < p.D; ++t) {
-            double d = (double)bf16_bits_to_f32(q[t]) - (double)c[t];
-            double sq = d * d;
-            acc = acc + sq;
-          }
+    int js[4];
+    int n = 0;
+    for (int w = 0; w <= p.mask_words; ++w) {
+      uint32_t bits = (w < p.mask_words) ? mask[w] : 0u;
+      // flush a full group, or the remainder after the last word
+      while (bits || (w == p.mask_words && n > 0)) {
+        if (bits) {
+          const int j = 32 * w + (__ffs(bits) - 1);
+          bits &= bits - 1u;
+          if (j >= p.k) continue;
+          js[n++] = j;
+          if (n < 4) continue;
         }
-        if (bj < 0 || acc < best) { best = acc; bj = j; }
+        double acc[4];
+        dist4<QF32, VEC>(p.q, off, p.codebook, js, n, p.D, acc);
+        for (int c = 0; c < n; ++c)
+          if (bj < 0 || acc[c] < best) { best = acc[c]; bj = js[c]; }
+        n = 0;
       }
     }
     if (bj >= 0) p.labels[pix] = (uint8_t)bj;
@@ -471,66 +642,62 @@ bool rows_aligned(const AssignArgs& a, int elem_bytes) {
   return (base % 16 == 0) && ((a.stride * elem_bytes) % 16 == 0);
 }
 
-template <int KB, int NB, int S, bool QF32, bool VEC, int WPB>
+template <int KB, int NB, int S, bool QF32, bool VEC>
 hipError_t go_refined(const KParams& kp, size_t lds, int grid, hipStream_t s) {
-  auto kern = assign_refined_kernel<KB, NB, S, QF32, VEC, WPB>;
+  auto kern = assign_refined_kernel<KB, NB, S, QF32, VEC>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(WPB * 64), lds, s, kp);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kWPB * 64), lds, s, kp);
   return hipGetLastError();
 }
 
-template <int KB, int NB, int S, bool QF32, int WPB>
+template <int KB, int NB, int S, bool QF32>
 hipError_t go_refined_v(const KParams& kp, size_t lds, int grid, bool vec, hipStream_t s) {
-  return vec ? go_refined<KB, NB, S, QF32, true, WPB>(kp, lds, grid, s)
-             : go_refined<KB, NB, S, QF32, false, WPB>(kp, lds, grid, s);
+  return vec ? go_refined<KB, NB, S, QF32, true>(kp, lds, grid, s)
+             : go_refined<KB, NB, S, QF32, false>(kp, lds, grid, s);
 }
 
-template <int KB, int NB, int WPB>
+template <int KB, int NB>
 hipError_t go_refined_s(const KParams& kp, size_t lds, int grid, int S, bool qf32, bool vec,
                         hipStream_t s) {
-  if (qf32) {
-    if (S == 4) return go_refined_v<KB, NB, 4, true, WPB>(kp, lds, grid, vec, s);
-    if (S == 2) return go_refined_v<KB, NB, 2, true, WPB>(kp, lds, grid, vec, s);
-    return go_refined_v<KB, NB, 1, true, WPB>(kp, lds, grid, vec, s);
-  }
-  if (S == 4) return go_refined_v<KB, NB, 4, false, WPB>(kp, lds, grid, vec, s);
-  if (S == 2) return go_refined_v<KB, NB, 2, false, WPB>(kp, lds, grid, vec, s);
-  return go_refined_v<KB, NB, 1, false, WPB>(kp, lds, grid, vec, s);
+  // load groups are one K-step (S == 1) for every geometry
+  if (S != 1) return hipErrorInvalidValue;
+  if (qf32) return go_refined_v<KB, NB, 1, true>(kp, lds, grid, vec, s);
+  return go_refined_v<KB, NB, 1, false>(kp, lds, grid, vec, s);
 }
 
-template <int KB, int NB, int E, bool QF32, bool VEC, int WPB>
+template <int KB, int NB, int E, bool QF32, bool VEC>
 hipError_t go_plain(const KParams& kp, size_t lds, int grid, hipStream_t s) {
-  auto kern = assign_plain_kernel<KB, NB, E, QF32, VEC, WPB>;
+  auto kern = assign_plain_kernel<KB, NB, E, QF32, VEC>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(WPB * 64), lds, s, kp);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kWPB * 64), lds, s, kp);
   return hipGetLastError();
 }
 
-template <int KB, int NB, int WPB>
+template <int KB, int NB>
 hipError_t go_plain_s(const KParams& kp, size_t lds, int grid, int E, bool qf32, bool vec,
                       hipStream_t s) {
   if (qf32) {
-    if (E == 8) return vec ? go_plain<KB, NB, 8, true, true, WPB>(kp, lds, grid, s)
-                           : go_plain<KB, NB, 8, true, false, WPB>(kp, lds, grid, s);
-    return vec ? go_plain<KB, NB, 4, true, true, WPB>(kp, lds, grid, s)
-               : go_plain<KB, NB, 4, true, false, WPB>(kp, lds, grid, s);
+    if (E == 8) return vec ? go_plain<KB, NB, 8, true, true>(kp, lds, grid, s)
+                           : go_plain<KB, NB, 8, true, false>(kp, lds, grid, s);
+    return vec ? go_plain<KB, NB, 4, true, true>(kp, lds, grid, s)
+               : go_plain<KB, NB, 4, true, false>(kp, lds, grid, s);
   }
-  if (E == 8) return vec ? go_plain<KB, NB, 8, false, true, WPB>(kp, lds, grid, s)
-                         : go_plain<KB, NB, 8, false, false, WPB>(kp, lds, grid, s);
-  return vec ? go_plain<KB, NB, 4, false, true, WPB>(kp, lds, grid, s)
-             : go_plain<KB, NB, 4, false, false, WPB>(kp, lds, grid, s);
+  if (E == 8) return vec ? go_plain<KB, NB, 8, false, true>(kp, lds, grid, s)
+                         : go_plain<KB, NB, 8, false, false>(kp, lds, grid, s);
+  return vec ? go_plain<KB, NB, 4, false, true>(kp, lds, grid, s)
+             : go_plain<KB, NB, 4, false, false>(kp, lds, grid, s);
 }
 
-constexpr int kWPB = 4;
-constexpr size_t kResidentLds = 96 * 1024;
-
 }  // namespace
+
+// Pixel blocks per wave: KB*NB*4 accumulators stay <= 128 registers.
+static int pick_nb(int kb) { return kb <= 8 ? 4 : 2; }
 
 hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu) {
   const DeviceTemplate& t = *a.t;
@@ -552,25 +719,21 @@ hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu) {
   kp.a2 = a.bound.a2;
   const bool qf32 = a.dtype == VQNNF_F32;
   const bool vec = rows_aligned(a, qf32 ? 4 : 2);
-  const size_t group_bytes = (size_t)g.s_bf16 * 2 * g.kb * 64 * 16;
-  const size_t all_bytes = group_bytes * kp.n_groups;
-  kp.resident = all_bytes <= kResidentLds;
-  const size_t lds = kp.resident ? all_bytes : group_bytes;
-  // pixel blocks per wave: KB*NB*4 accumulators stay <= 128 registers
-  const int NB = g.kb <= 8 ? 4 : 2;
-  const int tile_px = kWPB * NB * 16;
+  const size_t lds = 2 * (size_t)g.s_bf16 * 2 * g.kb * 64 * 16;
+  const int NB = pick_nb(g.kb);
+  const int64_t tile_px = (int64_t)kWPB * NB * 16;
   kp.n_tiles = (a.n_pix + tile_px - 1) / tile_px;
-  int grid = (int)std::min<int64_t>(kp.n_tiles, kp.resident ? (int64_t)n_cu * 8 : kp.n_tiles);
+  const int grid = (int)std::min<int64_t>(kp.n_tiles, (int64_t)n_cu);
   timing_begin(K_ASSIGN_REFINED);
   hipError_t e;
   const int S = g.s_bf16;
   switch (g.kb) {
-    case 1: e = go_refined_s<1, 4, kWPB>(kp, lds, grid, S, qf32, vec, s); break;
-    case 2: e = go_refined_s<2, 4, kWPB>(kp, lds, grid, S, qf32, vec, s); break;
-    case 3: e = go_refined_s<3, 4, kWPB>(kp, lds, grid, S, qf32, vec, s); break;
-    case 4: e = go_refined_s<4, 4, kWPB>(kp, lds, grid, S, qf32, vec, s); break;
-    case 8: e = go_refined_s<8, 4, kWPB>(kp, lds, grid, S, qf32, vec, s); break;
-    case 16: e = go_refined_s<16, 2, kWPB>(kp, lds, grid, S, qf32, vec, s); break;
+    case 1: e = go_refined_s<1, 4>(kp, lds, grid, S, qf32, vec, s); break;
+    case 2: e = go_refined_s<2, 4>(kp, lds, grid, S, qf32, vec, s); break;
+    case 3: e = go_refined_s<3, 4>(kp, lds, grid, S, qf32, vec, s); break;
+    case 4: e = go_refined_s<4, 4>(kp, lds, grid, S, qf32, vec, s); break;
+    case 8: e = go_refined_s<8, 4>(kp, lds, grid, S, qf32, vec, s); break;
+    case 16: e = go_refined_s<16, 2>(kp, lds, grid, S, qf32, vec, s); break;
     default: e = hipErrorInvalidValue; break;
   }
   timing_end(K_ASSIGN_REFINED);
@@ -591,24 +754,21 @@ hipError_t launch_assign_plain(const AssignArgs& a, hipStream_t s, int n_cu) {
   kp.labels = a.labels;
   const bool qf32 = a.dtype == VQNNF_F32;
   const bool vec = rows_aligned(a, qf32 ? 4 : 2);
-  const size_t group_bytes = (size_t)g.e_f32 * g.kb * 64 * 4;
-  const size_t all_bytes = group_bytes * kp.n_groups;
-  kp.resident = all_bytes <= kResidentLds;
-  const size_t lds = kp.resident ? all_bytes : group_bytes;
-  const int NB = g.kb <= 8 ? 4 : 2;
-  const int tile_px = kWPB * NB * 16;
+  const size_t lds = 2 * (size_t)g.e_f32 * g.kb * 64 * 4;
+  const int NB = pick_nb(g.kb);
+  const int64_t tile_px = (int64_t)kWPB * NB * 16;
   kp.n_tiles = (a.n_pix + tile_px - 1) / tile_px;
-  int grid = (int)std::min<int64_t>(kp.n_tiles, kp.resident ? (int64_t)n_cu * 8 : kp.n_tiles);
+  const int grid = (int)std::min<int64_t>(kp.n_tiles, (int64_t)n_cu);
   timing_begin(K_ASSIGN_PLAIN);
   hipError_t e;
   const int E = g.e_f32;
   switch (g.kb) {
-    case 1: e = go_plain_s<1, 4, kWPB>(kp, lds, grid, E, qf32, vec, s); break;
-    case 2: e = go_plain_s<2, 4, kWPB>(kp, lds, grid, E, qf32, vec, s); break;
-    case 3: e = go_plain_s<3, 4, kWPB>(kp, lds, grid, E, qf32, vec, s); break;
-    case 4: e = go_plain_s<4, 4, kWPB>(kp, lds, grid, E, qf32, vec, s); break;
-    case 8: e = go_plain_s<8, 4, kWPB>(kp, lds, grid, E, qf32, vec, s); break;
-    case 16: e = go_plain_s<16, 2, kWPB>(kp, lds, grid, E, qf32, vec, s); break;
+    case 1: e = go_plain_s<1, 4>(kp, lds, grid, E, qf32, vec, s); break;
+    case 2: e = go_plain_s<2, 4>(kp, lds, grid, E, qf32, vec, s); break;
+    case 3: e = go_plain_s<3, 4>(kp, lds, grid, E, qf32, vec, s); break;
+    case 4: e = go_plain_s<4, 4>(kp, lds, grid, E, qf32, vec, s); break;
+    case 8: e = go_plain_s<8, 4>(kp, lds, grid, E, qf32, vec, s); break;
+    case 16: e = go_plain_s<16, 2>(kp, lds, grid, E, qf32, vec, s); break;
     default: e = hipErrorInvalidValue; break;
   }
   timing_end(K_ASSIGN_PLAIN);
@@ -623,17 +783,23 @@ hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu) {
   rp.D = a.D;
   rp.k = t.k;
   rp.mask_words = (t.geom.kpad + 31) / 32;
-  rp.qf32 = a.dtype == VQNNF_F32;
   rp.codebook = t.d_codebook;
   rp.wl_count = a.wl_count;
   rp.wl_pix = a.wl_pix;
   rp.wl_mask = a.wl_mask;
   rp.labels = a.labels;
+  const bool qf32 = a.dtype == VQNNF_F32;
+  const bool vec = rows_aligned(a, qf32 ? 4 : 2) && (a.D % 4 == 0);
   int grid = n_cu * 4;
   timing_begin(K_RESCORE);
-  hipLaunchKernelGGL(rescore_kernel, dim3(grid), dim3(256), 0, s, rp);
+  if (qf32) {
+    if (vec) hipLaunchKernelGGL((rescore_kernel<true, true>), dim3(grid), dim3(256), 0, s, rp);
+    else hipLaunchKernelGGL((rescore_kernel<true, false>), dim3(grid), dim3(256), 0, s, rp);
+  } else {
+    if (vec) hipLaunchKernelGGL((rescore_kernel<false, true>), dim3(grid), dim3(256), 0, s, rp);
+    else hipLaunchKernelGGL((rescore_kernel<false, false>), dim3(grid), dim3(256), 0, s, rp);
+  }
   timing_end(K_RESCORE);
   return hipGetLastError();
 }
-
 }  // namespace vqnnf

@@ -69,6 +69,7 @@ struct vqnnf_ctx {
   Buffer wl_mask;      // u32 [n_pix][mask_words]
   Buffer int_side;     // integral side arrays
   Buffer int_p;        // integral image for the integral score path
+  Buffer partials;     // per channel group partial sums of the on-chip score
   // timing
   bool timing = false;
   std::vector<TimingRecord> pending;
@@ -448,7 +449,8 @@ void vqnnf_ctx_destroy(vqnnf_ctx* c) {
   if (!c || c->magic != kCtxMagic) return;
   if (c->has_device) {
     hipStreamSynchronize(c->stream);
-    Buffer* bs[] = {&c->control, &c->labels, &c->wl_pix, &c->wl_mask, &c->int_side, &c->int_p};
+    Buffer* bs[] = {&c->control, &c->labels, &c->wl_pix, &c->wl_mask, &c->int_side, &c->int_p,
+                    &c->partials};
     for (Buffer* b : bs)
       if (b->p) hipFree(b->p);
     for (auto& r : c->pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
@@ -623,6 +625,7 @@ static vqnnf_status score_common(vqnnf_ctx* c, const vqnnf_template* t, const ui
   a.W = W;
   a.heatmap = heatmap;
   a.best = (unsigned long long*)c->control.p;
+  a.partials = c->partials.p;
   if (!zeroed) HIP_TRY(launch_zero_u64(a.best, c->stream));
   if (labels) {
     size_t lds = 0;
@@ -642,9 +645,11 @@ vqnnf_status vqnnf_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* l
   if (!fused_supported(t->t))
     return fail(VQNNF_ENOTSUP, "on-chip scoring needs the full-window + g x g grid bank (g <= 4) "
                 "within the LDS budget; use vqnnf_filter + vqnnf_score_integral");
-  if ((s = check_cap(c, {{&c->control, 64}}))) return s;
+  const size_t pb = fused_partial_bytes(t->t, H, W);
+  if ((s = check_cap(c, {{&c->control, 64}, {&c->partials, pb}}))) return s;
   if ((s = need_device(c))) return s;
   if ((s = ensure(c, c->control, 64, "control block"))) return s;
+  if ((s = ensure(c, c->partials, pb, "score partial sums"))) return s;
   HookScope hs(c);
   return score_common(c, t, labels, nullptr, H, W, heatmap, best_xy, best_score, false);
 }
@@ -675,12 +680,14 @@ vqnnf_status vqnnf_match(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap
   const int64_t R = (q->H + kIntTile - 1) / kIntTile, S = (q->W + kIntTile - 1) / kIntTile;
   size_t side = fused ? 0 : (size_t)((int64_t)q->H * S + R * q->W + R * S) * k * 4;
   size_t pbytes = fused ? 0 : (size_t)(q->H + 1) * (q->W + 1) * k * 4;
+  size_t partb = fused ? fused_partial_bytes(t->t, q->H, q->W) : 0;
   if ((s = check_cap(c, {{&c->control, 64}, {&c->labels, (size_t)n},
                          {&c->wl_pix, prec ? (size_t)n * 4 : 0},
                          {&c->wl_mask, prec ? (size_t)n * 4 * mask_words(t->t) : 0},
-                         {&c->int_side, side}, {&c->int_p, pbytes}})))
+                         {&c->int_side, side}, {&c->int_p, pbytes}, {&c->partials, partb}})))
     return s;
   if ((s = assign_scratch(c, t, n, prec, true))) return s;
+  if (fused && (s = ensure(c, c->partials, partb, "score partial sums"))) return s;
   if (!fused) {
     if ((s = ensure(c, c->int_side, side, "integral-image side arrays"))) return s;
     if ((s = ensure(c, c->int_p, pbytes, "integral image"))) return s;

@@ -131,17 +131,20 @@ struct ScoreArgs {
   int H, W;
   float* heatmap;
   unsigned long long* best;    // packed (orderable score, ~index), must be 0
+  void* partials;              // on-chip path: per channel group partial sums
 };
 hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out);
 hipError_t launch_score_integral(const ScoreArgs& a, hipStream_t s);
 // True when the on-chip score kernel can take this template's bank.
 bool fused_supported(const DeviceTemplate& t);
+// Scratch bytes of the on-chip path's per-channel-group partial sums.
+size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
 
 // Kernel-name registry for timing.
 enum KernelId {
   K_FILL = 0, K_ASSIGN_PLAIN, K_ASSIGN_REFINED, K_RESCORE, K_INT_EDGE, K_INT_PREFIX,
-  K_INT_MAIN, K_SCORE_FUSED, K_SCORE_INTEGRAL, K_COUNT
+  K_INT_MAIN, K_SCORE_FUSED, K_SCORE_COMBINE, K_SCORE_INTEGRAL, K_COUNT
 };
 const char* kernel_name(int id);
 

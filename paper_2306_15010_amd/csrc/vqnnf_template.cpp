@@ -188,10 +188,14 @@ AssignGeom make_assign_geom(int k, int D) {
   if (g.kb > 8) g.kb = 16;
   g.kpad = 16 * g.kb;
   int d32 = ((D + 31) / 32) * 32;
-  g.s_bf16 = (d32 % 128 == 0) ? 4 : (d32 % 64 == 0) ? 2 : 1;
-  g.d_pad_bf16 = d32;
+  // one K-step (32 elements) per load group: with the next group's query
+  // and codebook fragments in flight, larger groups overflow the register
+  // budget of 8 waves per CU
+  g.s_bf16 = 1;
+  // an even number of groups: the kernel alternates two query buffers
+  g.d_pad_bf16 = ((D + 63) / 64) * 64;
   int d16 = ((D + 15) / 16) * 16;
-  g.e_f32 = (d16 % 32 == 0) ? 8 : 4;
+  g.e_f32 = (g.kb < 8 && d16 % 32 == 0) ? 8 : 4;
   g.d_pad_f32 = d16;
   return g;
 }
@@ -223,7 +227,7 @@ BoundCoef make_bound(const DeviceTemplate& t, const std::vector<float>& hi,
                      const std::vector<float>& lo, const std::vector<float>& cn32, bool f32_query) {
   const int D = t.D, k = t.k;
   const double u = 0x1.0p-23;  // per-addend relative error allowed to the accumulator
-  const double n_add = (double)(f32_query ? 3 : 2) * t.geom.d_pad_bf16 + 1.0;
+  const double n_add = (double)(f32_query ? 3 : 2) * t.geom.d_pad_bf16;
   const double gam = n_add * u / (1.0 - n_add * u);
   const double u64 = 0x1.0p-53;
   const double gam64 = (D + 2) * u64 / (1.0 - (D + 2) * u64);
@@ -248,8 +252,11 @@ BoundCoef make_bound(const DeviceTemplate& t, const std::vector<float>& hi,
     double cn = std::sqrt(cn2) * slack, rn = std::sqrt(r2) * slack;
     double an = std::sqrt(a2) * slack, lon = std::sqrt(lo2) * slack;
     double e_norm = std::fabs((double)cn32[j] - cn2) + (D + 2) * 0x1.0p-52 * cn2;
-    double a0j = e_norm + gam * std::fabs((double)cn32[j]);
-    double a1j = 2.0 * (qfac * rn + lofac * lon + rhofac * cn) + 2.0 * gam * pfac * an;
+    // the products accumulate from zero (gamma bounds their rounding); the
+    // FP32 norm is added once at the end (one more rounding of |s_j|)
+    double a0j = e_norm + 0x1.0p-23 * std::fabs((double)cn32[j]);
+    double a1j = 2.0 * (qfac * rn + lofac * lon + rhofac * cn) + 2.0 * gam * pfac * an +
+                 0x1.0p-23 * 2.0 * (1.0 + 2.0 * gam) * pfac * an;
     A0 = std::max(A0, a0j);
     A1 = std::max(A1, a1j);
     cmax = std::max(cmax, cn);
