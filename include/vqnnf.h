@@ -73,7 +73,8 @@ typedef struct {
   const void* data;            /* see each call for host/device            */
   int32_t dtype;               /* vqnnf_dtype                               */
   int32_t H, W, D;             /* rows, columns, feature dimension          */
-  int64_t pixel_stride;        /* elements between pixels; 0 means D        */
+  int64_t pixel_stride;        /* elements between pixels; 0 means D; one
+                                  pixel row is at most 4 MiB (else EINVAL) */
   const float* channel_scale;  /* FP8 only: host float[D]; else NULL        */
 } vqnnf_fmap;
 

@@ -88,12 +88,13 @@ struct KParams {
 
 // Loads NE consecutive query elements of one pixel starting at element d0,
 // zero beyond D.  QF32: values are floats; else BF16 bit patterns widened.
-template <bool QF32, bool VEC, int NE>
+// VEC: 16-byte aligned rows; FULL: the caller guarantees d0 + NE <= D.
+template <bool QF32, bool VEC, int NE, bool FULL = false>
 __device__ __forceinline__ void load_query(const void* q, int64_t off, int d0, int D,
                                            uint32_t (&out)[QF32 ? NE : NE / 2]) {
   if (QF32) {
     const float* p = (const float*)q + off + d0;
-    if (VEC && d0 + NE <= D) {
+    if (VEC && (FULL || d0 + NE <= D)) {
 #pragma unroll
       for (int i = 0; i < NE / 4; ++i) {
         uint4 v = *(const uint4*)(p + 4 * i);
@@ -105,7 +106,7 @@ __device__ __forceinline__ void load_query(const void* q, int64_t off, int d0, i
     }
   } else {
     const uint16_t* p = (const uint16_t*)q + off + d0;
-    if (VEC && d0 + NE <= D) {
+    if (VEC && (FULL || d0 + NE <= D)) {
       if (NE % 8 == 0) {
 #pragma unroll
         for (int i = 0; i < NE / 8; ++i) {
@@ -150,40 +151,63 @@ __device__ __forceinline__ void merge_top2(float& v1, int& j1, float& v2, float 
 
 // ============================================================ BF16 refined
 // Template parameters: KB codeword blocks of 16, NB pixel blocks of 16 per
-// wave, S K-steps (of 32 elements) per load group, QF32: FP32-stored query
-// (hi/lo split in registers), VEC: 16-byte aligned rows.
+// wave, QF32: FP32-stored query (hi/lo split in registers), FAST: 16-byte
+// aligned rows and D a multiple of 64 (every load group is full, no bounds
+// checks).
 //
-// A block of 8 waves owns tiles of 8*NB*16 pixels and walks the load groups
-// of D.  The codebook fragments of group g+1 are fetched into registers and
-// the query elements of group g+1 are requested while group g is multiplied;
-// the fragments are written to the other half of a double-buffered LDS
-// stage, so one barrier per group suffices.  Blocks are persistent over
-// tiles, and the prefetch runs across tile boundaries.
+// A block of 8 waves owns tiles of 8*NB*16 pixels and walks D in load groups
+// of 32 elements (one K-step); the group count is even.  Work is a flat
+// stream of (tile, group) steps.  Step s:
+//   wait for the codebook group of step s to land in LDS, barrier;
+//   start the direct global->LDS copy of group s+1 into the other stage;
+//   multiply group s (codebook from LDS, query from registers);
+//   at the end of a tile: epilogue (argmin, bound, worklist);
+//   request the query elements of step s+2 into the register buffer just
+//   consumed (two buffers: even and odd groups).
+// Memory counters drain in issue order, so the wait for the codebook copy of
+// step s leaves exactly the query loads of step s+1 outstanding.
 constexpr int kWPB = 8;
 
-// Work of one block is a flat stream of (tile, group) steps; the query
-// elements of step s+2 are requested while step s is multiplied, alternating
-// between two register buffers (even and odd steps).
 struct StepCursor {
   int64_t tile;
   int gi;
 };
 
-template <int KB, int NB, int S, bool QF32, bool VEC>
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Raw buffer resource over [base, base + 4 GiB): stride 0, 32-bit data
+// format, so a load's address is base + voffset + soffset and the uniform part
+// of every address stays in scalar registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
+}
+
+// s_waitcnt with only the vector-memory counter limited to N (gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt at their no-wait maxima).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+template <int KB, int NB, bool QF32, bool FAST>
 __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
-  extern __shared__ uint4 lds[];
   constexpr int NT = kWPB * 64;
-  constexpr int GF = S * 2 * KB * 64;              // uint4 per load group
-  constexpr int CPT = (GF + NT - 1) / NT;          // staged per thread
-  constexpr int NEL = 8 * S;                       // elements per lane per group
+  constexpr int GF = 2 * KB * 64;                  // uint4 per load group (hi + lo)
+  constexpr int CPT = (GF + NT - 1) / NT;          // copies per thread per group
+  constexpr int NEL = 8;                           // elements per lane per group
   constexpr int QW = QF32 ? NEL : NEL / 2;         // 32-bit words per lane per group
+  constexpr int QN = FAST ? NB * (QF32 ? 2 : 1) : 0;  // vector loads per query request
   constexpr int MW = (KB + 1) / 2;                 // candidate mask words
+  constexpr int EB = QF32 ? 4 : 2;                 // bytes per query element
+  // stages padded to whole copies (the padding receives duplicate data)
+  __shared__ uint4 st0[CPT * NT], st1[CPT * NT];
+  __shared__ float cn_s[16 * KB];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n = lane & 15, g = lane >> 4;
-  const uint4* frag = (const uint4*)p.frag;
   const int ngr = p.n_groups;
-  constexpr int64_t TILE = kWPB * NB * 16;
+  constexpr int TILE = kWPB * NB * 16;
   if ((int64_t)blockIdx.x >= p.n_tiles) return;
 
   auto advance = [&](StepCursor c) {
@@ -193,26 +217,65 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
     }
     return c;
   };
-  auto pix_off = [&](int64_t tl, int nb) {
-    int64_t pix = tl * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
-    if (pix >= p.n_pix) pix = p.n_pix - 1;
-    return pix * p.stride;
-  };
-  uint4 cbr[CPT];
-  uint32_t qa[NB][QW], qb[NB][QW];
-  auto load_cb = [&](int gi) {
-    const uint4* src = frag + (int64_t)gi * GF;
+  // every wave copies its 1 KiB slices of the group; lane l writes 16 bytes
+  // at slice + 16*l.  Issued unconditionally so that the memory counters
+  // advance by the same amount on every path.
+  const __amdgpu_buffer_rsrc_t cb_rs = raw_rsrc(p.frag);
+  auto dma_cb = [&](int gi, uint4* stage) {
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
-      const int idx = threadIdx.x + i * NT;
-      if (idx < GF) cbr[i] = src[idx];
+      const int base = i * NT + wave * 64;
+      const int sb = base < GF ? base : base % GF;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(cb_rs, (lds_void_t*)(stage + base), 16, lane * 16,
+                                               (gi * GF + sb) * 16, 0, 0);
     }
   };
-  auto load_q = [&](StepCursor c, uint32_t (&dst)[NB][QW]) {
-    if (c.tile >= p.n_tiles) return;
-    const int d0 = c.gi * 32 * S + NEL * g;
+  // byte offset of this lane's pixel nb inside a tile, clamped to the last
+  // pixel of the map (a past-the-end request reads valid memory and is never
+  // used)
+  uint32_t qoff[NB];
+  auto set_tile = [&](int64_t tl) {
+    const int64_t t = tl < p.n_tiles ? tl : (int64_t)blockIdx.x;
+    const int64_t first = t * TILE;
+    const int64_t lim = p.n_pix - 1 - first;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) load_query<QF32, VEC, NEL>(p.q, pix_off(c.tile, nb), d0, p.D, dst[nb]);
+    for (int nb = 0; nb < NB; ++nb) {
+      int64_t px = (int64_t)wave * NB * 16 + 16 * nb + n;
+      px = px < lim ? px : lim;
+      qoff[nb] = (uint32_t)(px * p.stride * EB) + (uint32_t)(NEL * g * EB);
+    }
+    return (const char*)p.q + first * p.stride * EB;
+  };
+  uint32_t qa[NB][QW], qb[NB][QW];
+  // query elements of group gi for the tile whose base set_tile returned
+  auto load_q = [&](const char* tb, int gi, uint32_t (&dst)[NB][QW]) {
+    if (FAST) {
+      const __amdgpu_buffer_rsrc_t rs = raw_rsrc(tb);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int i = 0; i < QW / 4; ++i) {
+          const uint4 v = __builtin_bit_cast(
+              uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, qoff[nb] + 16 * i, gi * 32 * EB, 0));
+          dst[nb][4 * i] = v.x; dst[nb][4 * i + 1] = v.y;
+          dst[nb][4 * i + 2] = v.z; dst[nb][4 * i + 3] = v.w;
+        }
+    } else {
+      // element loads with bounds checks (D not a multiple of 64 or
+      // unaligned rows), relative to the pixel row start
+      const int d0 = gi * 32 + NEL * g;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int64_t row = (int64_t)(qoff[nb] - (uint32_t)(NEL * g * EB)) / EB;
+        load_query<QF32, false, NEL>(tb, row, d0, p.D, dst[nb]);
+      }
+    }
+  };
+  // the codebook copy of the current step has landed once at most the query
+  // loads of the next step are outstanding
+  auto wait_stage = [&]() {
+    if (QN > 0) wait_vm<QN>();
+    else wait_vm<0>();
   };
 
   f32x4_t acc[KB][NB];
@@ -226,51 +289,46 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
     for (int nb = 0; nb < NB; ++nb) qn2[nb] = 0.f;
   };
 
-  // multiply-accumulate of one group from the LDS stage and a query buffer
+  // multiply-accumulate of one group from an LDS stage and a query buffer
   auto compute = [&](const uint4* stage, uint32_t (&cur)[NB][QW]) {
+    uint4 bhi[NB], blo[NB];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      uint4 bhi[NB], blo[NB];
+    for (int nb = 0; nb < NB; ++nb) {
+      if (QF32) {
+        uint32_t h[8], l[8];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        if (QF32) {
-          uint32_t h[8], l[8];
+        for (int i = 0; i < 8; ++i) {
+          const float x = __uint_as_float(cur[nb][i]);
+          qn2[nb] = fmaf(x, x, qn2[nb]);
+          const uint32_t hb = f32_to_bf16_rne(x);
+          const float r = x - bf16_bits_to_f32(hb);
+          h[i] = hb;
+          l[i] = f32_to_bf16_rne(r);
+        }
+        bhi[nb] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                             h[6] | (h[7] << 16));
+        blo[nb] = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16),
+                             l[6] | (l[7] << 16));
+      } else {
+        const uint32_t ws[4] = {cur[nb][0], cur[nb][1], cur[nb][2], cur[nb][3]};
+        bhi[nb] = make_uint4(ws[0], ws[1], ws[2], ws[3]);
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const float x = __uint_as_float(cur[nb][8 * s + i]);
-            qn2[nb] = fmaf(x, x, qn2[nb]);
-            const uint32_t hb = f32_to_bf16_rne(x);
-            const float r = x - bf16_bits_to_f32(hb);
-            h[i] = hb;
-            l[i] = f32_to_bf16_rne(r);
-          }
-          bhi[nb] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
-                               h[6] | (h[7] << 16));
-          blo[nb] = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16),
-                               l[6] | (l[7] << 16));
-        } else {
-          const uint32_t w0 = cur[nb][4 * s], w1 = cur[nb][4 * s + 1];
-          const uint32_t w2 = cur[nb][4 * s + 2], w3 = cur[nb][4 * s + 3];
-          bhi[nb] = make_uint4(w0, w1, w2, w3);
-          const uint32_t ws[4] = {w0, w1, w2, w3};
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float lo = __uint_as_float(ws[i] << 16), hi = __uint_as_float(ws[i] & 0xFFFF0000u);
-            qn2[nb] = fmaf(lo, lo, qn2[nb]);
-            qn2[nb] = fmaf(hi, hi, qn2[nb]);
-          }
+        for (int i = 0; i < 4; ++i) {
+          const float lo = __uint_as_float(ws[i] << 16), hi = __uint_as_float(ws[i] & 0xFFFF0000u);
+          qn2[nb] = fmaf(lo, lo, qn2[nb]);
+          qn2[nb] = fmaf(hi, hi, qn2[nb]);
         }
       }
+    }
 #pragma unroll
-      for (int mb = 0; mb < KB; ++mb) {
-        const uint4 ahi = stage[((s * 2 + 0) * KB + mb) * 64 + lane];
-        const uint4 alo = stage[((s * 2 + 1) * KB + mb) * 64 + lane];
+    for (int mb = 0; mb < KB; ++mb) {
+      const uint4 ahi = stage[mb * 64 + lane];
+      const uint4 alo = stage[(KB + mb) * 64 + lane];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          acc[mb][nb] = mfma_bf16(ahi, bhi[nb], acc[mb][nb]);
-          acc[mb][nb] = mfma_bf16(alo, bhi[nb], acc[mb][nb]);
-          if (QF32) acc[mb][nb] = mfma_bf16(ahi, blo[nb], acc[mb][nb]);
-        }
+      for (int nb = 0; nb < NB; ++nb) {
+        acc[mb][nb] = mfma_bf16(ahi, bhi[nb], acc[mb][nb]);
+        acc[mb][nb] = mfma_bf16(alo, bhi[nb], acc[mb][nb]);
+        if (QF32) acc[mb][nb] = mfma_bf16(ahi, blo[nb], acc[mb][nb]);
       }
     }
   };
@@ -278,19 +336,18 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
   // epilogue of a finished tile: s_j = ||c_j||^2 + (-2 q.c_j), the norm
   // added once after the products were accumulated from zero
   auto finish = [&](int64_t tile) {
-    float cn[KB][4];
 #pragma unroll
     for (int mb = 0; mb < KB; ++mb) {
-      const f32x4_t c0 = *(const f32x4_t*)(p.cnorm + 16 * mb + 4 * g);
+      const f32x4_t c0 = *(const f32x4_t*)(cn_s + 16 * mb + 4 * g);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) cn[mb][i] = c0[i];
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[mb][nb][i] = c0[i] + acc[mb][nb][i];
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-#pragma unroll
-      for (int mb = 0; mb < KB; ++mb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[mb][nb][i] = cn[mb][i] + acc[mb][nb][i];
+      // best (first index on ties) and second-best score of this lane's
+      // codewords, in ascending index order, without branches
       float v1 = 3.4e38f, v2 = 3.4e38f;
       int j1 = 0;
 #pragma unroll
@@ -298,9 +355,10 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const float v = acc[mb][nb][i];
-          const int j = 16 * mb + 4 * g + i;
-          if (v < v1) { v2 = v1; v1 = v; j1 = j; }
-          else if (v < v2) { v2 = v; }
+          const bool better = v < v1;
+          v2 = fminf(v2, fmaxf(v1, v));
+          j1 = better ? 16 * mb + 4 * g + i : j1;
+          v1 = better ? v : v1;
         }
       float q2 = qn2[nb];
 #pragma unroll
@@ -346,40 +404,44 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
     }
   };
 
-  // groups per tile are even (D is padded to a multiple of 64), so buffer
-  // qa always holds even groups and qb odd groups, across tiles too
-  StepCursor c0{(int64_t)blockIdx.x, 0};
-  load_cb(0);
-  load_q(c0, qa);
-  load_q(advance(c0), qb);
-  int buf = 0;
+  for (int i = threadIdx.x; i < 16 * KB; i += NT) cn_s[i] = p.cnorm[i];
+  // prologue: group 0 of the first tile in stage st0, its query elements in
+  // qa and those of group 1 in qb
+  const char* tb = set_tile(blockIdx.x);
+  dma_cb(0, st0);
+  load_q(tb, 0, qa);
+  load_q(tb, 1, qb);
+  wait_vm<0>();
+  // groups per tile are even, so even groups use stage st0 and buffer qa,
+  // odd groups st1 and qb, across tiles too
   for (int64_t tile = blockIdx.x; tile < p.n_tiles; tile += gridDim.x) {
     reset();
+    const char* tb_next = tb;
     for (int gi = 0; gi < ngr; gi += 2) {
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const StepCursor cur{tile, gi + half};
-        uint4* stage = lds + buf * GF;
-#pragma unroll
-        for (int i = 0; i < CPT; ++i) {
-          const int idx = threadIdx.x + i * NT;
-          if (idx < GF) stage[idx] = cbr[i];
-        }
+      const bool last = gi + 2 == ngr;
+      {  // even group gi; requests group gi + 2 (or group 0 of the next tile)
+        wait_stage();
         __syncthreads();
-        const StepCursor nx = advance(cur);
-        if (nx.tile < p.n_tiles) load_cb(nx.gi);
-        if (half == 0) {
-          compute(stage, qa);
-          load_q(advance(nx), qa);
-        } else {
-          compute(stage, qb);
-          load_q(advance(nx), qb);
-        }
-        buf ^= 1;
+        dma_cb(gi + 1, st1);
+        __builtin_amdgcn_sched_barrier(0);  // the copy stays ahead of later loads
+        compute(st0, qa);
+        if (last) tb_next = set_tile(tile + gridDim.x);
+        load_q(last ? tb_next : tb, last ? 0 : gi + 2, qa);
+      }
+      {  // odd group gi + 1; requests group gi + 3 (or group 1 of the next tile)
+        wait_stage();
+        __syncthreads();
+        dma_cb(last ? 0 : gi + 2, st0);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(st1, qb);
+        if (last) finish(tile);
+        load_q(last ? tb_next : tb, last ? 1 : gi + 3, qb);
       }
     }
-    finish(tile);
+    tb = tb_next;
   }
+  // no copy into LDS may still be in flight when the workgroup retires
+  wait_vm<0>();
 }
 
 // ============================================================ FP32 plain
@@ -642,30 +704,18 @@ bool rows_aligned(const AssignArgs& a, int elem_bytes) {
   return (base % 16 == 0) && ((a.stride * elem_bytes) % 16 == 0);
 }
 
-template <int KB, int NB, int S, bool QF32, bool VEC>
-hipError_t go_refined(const KParams& kp, size_t lds, int grid, hipStream_t s) {
-  auto kern = assign_refined_kernel<KB, NB, S, QF32, VEC>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kWPB * 64), lds, s, kp);
+template <int KB, int NB, bool QF32, bool FAST>
+hipError_t go_refined(const KParams& kp, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((assign_refined_kernel<KB, NB, QF32, FAST>), dim3(grid), dim3(kWPB * 64), 0, s, kp);
   return hipGetLastError();
 }
 
-template <int KB, int NB, int S, bool QF32>
-hipError_t go_refined_v(const KParams& kp, size_t lds, int grid, bool vec, hipStream_t s) {
-  return vec ? go_refined<KB, NB, S, QF32, true>(kp, lds, grid, s)
-             : go_refined<KB, NB, S, QF32, false>(kp, lds, grid, s);
-}
-
 template <int KB, int NB>
-hipError_t go_refined_s(const KParams& kp, size_t lds, int grid, int S, bool qf32, bool vec,
-                        hipStream_t s) {
-  // load groups are one K-step (S == 1) for every geometry
-  if (S != 1) return hipErrorInvalidValue;
-  if (qf32) return go_refined_v<KB, NB, 1, true>(kp, lds, grid, vec, s);
-  return go_refined_v<KB, NB, 1, false>(kp, lds, grid, vec, s);
+hipError_t go_refined_q(const KParams& kp, int grid, bool qf32, bool fast, hipStream_t s) {
+  if (qf32) return fast ? go_refined<KB, NB, true, true>(kp, grid, s)
+                        : go_refined<KB, NB, true, false>(kp, grid, s);
+  return fast ? go_refined<KB, NB, false, true>(kp, grid, s)
+              : go_refined<KB, NB, false, false>(kp, grid, s);
 }
 
 template <int KB, int NB, int E, bool QF32, bool VEC>
@@ -718,22 +768,22 @@ hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu) {
   kp.a1 = a.bound.a1;
   kp.a2 = a.bound.a2;
   const bool qf32 = a.dtype == VQNNF_F32;
-  const bool vec = rows_aligned(a, qf32 ? 4 : 2);
-  const size_t lds = 2 * (size_t)g.s_bf16 * 2 * g.kb * 64 * 16;
+  // full load groups: D a multiple of two K-steps of 32, rows 16-byte aligned
+  const bool fast = rows_aligned(a, qf32 ? 4 : 2) && (a.D % 64 == 0) && g.s_bf16 == 1;
   const int NB = pick_nb(g.kb);
   const int64_t tile_px = (int64_t)kWPB * NB * 16;
   kp.n_tiles = (a.n_pix + tile_px - 1) / tile_px;
   const int grid = (int)std::min<int64_t>(kp.n_tiles, (int64_t)n_cu);
+  if (g.s_bf16 != 1 || kp.n_groups % 2 != 0) return hipErrorInvalidValue;
   timing_begin(K_ASSIGN_REFINED);
   hipError_t e;
-  const int S = g.s_bf16;
   switch (g.kb) {
-    case 1: e = go_refined_s<1, 4>(kp, lds, grid, S, qf32, vec, s); break;
-    case 2: e = go_refined_s<2, 4>(kp, lds, grid, S, qf32, vec, s); break;
-    case 3: e = go_refined_s<3, 4>(kp, lds, grid, S, qf32, vec, s); break;
-    case 4: e = go_refined_s<4, 4>(kp, lds, grid, S, qf32, vec, s); break;
-    case 8: e = go_refined_s<8, 4>(kp, lds, grid, S, qf32, vec, s); break;
-    case 16: e = go_refined_s<16, 2>(kp, lds, grid, S, qf32, vec, s); break;
+    case 1: e = go_refined_q<1, 4>(kp, grid, qf32, fast, s); break;
+    case 2: e = go_refined_q<2, 4>(kp, grid, qf32, fast, s); break;
+    case 3: e = go_refined_q<3, 4>(kp, grid, qf32, fast, s); break;
+    case 4: e = go_refined_q<4, 4>(kp, grid, qf32, fast, s); break;
+    case 8: e = go_refined_q<8, 4>(kp, grid, qf32, fast, s); break;
+    case 16: e = go_refined_q<16, 2>(kp, grid, qf32, fast, s); break;
     default: e = hipErrorInvalidValue; break;
   }
   timing_end(K_ASSIGN_REFINED);

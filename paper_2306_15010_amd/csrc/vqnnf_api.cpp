@@ -211,6 +211,8 @@ vqnnf_status check_map(const vqnnf_fmap* m, const char* what) {
   int64_t st = m->pixel_stride ? m->pixel_stride : m->D;
   if (st < m->D) return fail(VQNNF_EINVAL, "%s: pixel_stride %lld < D %d", what, (long long)st, m->D);
   if ((int64_t)m->H * m->W >= (1ll << 31)) return fail(VQNNF_EINVAL, "%s: H*W must be < 2^31", what);
+  if (st * (int64_t)dtype_size(m->dtype) > (1ll << 22))
+    return fail(VQNNF_EINVAL, "%s: a pixel row (pixel_stride * element size) must be <= 4 MiB", what);
   if (m->dtype == VQNNF_FP8_E4M3 && !m->channel_scale)
     return fail(VQNNF_EINVAL, "%s: FP8 map needs channel_scale", what);
   return ok();
