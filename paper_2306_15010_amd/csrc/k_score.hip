@@ -51,22 +51,63 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
+// Block-wide maximum of the keys (blockDim.x = 256), then one atomicMax per
+// block, skipped when the stored key is already larger: the key only grows,
+// so a stale read can only cost an unneeded atomic.
+__device__ __forceinline__ void block_max_to(unsigned long long key, unsigned long long* best) {
+  __shared__ unsigned long long wmax[4];
+  key = wave_max_u64(key);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long k = wmax[0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) k = wmax[i] > k ? wmax[i] : k;
+    if (k > __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(best, k);
+  }
+}
+
 // ================================================================ fused
-struct FusedParams {
+// One block owns a tile of up to kTXW x tyw windows and one group of kKG
+// channels.  LDS holds, per grid row-band b and per column c of the
+// txw + w - 1 columns the tile touches:
+//   Q[b][c]  the band's column histogram (channel pairs as packed u16,
+//            four pairs per 16-byte entry),
+//   H[b][c]  its prefix along the columns, H[b][c] = sum_{c' < c} Q[b][c'],
+// so the count of bin (a, b) of window x is H[b][x + X_{a+1}] - H[b][x + X_a]
+// and the full window is the sum of the bands' H[b][x + w] - H[b][x].
+// Per window row, two phases separated by barriers:
+//   1. one wave per (band, pair group) row rebuilds its prefix: lane s sums
+//      segment s (kSL columns, kept in registers), a DPP scan of the segment
+//      totals gives the offsets, the lane writes its segment of H;
+//   2. every thread scores one window against four channel pairs,
+//      accumulating sum_j min(T_j, C_j) with v_dot2_u32_u16, while the
+//      column threads move Q down to the next row (two labels per band and
+//      column change).
+// The integer sums of the group are written per window; a second kernel adds
+// the groups, forms eq. 2 and the argmax.
+constexpr int kSL = 7;                 // columns per prefix segment (odd: a wave's lanes hit distinct banks)
+constexpr int kNSeg = 53;              // segments per row (<= 64 lanes)
+constexpr int kHS = kSL * kNSeg;       // LDS row length in 16-byte entries
+constexpr int kColsMax = kHS - kSL;    // nseg = cols / kSL + 1 segments cover [0, cols]
+constexpr int kKG = 16;                // channels per block
+constexpr int kPQ = kKG / 8;           // 16-byte entries (four pairs) per column per band
+constexpr int kTXW = 256;              // windows per tile row
+constexpr int kST = 512;               // threads per block: kTXW windows x kPQ pair groups
+
+struct TileParams {
   const uint8_t* labels;
   int H, W;           // label map
   int w, h;           // template
   int ow, oh;         // heatmap
-  int kpad, kg;       // channels (padded) and channels per block (group)
-  int qs, hs;         // LDS row strides (dwords) of Q and H
+  int txw, tyw;       // windows per tile row (<= kTXW) and window rows per tile
+  int kpad;
   int xe[5], ye[5];
   const uint32_t* t16;  // [nf][kpad/2] template counts, u16 pairs
-  uint16_t* part;       // [n_groups][nf][oh*ow] sum_j min(T_j, C_j) per group
+  uint32_t* part;       // [n_groups][nacc][oh*ow] sums of min(T_j, C_j)
 };
 
-constexpr int kTYW = 32;    // window rows per tile
-constexpr int kFT = 1024;   // threads per block
-constexpr int kSEG = 8;     // columns per prefix segment
+typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
 
 // Inclusive prefix sum across the 64 lanes of a wave with DPP: row_shr 1, 2,
 // 4, 8 inside each row of 16 lanes, then row_bcast 15 and 31 carry the row
@@ -81,42 +122,50 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
-// Block (x tile of TXW windows, y tile of kTYW rows, channel group of KG
-// channels).  NP = kFT / TXW threads per window, each taking every NP-th
-// channel pair of the group.
-//
-// LDS per band b and channel quad q: Q[b][q][c] (four uint8 column counts),
-// the segment totals T[b][q][s] = sum of Q over the kSEG columns of segment s
-// (two packed u16 pairs), kept up to date by the vertical updates, and the
-// prefix H[b][pair][c].  Per window row: vertical update (Q and T) | scan of T
-// per (b, q) row -> segment offsets | write H = offset + running sum inside
-// the segment | evaluate windows.
-template <int G, int TXW, int KG>
-__global__ __launch_bounds__(kFT) void score_partial_kernel(FusedParams p) {
-  constexpr int NF = 1 + G * G;
-  constexpr int NP = kFT / TXW;
-  constexpr int KQ = KG / 4, KP = KG / 2;
-  extern __shared__ uint32_t sm[];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int x0 = blockIdx.x * TXW, y0 = blockIdx.y * kTYW;
-  const int grp = blockIdx.z;
-  const int j0 = grp * KG;                            // first channel of the group
-  const int txv = min(TXW, p.ow - x0), tyv = min(kTYW, p.oh - y0);
-  const int cols = txv + p.w - 1;
-  const int nseg = (cols + kSEG - 1) / kSEG;          // <= 64
-  uint32_t* Q = sm;                                   // [G][KQ][qs]
-  uint32_t* Hs = Q + G * KQ * p.qs;                   // [G][KP][hs]
-  uint32_t* segt = Hs + G * KP * p.hs;                // [G][KQ][64][2] totals
-  uint32_t* sego = segt + G * KQ * 64 * 2;            // [G][KQ][64][2] offsets
-  uint32_t* red = sego + G * KQ * 64 * 2;             // [NF][TXW]
+// Four packed pairs added as two 64-bit words: every 16-bit count stays below
+// 2^16, so no carry crosses a field.
+__device__ __forceinline__ uint4 add4(uint4 a, uint4 b) {
+  return __builtin_bit_cast(uint4, __builtin_bit_cast(u64x2_t, a) + __builtin_bit_cast(u64x2_t, b));
+}
+__device__ __forceinline__ uint32_t comp(uint4 v, int s) {
+  return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
+}
+__device__ __forceinline__ uint32_t min_dot(uint32_t c, uint32_t t, uint32_t acc) {
+  const u16x2_t m = __builtin_elementwise_min(__builtin_bit_cast(u16x2_t, c), __builtin_bit_cast(u16x2_t, t));
+  return __builtin_amdgcn_udot2(m, (u16x2_t){1, 1}, acc, false);
+}
 
-  for (int i = tid; i < G * KQ * p.qs; i += kFT) Q[i] = 0u;
-  for (int i = tid; i < NF * TXW; i += kFT) red[i] = 0u;
+// UNI: every bin has the same weight, so the bins share one accumulator
+// (accumulator 0: full window, 1: bins); otherwise one per filter.
+template <int G, bool UNI>
+__global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
+  constexpr int NF = 1 + G * G;
+  constexpr int NACC = UNI ? 2 : NF;
+  constexpr int NR = G * kPQ;                        // (band, pair group) rows
+  static_assert(NR <= kST / 64, "one wave per prefix row");
+  __shared__ uint4 Qs[NR][kHS];
+  __shared__ uint4 Hs[NR][kHS];
+  __shared__ uint32_t red[NACC][kTXW];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int x0 = blockIdx.x * p.txw, y0 = blockIdx.y * p.tyw;
+  const int grp = blockIdx.z, j0 = grp * kKG;
+  const int txv = min(p.txw, p.ow - x0), tyv = min(p.tyw, p.oh - y0);
+  const int cols = txv + p.w - 1;
+  const int nseg = cols / kSL + 1;                   // segments cover [0, cols]
+  const int64_t nwin = (int64_t)p.ow * p.oh;
+  uint32_t* Q32 = (uint32_t*)&Qs[0][0];
+  // channel jl of the group lives in row b*kPQ + jl/8, word (jl/2)%4, half jl%2
+  auto qword = [&](int b, int jl, int c) -> uint32_t* {
+    return Q32 + ((b * kPQ + (jl >> 3)) * kHS + c) * 4 + ((jl >> 1) & 3);
+  };
+
+  for (int i = tid; i < NR * kHS; i += kST) (&Qs[0][0])[i] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
-  // initial band histograms of the group's channels: items of 8 rows of one
-  // column, the 8 label loads issued together
+  // band histograms at the tile's first row: items of 8 rows of one column,
+  // the 8 label loads issued together
   const int nrc = (p.h + 7) / 8;
-  for (int i = tid; i < nrc * cols; i += kFT) {
+  for (int i = tid; i < nrc * cols; i += kST) {
     const int c = i % cols, r0 = (i / cols) * 8;
     int l8[8];
 #pragma unroll
@@ -127,42 +176,19 @@ __global__ __launch_bounds__(kFT) void score_partial_kernel(FusedParams p) {
     for (int r = 0; r < 8; ++r) {
       if (r0 + r >= p.h) break;
       while (r0 + r >= p.ye[b + 1]) ++b;
-      if ((unsigned)l8[r] < (unsigned)KG)
-        atomicAdd(&Q[(b * KQ + (l8[r] >> 2)) * p.qs + c], 1u << (8 * (l8[r] & 3)));
+      if ((unsigned)l8[r] < (unsigned)kKG) atomicAdd(qword(b, l8[r], c), 1u << (16 * (l8[r] & 1)));
     }
-  }
-  __syncthreads();
-  // initial segment totals
-  for (int it = tid; it < G * KQ * 64; it += kFT) {
-    const int bq = it % (G * KQ), seg = it / (G * KQ);
-    uint32_t r0 = 0u, r1 = 0u;
-    if (seg < nseg) {
-      const uint32_t* qrow = Q + bq * p.qs + seg * kSEG;
-#pragma unroll
-      for (int i = 0; i < kSEG; ++i) {
-        const uint32_t v = (seg * kSEG + i < cols) ? qrow[i] : 0u;
-        r0 += (v & 0xFFu) | ((v & 0xFF00u) << 8);
-        r1 += ((v >> 16) & 0xFFu) | ((v >> 8) & 0xFF0000u);
-      }
-    }
-    segt[(bq * 64 + seg) * 2] = r0;
-    segt[(bq * 64 + seg) * 2 + 1] = r1;
   }
 
-  const int xl = tid % TXW;
-  const int part = __builtin_amdgcn_readfirstlane(tid / TXW);   // uniform per wave
-  const int64_t nwin = (int64_t)p.ow * p.oh;
-  // template counts of this thread's channel pairs, in registers
-  constexpr int PPT = (KP + NP - 1) / NP;             // pairs per thread
-  uint32_t tcr[PPT][NF];
+  // scoring role: window xl of the tile, pair group pq (uniform per wave)
+  const int pq = wv & 1;
+  const int xl = (wv >> 1) * 64 + lane;
+  uint32_t T[NF][4];
 #pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int pl = part + NP * i;
+  for (int f = 0; f < NF; ++f)
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
-      tcr[i][f] = (pl < KP) ? p.t16[f * (p.kpad / 2) + j0 / 2 + pl] : 0u;
-  }
-  // labels entering / leaving each band at the next row step, prefetched
+    for (int s = 0; s < 4; ++s) T[f][s] = p.t16[f * (p.kpad / 2) + j0 / 2 + pq * 4 + s];
+  // labels leaving / entering each band at the next row step, prefetched
   int lo[G], li[G];
   auto fetch = [&](int ynext, int c) {
 #pragma unroll
@@ -171,193 +197,115 @@ __global__ __launch_bounds__(kFT) void score_partial_kernel(FusedParams p) {
       li[b] = (int)p.labels[(int64_t)(ynext - 1 + p.ye[b + 1]) * p.W + x0 + c] - j0;
     }
   };
-  // columns are owned by threads tid < cols (cols <= TXW + 254 < kFT)
   if (tyv > 1 && tid < cols) fetch(y0 + 1, tid);
 
+  uint32_t acc[NACC];
+  auto store_row = [&](int yy) {  // pair group 0 adds group 1's sums
+    const int64_t win = (int64_t)yy * p.ow + x0 + xl;
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) p.part[((int64_t)grp * NACC + a) * nwin + win] = acc[a] + red[a][xl];
+  };
   for (int dy = 0; dy < tyv; ++dy) {
     const int y = y0 + dy;
-    if (dy > 0 && tid < cols) {
-      const int c = tid, sg = c / kSEG;
+    __syncthreads();   // Q at row y complete; previous row's H and red consumed
+    // ---- phase 1: prefix of row wv, lane = segment
+    if (wv < NR) {
+      const int c0 = lane * kSL;
+      const bool act = lane < nseg;
+      uint4 loc[kSL];
+      uint4 run = make_uint4(0u, 0u, 0u, 0u);
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < kSL; ++i) {
+          loc[i] = run;
+          run = add4(run, Qs[wv][c0 + i]);
+        }
+      }
+      const uint4 inc = make_uint4(wave_incl_scan(run.x), wave_incl_scan(run.y), wave_incl_scan(run.z),
+                                   wave_incl_scan(run.w));
+      const uint4 off = make_uint4(inc.x - run.x, inc.y - run.y, inc.z - run.z, inc.w - run.w);
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < kSL; ++i) Hs[wv][c0 + i] = add4(off, loc[i]);
+      }
+    }
+    if (dy > 0 && pq == 0 && xl < txv) store_row(y - 1);
+    __syncthreads();   // H at row y complete
+    // ---- phase 2: score window xl against pairs 4*pq .. 4*pq + 3 of the group
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) acc[a] = 0u;
+    if (xl < txv) {
+      uint32_t full[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int b = 0; b < G; ++b) {
+        uint4 hv[G + 1];
+#pragma unroll
+        for (int a = 0; a <= G; ++a) hv[a] = Hs[b * kPQ + pq][xl + p.xe[a]];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+          for (int a = 0; a < G; ++a) {
+            const uint32_t bin = comp(hv[a + 1], s) - comp(hv[a], s);
+            const int ai = UNI ? 1 : 1 + b * G + a;
+            acc[ai] = min_dot(bin, T[1 + b * G + a][s], acc[ai]);
+          }
+          full[s] += comp(hv[G], s) - comp(hv[0], s);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[0] = min_dot(full[s], T[0][s], acc[0]);
+      if (pq == 1) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) red[a][xl] = acc[a];
+      }
+    }
+    // ---- vertical update of Q to row y + 1, then prefetch for row y + 2
+    if (dy + 1 < tyv && tid < cols) {
+      const int c = tid;
 #pragma unroll
       for (int b = 0; b < G; ++b) {
         if (lo[b] == li[b]) continue;
-        if ((unsigned)lo[b] < (unsigned)KG) {
-          const int q = lo[b] >> 2;
-          Q[(b * KQ + q) * p.qs + c] -= 1u << (8 * (lo[b] & 3));
-          atomicSub(&segt[((b * KQ + q) * 64 + sg) * 2 + ((lo[b] >> 1) & 1)], 1u << (16 * (lo[b] & 1)));
-        }
-        if ((unsigned)li[b] < (unsigned)KG) {
-          const int q = li[b] >> 2;
-          Q[(b * KQ + q) * p.qs + c] += 1u << (8 * (li[b] & 3));
-          atomicAdd(&segt[((b * KQ + q) * 64 + sg) * 2 + ((li[b] >> 1) & 1)], 1u << (16 * (li[b] & 1)));
-        }
+        if ((unsigned)lo[b] < (unsigned)kKG) atomicSub(qword(b, lo[b], c), 1u << (16 * (lo[b] & 1)));
+        if ((unsigned)li[b] < (unsigned)kKG) atomicAdd(qword(b, li[b], c), 1u << (16 * (li[b] & 1)));
       }
-    }
-    __syncthreads();
-    // ---- per (band, quad) row, one wave: exclusive scan of the segment
-    // totals -> offsets; entry `cols` of H receives the row total
-    for (int bq = wv; bq < G * KQ; bq += kFT / 64) {
-      const int b = bq / KQ, qq = bq % KQ;
-      const uint32_t t0 = lane < nseg ? segt[(bq * 64 + lane) * 2] : 0u;
-      const uint32_t t1 = lane < nseg ? segt[(bq * 64 + lane) * 2 + 1] : 0u;
-      const uint32_t i0 = wave_incl_scan(t0), i1 = wave_incl_scan(t1);
-      sego[(bq * 64 + lane) * 2] = i0 - t0;
-      sego[(bq * 64 + lane) * 2 + 1] = i1 - t1;
-      if (lane == nseg - 1) {
-        uint32_t* h0 = Hs + (b * KP + 2 * qq) * p.hs;
-        h0[cols] = i0;
-        h0[p.hs + cols] = i1;
-      }
-    }
-    __syncthreads();
-    // ---- H = segment offset + running sum inside the segment; consecutive
-    // lanes take different rows (odd row stride: no bank conflicts)
-    for (int it = tid; it < G * KQ * nseg; it += kFT) {
-      const int bq = it % (G * KQ), seg = it / (G * KQ);
-      const int b = bq / KQ, qq = bq % KQ;
-      const int c0 = seg * kSEG;
-      const uint32_t* qrow = Q + bq * p.qs + c0;
-      uint32_t* h0 = Hs + (b * KP + 2 * qq) * p.hs + c0;
-      uint32_t* h1 = h0 + p.hs;
-      uint32_t v[kSEG];
-#pragma unroll
-      for (int i = 0; i < kSEG; ++i) v[i] = (c0 + i < cols) ? qrow[i] : 0u;
-      uint32_t r0 = sego[(bq * 64 + seg) * 2], r1 = sego[(bq * 64 + seg) * 2 + 1];
-#pragma unroll
-      for (int i = 0; i < kSEG; ++i) {
-        h0[i] = r0;
-        h1[i] = r1;
-        r0 += (v[i] & 0xFFu) | ((v[i] & 0xFF00u) << 8);
-        r1 += ((v[i] >> 16) & 0xFFu) | ((v[i] >> 8) & 0xFF0000u);
-      }
-    }
-    __syncthreads();
-    // next row's labels are requested now and consumed after the evaluation
-    if (dy + 1 < tyv && tid < cols) fetch(y + 1, tid);
-    // ---- evaluate windows: thread (xl, part) takes every NP-th pair
-    uint32_t acc[NF];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) acc[f] = 0u;
-    if (xl < txv) {
-#pragma unroll
-      for (int i = 0; i < PPT; ++i) {
-        const int pl = part + NP * i;
-        if (pl >= KP) break;
-        uint32_t full = 0u;
-#pragma unroll
-        for (int b = 0; b < G; ++b) {
-          const uint32_t* hrow = Hs + (b * KP + pl) * p.hs + xl;
-          uint32_t hb[G + 1];
-#pragma unroll
-          for (int a = 0; a <= G; ++a) hb[a] = hrow[p.xe[a]];
-#pragma unroll
-          for (int a = 0; a < G; ++a)
-            acc[1 + b * G + a] = pk_min_add(acc[1 + b * G + a], hb[a + 1] - hb[a], tcr[i][1 + b * G + a]);
-          full += hb[G] - hb[0];
-        }
-        acc[0] = pk_min_add(acc[0], full, tcr[i][0]);
-      }
-    }
-    // ---- combine the NP parts and write the group's partial sums
-    if (part > 0 && xl < txv) {
-#pragma unroll
-      for (int f = 0; f < NF; ++f) atomicAdd(&red[f * TXW + xl], acc[f]);
-    }
-    __syncthreads();
-    if (part == 0 && xl < txv) {
-      const int64_t win = (int64_t)y * p.ow + x0 + xl;
-#pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        const uint32_t t = acc[f] + red[f * TXW + xl];
-        red[f * TXW + xl] = 0u;
-        p.part[((int64_t)grp * NF + f) * nwin + win] = (uint16_t)((t & 0xFFFFu) + (t >> 16));
-      }
+      if (dy + 2 < tyv) fetch(y + 2, c);
     }
   }
+  __syncthreads();
+  if (pq == 0 && xl < txv) store_row(y0 + tyv - 1);
 }
 
-// Sums the groups' partials, forms eq. 2 and the argmax.
+// Adds the groups' integer sums, forms eq. 2 and the argmax.
 struct CombineParams {
-  const uint16_t* part;
+  const uint32_t* part;
   int64_t nwin;
-  int ow, ngroups, nf;
-  float wt[17];
-  int area[17];
+  int ngroups;
+  float wt[17];       // per accumulator weight
+  int area2[17];      // per accumulator: twice the summed bin areas
   float* heatmap;
   unsigned long long* best;
 };
 
-// Eight windows per thread, 16-byte loads of the partial sums; the group
-// loop is unrolled so every load of a filter is in flight at once.
-template <int NF, int NG>
+template <int NACC>
 __global__ __launch_bounds__(256) void score_combine_kernel(CombineParams p) {
-  const int64_t w0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
+  const int64_t win = (int64_t)blockIdx.x * 256 + threadIdx.x;
   unsigned long long key = 0ull;
-  if (w0 < p.nwin) {
-    const int nv = (int)min((int64_t)8, p.nwin - w0);
-    const bool vec = (nv == 8) && ((p.nwin & 7) == 0);
-    float s[8];
+  if (win < p.nwin) {
+    uint32_t m[NACC];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s[i] = 0.f;
+    for (int a = 0; a < NACC; ++a) m[a] = 0u;
+    for (int g = 0; g < p.ngroups; ++g)
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      int mins[8];
+      for (int a = 0; a < NACC; ++a) m[a] += p.part[((int64_t)g * NACC + a) * p.nwin + win];
+    // sum_j |T_j - C_j| = 2A - 2 sum_j min(T_j, C_j), exact in integers
+    float s = 0.f;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) mins[i] = 0;
-      if (vec) {
-        uint4 v[NG];
-#pragma unroll
-        for (int g = 0; g < NG; ++g) v[g] = *(const uint4*)(p.part + ((int64_t)g * NF + f) * p.nwin + w0);
-#pragma unroll
-        for (int g = 0; g < NG; ++g) {
-          const uint32_t ws[4] = {v[g].x, v[g].y, v[g].z, v[g].w};
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            mins[2 * i] += (int)(ws[i] & 0xFFFFu);
-            mins[2 * i + 1] += (int)(ws[i] >> 16);
-          }
-        }
-      } else {
-        for (int g = 0; g < NG; ++g)
-          for (int i = 0; i < nv; ++i) mins[i] += p.part[((int64_t)g * NF + f) * p.nwin + w0 + i];
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) s[i] = fmaf(p.wt[f], (float)(2 * p.area[f] - 2 * mins[i]), s[i]);
-    }
-    for (int i = 0; i < nv; ++i) {
-      const float score = -s[i];
-      p.heatmap[w0 + i] = score;
-      const unsigned long long k2 = best_key(score, (uint32_t)(w0 + i));
-      key = k2 > key ? k2 : key;
-    }
+    for (int a = 0; a < NACC; ++a) s = fmaf(p.wt[a], (float)(p.area2[a] - 2 * (int)m[a]), s);
+    const float score = -s;
+    p.heatmap[win] = score;
+    key = best_key(score, (uint32_t)win);
   }
-  key = wave_max_u64(key);
-  if ((threadIdx.x & 63) == 0 && key) atomicMax(p.best, key);
-}
-
-template <int NF>
-hipError_t go_combine_nf(const CombineParams& cp, hipStream_t s) {
-  const dim3 grid((unsigned)((cp.nwin + 2047) / 2048)), blk(256);
-  switch (cp.ngroups) {
-    case 1: hipLaunchKernelGGL((score_combine_kernel<NF, 1>), grid, blk, 0, s, cp); break;
-    case 2: hipLaunchKernelGGL((score_combine_kernel<NF, 2>), grid, blk, 0, s, cp); break;
-    case 4: hipLaunchKernelGGL((score_combine_kernel<NF, 4>), grid, blk, 0, s, cp); break;
-    case 8: hipLaunchKernelGGL((score_combine_kernel<NF, 8>), grid, blk, 0, s, cp); break;
-    case 16: hipLaunchKernelGGL((score_combine_kernel<NF, 16>), grid, blk, 0, s, cp); break;
-    case 32: hipLaunchKernelGGL((score_combine_kernel<NF, 32>), grid, blk, 0, s, cp); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t go_combine(const CombineParams& cp, hipStream_t s) {
-  switch (cp.nf) {
-    case 2: return go_combine_nf<2>(cp, s);
-    case 5: return go_combine_nf<5>(cp, s);
-    case 10: return go_combine_nf<10>(cp, s);
-    case 17: return go_combine_nf<17>(cp, s);
-    default: return hipErrorInvalidValue;
-  }
+  block_max_to(key, p.best);
 }
 
 // ================================================================ integral
@@ -375,166 +323,160 @@ struct IntParams {
 __global__ __launch_bounds__(256) void score_integral_kernel(IntParams p) {
   const int lane = threadIdx.x & 63;
   const int64_t win = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (win >= (int64_t)p.ow * p.oh) return;
-  const int x = (int)(win % p.ow), y = (int)(win / p.ow);
-  const int64_t row = (int64_t)(p.W + 1) * p.k;
-  float s = 0.f;
-  for (int f = 0; f < p.nf; ++f) {
-    const int bx0 = p.boxes[4 * f], by0 = p.boxes[4 * f + 1];
-    const int bx1 = p.boxes[4 * f + 2], by1 = p.boxes[4 * f + 3];
-    const int32_t* p00 = p.P + (int64_t)(y + by0) * row + (int64_t)(x + bx0) * p.k;
-    const int32_t* p01 = p.P + (int64_t)(y + by0) * row + (int64_t)(x + bx1) * p.k;
-    const int32_t* p10 = p.P + (int64_t)(y + by1) * row + (int64_t)(x + bx0) * p.k;
-    const int32_t* p11 = p.P + (int64_t)(y + by1) * row + (int64_t)(x + bx1) * p.k;
-    int l1 = 0;
-    for (int j = lane; j < p.k; j += 64) {
-      const int c = p11[j] - p01[j] - p10[j] + p00[j];
-      const int d = p.counts[f * p.kpad + j] - c;
-      l1 += d < 0 ? -d : d;
-    }
+  unsigned long long key = 0ull;
+  if (win < (int64_t)p.ow * p.oh) {  // uniform per wave
+    const int x = (int)(win % p.ow), y = (int)(win / p.ow);
+    const int64_t row = (int64_t)(p.W + 1) * p.k;
+    float s = 0.f;
+    for (int f = 0; f < p.nf; ++f) {
+      const int bx0 = p.boxes[4 * f], by0 = p.boxes[4 * f + 1];
+      const int bx1 = p.boxes[4 * f + 2], by1 = p.boxes[4 * f + 3];
+      const int32_t* p00 = p.P + (int64_t)(y + by0) * row + (int64_t)(x + bx0) * p.k;
+      const int32_t* p01 = p.P + (int64_t)(y + by0) * row + (int64_t)(x + bx1) * p.k;
+      const int32_t* p10 = p.P + (int64_t)(y + by1) * row + (int64_t)(x + bx0) * p.k;
+      const int32_t* p11 = p.P + (int64_t)(y + by1) * row + (int64_t)(x + bx1) * p.k;
+      int l1 = 0;
+      for (int j = lane; j < p.k; j += 64) {
+        const int c = p11[j] - p01[j] - p10[j] + p00[j];
+        const int d = p.counts[f * p.kpad + j] - c;
+        l1 += d < 0 ? -d : d;
+      }
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) l1 += __shfl_xor(l1, m);
-    s = fmaf(p.weights[f], (float)l1, s);
+      for (int m = 32; m >= 1; m >>= 1) l1 += __shfl_xor(l1, m);
+      s = fmaf(p.weights[f], (float)l1, s);
+    }
+    if (lane == 0) {
+      const float score = -s;
+      p.heatmap[win] = score;
+      key = best_key(score, (uint32_t)win);
+    }
   }
-  if (lane == 0) {
-    const float score = -s;
-    p.heatmap[win] = score;
-    atomicMax(p.best, best_key(score, (uint32_t)win));
-  }
+  block_max_to(key, p.best);
 }
 
 // ================================================================ launchers
 namespace {
 
-struct FusedPlan {
+struct TilePlan {
   bool ok;
-  int txw, kg, qs, hs;
-  size_t lds;
+  bool uni;
+  int txw, tyw;
+  int nacc;
 };
 
-FusedPlan plan_fused(const DeviceTemplate& t) {
-  FusedPlan pl{};
+// Tiles are as wide as the LDS rows allow (at most kTXW windows, at least 32).
+TilePlan plan_tile(const DeviceTemplate& t) {
+  TilePlan pl{};
+  if (!t.grid.valid) return pl;
   const int G = t.grid.g;
+  if (G < 1 || G > 4 || t.geom.kpad % kKG) return pl;
   int maxband = 0;
   for (int b = 0; b < G; ++b) maxband = std::max(maxband, t.grid.ye[b + 1] - t.grid.ye[b]);
-  const int kpad = t.geom.kpad;
-  const int NF = 1 + G * G;
-  for (int txw = 256; txw >= 64; txw /= 2) {
-    const int colsmax = txw + t.w - 1;
-    if ((int64_t)maxband * colsmax >= 65536) continue;   // 16-bit prefix would overflow
-    if ((colsmax + kSEG - 1) / kSEG > 64) continue;       // segment totals scanned by one wave
-    // padded so the unrolled segment loads and stores stay in their rows
-    const int qs = ((colsmax + kSEG - 1) / kSEG * kSEG) | 1;
-    const int hs = ((colsmax + kSEG) / kSEG * kSEG + 1) | 1;
-    // 16 channels per block keeps LDS under 80 KB: two blocks per CU
-    for (int kg = 16; kg >= 8; kg /= 2) {
-      if (kpad % kg) continue;
-      size_t lds = 4 * ((size_t)G * (kg / 4) * qs + (size_t)G * (kg / 2) * hs +
-                        2 * (size_t)G * (kg / 4) * 64 * 2 + (size_t)NF * txw);
-      if (lds <= 160 * 1024) {
-        pl.ok = true;
-        pl.txw = txw;
-        pl.kg = kg;
-        pl.qs = qs;
-        pl.hs = hs;
-        pl.lds = lds;
-        return pl;
-      }
-    }
-  }
+  pl.txw = std::min(kTXW, kColsMax + 1 - t.w);
+  if (pl.txw < 32) return pl;
+  if ((int64_t)maxband * (kColsMax + 1) >= 65536) return pl;   // u16 prefix counts
+  pl.uni = true;
+  for (int f = 2; f < t.n_filters; ++f)
+    if (t.weights[f] != t.weights[1]) pl.uni = false;
+  pl.nacc = pl.uni ? 2 : t.n_filters;
+  pl.tyw = 32;
+  pl.ok = true;
   return pl;
 }
 
-template <int G, int TXW, int KG>
-hipError_t go_fused(const FusedParams& fp, const FusedPlan& pl, hipStream_t s) {
-  auto kern = score_partial_kernel<G, TXW, KG>;
-  if (pl.lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
-    if (e != hipSuccess) return e;
-  }
-  dim3 grid((fp.ow + TXW - 1) / TXW, (fp.oh + kTYW - 1) / kTYW, fp.kpad / KG);
-  hipLaunchKernelGGL(kern, grid, dim3(kFT), pl.lds, s, fp);
+template <int G, bool UNI>
+hipError_t go_tile(const TileParams& tp, hipStream_t s) {
+  dim3 grid((tp.ow + tp.txw - 1) / tp.txw, (tp.oh + tp.tyw - 1) / tp.tyw, tp.kpad / kKG);
+  hipLaunchKernelGGL((score_tile_kernel<G, UNI>), grid, dim3(kST), 0, s, tp);
   return hipGetLastError();
 }
 
-template <int G, int TXW>
-hipError_t go_fused_k(const FusedParams& fp, const FusedPlan& pl, hipStream_t s) {
-  return pl.kg == 16 ? go_fused<G, TXW, 16>(fp, pl, s) : go_fused<G, TXW, 8>(fp, pl, s);
+template <int G>
+hipError_t go_tile_u(const TileParams& tp, bool uni, hipStream_t s) {
+  return uni ? go_tile<G, true>(tp, s) : go_tile<G, false>(tp, s);
+}
+
+hipError_t go_combine(const CombineParams& cp, int nacc, hipStream_t s) {
+  const dim3 grid((unsigned)((cp.nwin + 255) / 256)), blk(256);
+  switch (nacc) {
+    case 2: hipLaunchKernelGGL((score_combine_kernel<2>), grid, blk, 0, s, cp); break;
+    case 5: hipLaunchKernelGGL((score_combine_kernel<5>), grid, blk, 0, s, cp); break;
+    case 10: hipLaunchKernelGGL((score_combine_kernel<10>), grid, blk, 0, s, cp); break;
+    case 17: hipLaunchKernelGGL((score_combine_kernel<17>), grid, blk, 0, s, cp); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
 
 size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W) {
-  FusedPlan pl = plan_fused(t);
+  TilePlan pl = plan_tile(t);
   if (!pl.ok) return 0;
   const int64_t nwin = (int64_t)(H - t.h + 1) * (W - t.w + 1);
-  return (size_t)(t.geom.kpad / pl.kg) * t.n_filters * nwin * 2;
+  return (size_t)(t.geom.kpad / kKG) * pl.nacc * nwin * 4;
 }
 
 hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out) {
   const DeviceTemplate& t = *a.t;
+  const int ow = a.W - t.w + 1, oh = a.H - t.h + 1;
   if (!t.grid.valid || !a.partials) return hipErrorInvalidValue;
-  FusedPlan pl = plan_fused(t);
+  TilePlan pl = plan_tile(t);
   if (!pl.ok) return hipErrorInvalidConfiguration;
-  FusedParams fp{};
-  fp.labels = a.labels;
-  fp.H = a.H;
-  fp.W = a.W;
-  fp.w = t.w;
-  fp.h = t.h;
-  fp.ow = a.W - t.w + 1;
-  fp.oh = a.H - t.h + 1;
-  fp.kpad = t.geom.kpad;
-  fp.kg = pl.kg;
-  fp.qs = pl.qs;
-  fp.hs = pl.hs;
+  TileParams tp{};
+  tp.labels = a.labels;
+  tp.H = a.H;
+  tp.W = a.W;
+  tp.w = t.w;
+  tp.h = t.h;
+  tp.ow = ow;
+  tp.oh = oh;
+  tp.txw = pl.txw;
+  tp.tyw = pl.tyw;
+  tp.kpad = t.geom.kpad;
   const int G = t.grid.g;
   for (int i = 0; i <= G; ++i) {
-    fp.xe[i] = t.grid.xe[i];
-    fp.ye[i] = t.grid.ye[i];
+    tp.xe[i] = t.grid.xe[i];
+    tp.ye[i] = t.grid.ye[i];
   }
-  fp.t16 = t.d_counts16;
-  fp.part = (uint16_t*)a.partials;
-  if (lds_bytes_out) *lds_bytes_out = pl.lds;
+  tp.t16 = t.d_counts16;
+  tp.part = (uint32_t*)a.partials;
+  if (lds_bytes_out) {
+    const int NR = G * kPQ;
+    *lds_bytes_out = (size_t)2 * NR * kHS * 16 + (size_t)pl.nacc * kTXW * 4;
+  }
   timing_begin(K_SCORE_FUSED);
   hipError_t e;
-  switch (pl.txw * 8 + G) {
-    case 256 * 8 + 1: e = go_fused_k<1, 256>(fp, pl, s); break;
-    case 256 * 8 + 2: e = go_fused_k<2, 256>(fp, pl, s); break;
-    case 256 * 8 + 3: e = go_fused_k<3, 256>(fp, pl, s); break;
-    case 256 * 8 + 4: e = go_fused_k<4, 256>(fp, pl, s); break;
-    case 128 * 8 + 1: e = go_fused_k<1, 128>(fp, pl, s); break;
-    case 128 * 8 + 2: e = go_fused_k<2, 128>(fp, pl, s); break;
-    case 128 * 8 + 3: e = go_fused_k<3, 128>(fp, pl, s); break;
-    case 128 * 8 + 4: e = go_fused_k<4, 128>(fp, pl, s); break;
-    case 64 * 8 + 1: e = go_fused_k<1, 64>(fp, pl, s); break;
-    case 64 * 8 + 2: e = go_fused_k<2, 64>(fp, pl, s); break;
-    case 64 * 8 + 3: e = go_fused_k<3, 64>(fp, pl, s); break;
-    case 64 * 8 + 4: e = go_fused_k<4, 64>(fp, pl, s); break;
+  switch (G) {
+    case 1: e = go_tile_u<1>(tp, pl.uni, s); break;
+    case 2: e = go_tile_u<2>(tp, pl.uni, s); break;
+    case 3: e = go_tile_u<3>(tp, pl.uni, s); break;
+    case 4: e = go_tile_u<4>(tp, pl.uni, s); break;
     default: e = hipErrorInvalidValue;
   }
   timing_end(K_SCORE_FUSED);
   if (e != hipSuccess) return e;
   CombineParams cp{};
-  cp.part = fp.part;
-  cp.nwin = (int64_t)fp.ow * fp.oh;
-  cp.ow = fp.ow;
-  cp.ngroups = fp.kpad / fp.kg;
-  cp.nf = t.n_filters;
+  cp.part = tp.part;
+  cp.nwin = (int64_t)ow * oh;
+  cp.ngroups = tp.kpad / kKG;
+  // accumulator a covers filters: UNI -> {0}, {1..NF-1}; else {a}
   for (int f = 0; f < t.n_filters; ++f) {
-    cp.wt[f] = t.weights[f];
     const int32_t* b = &t.boxes[(size_t)f * 4];
-    cp.area[f] = (b[2] - b[0]) * (b[3] - b[1]);
+    const int area = (b[2] - b[0]) * (b[3] - b[1]);
+    const int ai = pl.uni ? (f == 0 ? 0 : 1) : f;
+    cp.wt[ai] = t.weights[f];
+    cp.area2[ai] += 2 * area;
   }
   cp.heatmap = a.heatmap;
   cp.best = a.best;
   timing_begin(K_SCORE_COMBINE);
-  e = go_combine(cp, s);
+  e = go_combine(cp, pl.nacc, s);
   timing_end(K_SCORE_COMBINE);
   return e;
 }
 
-bool fused_supported(const DeviceTemplate& t) { return t.grid.valid && plan_fused(t).ok; }
+bool fused_supported(const DeviceTemplate& t) { return plan_tile(t).ok; }
 
 hipError_t launch_score_integral(const ScoreArgs& a, hipStream_t s) {
   const DeviceTemplate& t = *a.t;
