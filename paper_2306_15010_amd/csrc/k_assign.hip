@@ -16,6 +16,7 @@
 //    still candidates.  The FP64 re-score kernel settles those pixels with the
 //    exact sequential FP64 distance, lowest index on ties.
 #include "vqnnf_internal.h"
+#include "dev_common.h"
 
 namespace vqnnf {
 
@@ -571,11 +572,17 @@ __global__ __launch_bounds__(kWPB * 64) void assign_plain_kernel(KParams p) {
 }
 
 // ============================================================ FP64 re-score
-// One thread per flagged pixel: FP64 distances to every candidate codeword in
-// the fixed order d = sum_t (q_t - c_t)^2, sequential in t from 0, separate
-// subtract, multiply and add.  Candidates are taken four at a time, in
-// ascending index, as four independent sequential sums; a strict < over
-// ascending indices keeps the lowest index on ties.
+// Pixels flagged by the refined kernel are settled with the distance
+// d_j = sum_t (q_t - c_j,t)^2, sequential in t from 0 with separate FP64
+// subtract, multiply and add, for every candidate j of the pixel's mask; the
+// smallest d wins, the lowest index on ties.
+//
+// A wave takes kRPix worklist pixels.  Their (pixel, candidate) pairs are
+// numbered in pixel order with candidates ascending and dealt to the lanes 64
+// at a time, one sequential sum per lane; the query and codeword elements of
+// the next kRPF steps of kRStep elements are requested while the current ones
+// are summed.  After each round the lane of pixel s merges that round's
+// results of pixel s in pair order.
 struct RParams {
   const void* q;
   int64_t stride;
@@ -587,112 +594,152 @@ struct RParams {
   uint8_t* labels;
 };
 
+constexpr int kRPix = 32;    // worklist pixels per wave
+constexpr int kRStep = 8;    // elements per load step
+constexpr int kRPF = 4;      // steps per prefetch block
+
 template <bool QF32>
 __device__ __forceinline__ double q_elem(const void* q, int64_t off, int t) {
   if (QF32) return (double)((const float*)q)[off + t];
   return (double)bf16_bits_to_f32(((const uint16_t*)q)[off + t]);
 }
 
-// Sequential FP64 distances of one pixel to n <= 4 codewords.  VEC: 8-element
-// vector loads (query row and codebook rows 16-byte aligned).
+// Candidate j < k of a mask word w.
+__device__ __forceinline__ uint32_t valid_bits(uint32_t bits, int w, int k) {
+  const int lim = k - 32 * w;
+  return lim <= 0 ? 0u : (lim >= 32 ? bits : bits & ((1u << lim) - 1u));
+}
+
+__device__ __forceinline__ int nth_candidate(const uint32_t* m, int mw, int k, uint32_t r) {
+  for (int w = 0; w < mw; ++w) {
+    uint32_t bits = valid_bits(m[w], w, k);
+    const uint32_t n = (uint32_t)__popc(bits);
+    if (r < n) {
+      for (; r > 0; --r) bits &= bits - 1u;
+      return 32 * w + __ffs(bits) - 1;
+    }
+    r -= n;
+  }
+  return -1;
+}
+
+// Sequential FP64 distance of one query row to one codeword row.  VEC: both
+// rows 16-byte aligned; steps of kRStep elements, then a scalar tail.
 template <bool QF32, bool VEC>
-__device__ void dist4(const void* q, int64_t off, const float* cb, const int* js, int n, int D,
-                      double* acc) {
+__device__ double seq_dist(const void* q, int64_t qoff, const float* c, int D) {
 #pragma clang fp contract(off)
-  const float* c0 = cb + (int64_t)js[0] * D;
-  const float* c1 = cb + (int64_t)js[n > 1 ? 1 : 0] * D;
-  const float* c2 = cb + (int64_t)js[n > 2 ? 2 : 0] * D;
-  const float* c3 = cb + (int64_t)js[n > 3 ? 3 : 0] * D;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int t = 0;
-  if (VEC) {
-    for (; t + 8 <= D; t += 8) {
-      double qd[8];
-      if (QF32) {
-        const float4* qp = (const float4*)((const float*)q + off + t);
-        float4 x0 = qp[0], x1 = qp[1];
-        qd[0] = x0.x; qd[1] = x0.y; qd[2] = x0.z; qd[3] = x0.w;
-        qd[4] = x1.x; qd[5] = x1.y; qd[6] = x1.z; qd[7] = x1.w;
-      } else {
-        uint4 w = *(const uint4*)((const uint16_t*)q + off + t);
-        uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+  constexpr int QV = QF32 ? 2 : 1;   // uint4 per step of the query row
+  double acc = 0.0;
+  const int nst = VEC ? D / kRStep : 0;
+  if (nst > 0) {
+    const uint4* qp = (const uint4*)((const char*)q + qoff * (QF32 ? 4 : 2));
+    const uint4* cp = (const uint4*)c;
+    uint4 qa[kRPF][QV], ca[kRPF][2], qb[kRPF][QV], cb[kRPF][2];
+    // requests of a block are clamped to the last step: always in bounds
+    auto load_blk = [&](int s0, uint4 (&qd)[kRPF][QV], uint4 (&cd)[kRPF][2]) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          qd[2 * i] = (double)__uint_as_float(ws[i] << 16);
-          qd[2 * i + 1] = (double)__uint_as_float(ws[i] & 0xFFFF0000u);
+      for (int i = 0; i < kRPF; ++i) {
+        const int st = min(s0 + i, nst - 1);
+#pragma unroll
+        for (int v = 0; v < QV; ++v) qd[i][v] = qp[st * QV + v];
+        cd[i][0] = cp[st * 2];
+        cd[i][1] = cp[st * 2 + 1];
+      }
+    };
+    auto sum_blk = [&](int s0, const uint4 (&qd)[kRPF][QV], const uint4 (&cd)[kRPF][2]) {
+#pragma unroll
+      for (int i = 0; i < kRPF; ++i) {
+        if (s0 + i >= nst) break;
+        const uint32_t cw[8] = {cd[i][0].x, cd[i][0].y, cd[i][0].z, cd[i][0].w,
+                                cd[i][1].x, cd[i][1].y, cd[i][1].z, cd[i][1].w};
+        uint32_t qw[8];
+        if (QF32) {
+          qw[0] = qd[i][0].x; qw[1] = qd[i][0].y; qw[2] = qd[i][0].z; qw[3] = qd[i][0].w;
+          qw[4] = qd[i][QV - 1].x; qw[5] = qd[i][QV - 1].y; qw[6] = qd[i][QV - 1].z; qw[7] = qd[i][QV - 1].w;
+        } else {
+          const uint32_t ws[4] = {qd[i][0].x, qd[i][0].y, qd[i][0].z, qd[i][0].w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            qw[2 * e] = ws[e] << 16;
+            qw[2 * e + 1] = ws[e] & 0xFFFF0000u;
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const double dq = (double)__uint_as_float(qw[e]) - (double)__uint_as_float(cw[e]);
+          const double sq = dq * dq;
+          acc = acc + sq;
         }
       }
-      const float4* r0 = (const float4*)(c0 + t);
-      const float4* r1 = (const float4*)(c1 + t);
-      const float4* r2 = (const float4*)(c2 + t);
-      const float4* r3 = (const float4*)(c3 + t);
-      float4 u0 = r0[0], u1 = r0[1], v0 = r1[0], v1 = r1[1];
-      float4 w0 = r2[0], w1 = r2[1], z0 = r3[0], z1 = r3[1];
-      const float cA[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-      const float cB[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-      const float cC[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-      const float cD[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        double d0 = qd[i] - (double)cA[i];
-        double d1 = qd[i] - (double)cB[i];
-        double d2 = qd[i] - (double)cC[i];
-        double d3 = qd[i] - (double)cD[i];
-        double s0 = d0 * d0, s1 = d1 * d1, s2 = d2 * d2, s3 = d3 * d3;
-        a0 = a0 + s0;
-        a1 = a1 + s1;
-        a2 = a2 + s2;
-        a3 = a3 + s3;
-      }
+    };
+    load_blk(0, qa, ca);
+    for (int s0 = 0; s0 < nst; s0 += 2 * kRPF) {
+      load_blk(s0 + kRPF, qb, cb);
+      sum_blk(s0, qa, ca);
+      load_blk(s0 + 2 * kRPF, qa, ca);
+      sum_blk(s0 + kRPF, qb, cb);
     }
   }
-  for (; t < D; ++t) {
-    const double qv = q_elem<QF32>(q, off, t);
-    double d0 = qv - (double)c0[t], d1 = qv - (double)c1[t];
-    double d2 = qv - (double)c2[t], d3 = qv - (double)c3[t];
-    double s0 = d0 * d0, s1 = d1 * d1, s2 = d2 * d2, s3 = d3 * d3;
-    a0 = a0 + s0;
-    a1 = a1 + s1;
-    a2 = a2 + s2;
-    a3 = a3 + s3;
+  for (int t = nst * kRStep; t < D; ++t) {
+    const double dq = q_elem<QF32>(q, qoff, t) - (double)c[t];
+    const double sq = dq * dq;
+    acc = acc + sq;
   }
-  acc[0] = a0;
-  acc[1] = a1;
-  acc[2] = a2;
-  acc[3] = a3;
+  return acc;
 }
 
 template <bool QF32, bool VEC>
-__global__ __launch_bounds__(256) void rescore_kernel(RParams p) {
+__global__ __launch_bounds__(64) void rescore_kernel(RParams p) {
+  __shared__ uint32_t pfx[kRPix + 1];   // exclusive prefix of candidate counts
+  __shared__ double rd[64];
+  __shared__ int rj[64];
+  const int lane = threadIdx.x;
+  const int mw = p.mask_words;
   const uint32_t count = *p.wl_count;
-  for (uint32_t it = blockIdx.x * blockDim.x + threadIdx.x; it < count;
-       it += gridDim.x * blockDim.x) {
-    const uint32_t pix = p.wl_pix[it];
-    const uint32_t* mask = p.wl_mask + (int64_t)it * p.mask_words;
-    const int64_t off = (int64_t)pix * p.stride;
-    double best = 0.0;
-    int bj = -1;
-    int js[4];
-    int n = 0;
-    for (int w = 0; w <= p.mask_words; ++w) {
-      uint32_t bits = (w < p.mask_words) ? mask[w] : 0u;
-      // flush a full group, or the remainder after the last word
-      while (bits || (w == p.mask_words && n > 0)) {
-        if (bits) {
-          const int j = 32 * w + (__ffs(bits) - 1);
-          bits &= bits - 1u;
-          if (j >= p.k) continue;
-          js[n++] = j;
-          if (n < 4) continue;
-        }
-        double acc[4];
-        dist4<QF32, VEC>(p.q, off, p.codebook, js, n, p.D, acc);
-        for (int c = 0; c < n; ++c)
-          if (bj < 0 || acc[c] < best) { best = acc[c]; bj = js[c]; }
-        n = 0;
-      }
+  for (uint32_t g0 = blockIdx.x * kRPix; g0 < count; g0 += gridDim.x * kRPix) {
+    const uint32_t npx = min((uint32_t)kRPix, count - g0);
+    uint32_t nc = 0;
+    if (lane < (int)npx) {
+      const uint32_t* m = p.wl_mask + (int64_t)(g0 + lane) * mw;
+      for (int w = 0; w < mw; ++w) nc += (uint32_t)__popc(valid_bits(m[w], w, p.k));
     }
-    if (bj >= 0) p.labels[pix] = (uint8_t)bj;
+    const uint32_t inc = wave_incl_scan(nc);
+    const uint32_t total = (uint32_t)__shfl((int)inc, 63);
+    if (lane < kRPix) pfx[lane] = inc - nc;
+    if (lane == 0) pfx[kRPix] = total;
+    __syncthreads();
+    double best = 0.0;   // lane s < npx: running best of pixel s
+    int bj = -1;
+    for (uint32_t P0 = 0; P0 < total; P0 += 64) {
+      const uint32_t P = P0 + lane;
+      double d = 0.0;
+      int j = -1;
+      if (P < total) {
+        int s = 0;   // last slot with pfx[s] <= P: the pixel owning pair P
+#pragma unroll
+        for (int step = kRPix / 2; step >= 1; step >>= 1)
+          if (pfx[s + step] <= P) s += step;
+        j = nth_candidate(p.wl_mask + (int64_t)(g0 + s) * mw, mw, p.k, P - pfx[s]);
+        const int64_t qoff = (int64_t)p.wl_pix[g0 + s] * p.stride;
+        d = seq_dist<QF32, VEC>(p.q, qoff, p.codebook + (int64_t)j * p.D, p.D);
+      }
+      rd[lane] = d;
+      rj[lane] = j;
+      __syncthreads();
+      if (lane < (int)npx) {
+        const uint32_t a = max(pfx[lane], P0), b = min(pfx[lane + 1], P0 + 64);
+        for (uint32_t r = a; r < b; ++r) {
+          const double dd = rd[r - P0];
+          if (bj < 0 || dd < best) {
+            best = dd;
+            bj = rj[r - P0];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (lane < (int)npx && bj >= 0) p.labels[p.wl_pix[g0 + lane]] = (uint8_t)bj;
+    __syncthreads();
   }
 }
 
@@ -839,15 +886,16 @@ hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu) {
   rp.wl_mask = a.wl_mask;
   rp.labels = a.labels;
   const bool qf32 = a.dtype == VQNNF_F32;
+  // 16-byte steps of the query row and of every codeword row
   const bool vec = rows_aligned(a, qf32 ? 4 : 2) && (a.D % 4 == 0);
-  int grid = n_cu * 4;
+  const int grid = n_cu * 4;   // one wave per block; waves stride over the worklist
   timing_begin(K_RESCORE);
   if (qf32) {
-    if (vec) hipLaunchKernelGGL((rescore_kernel<true, true>), dim3(grid), dim3(256), 0, s, rp);
-    else hipLaunchKernelGGL((rescore_kernel<true, false>), dim3(grid), dim3(256), 0, s, rp);
+    if (vec) hipLaunchKernelGGL((rescore_kernel<true, true>), dim3(grid), dim3(64), 0, s, rp);
+    else hipLaunchKernelGGL((rescore_kernel<true, false>), dim3(grid), dim3(64), 0, s, rp);
   } else {
-    if (vec) hipLaunchKernelGGL((rescore_kernel<false, true>), dim3(grid), dim3(256), 0, s, rp);
-    else hipLaunchKernelGGL((rescore_kernel<false, false>), dim3(grid), dim3(256), 0, s, rp);
+    if (vec) hipLaunchKernelGGL((rescore_kernel<false, true>), dim3(grid), dim3(64), 0, s, rp);
+    else hipLaunchKernelGGL((rescore_kernel<false, false>), dim3(grid), dim3(64), 0, s, rp);
   }
   timing_end(K_RESCORE);
   return hipGetLastError();

@@ -25,6 +25,7 @@
 // score_integral: any indicator bank, reading the taps from a precomputed
 // integral image (vqnnf_filter's output).
 #include "vqnnf_internal.h"
+#include "dev_common.h"
 
 namespace vqnnf {
 
@@ -108,19 +109,6 @@ struct TileParams {
 };
 
 typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
-
-// Inclusive prefix sum across the 64 lanes of a wave with DPP: row_shr 1, 2,
-// 4, 8 inside each row of 16 lanes, then row_bcast 15 and 31 carry the row
-// totals into the following rows.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);
-  return x;
-}
 
 // Four packed pairs added as two 64-bit words: every 16-bit count stays below
 // 2^16, so no carry crosses a field.
@@ -423,6 +411,14 @@ hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_byt
   if (!t.grid.valid || !a.partials) return hipErrorInvalidValue;
   TilePlan pl = plan_tile(t);
   if (!pl.ok) return hipErrorInvalidConfiguration;
+  // equal tile widths; tile height so that the blocks fill whole rounds of
+  // two blocks per compute unit
+  const int nx = (ow + pl.txw - 1) / pl.txw;
+  pl.txw = (ow + nx - 1) / nx;
+  const int per_row = nx * (t.geom.kpad / kKG);
+  const int slots = 2 * std::max(a.n_cu, 1);
+  const int ny = std::max(1, (slots + per_row - 1) / per_row);
+  pl.tyw = std::max(8, (oh + ny - 1) / ny);
   TileParams tp{};
   tp.labels = a.labels;
   tp.H = a.H;

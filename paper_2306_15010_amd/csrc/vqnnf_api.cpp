@@ -628,6 +628,7 @@ static vqnnf_status score_common(vqnnf_ctx* c, const vqnnf_template* t, const ui
   a.heatmap = heatmap;
   a.best = (unsigned long long*)c->control.p;
   a.partials = c->partials.p;
+  a.n_cu = c->n_cu;
   if (!zeroed) HIP_TRY(launch_zero_u64(a.best, c->stream));
   if (labels) {
     size_t lds = 0;

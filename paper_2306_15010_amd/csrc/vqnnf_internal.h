@@ -132,6 +132,7 @@ struct ScoreArgs {
   float* heatmap;
   unsigned long long* best;    // packed (orderable score, ~index), must be 0
   void* partials;              // on-chip path: per channel group partial sums
+  int n_cu;                    // compute units (tile sizing)
 };
 hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out);
 hipError_t launch_score_integral(const ScoreArgs& a, hipStream_t s);
