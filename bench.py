@@ -59,6 +59,77 @@ def kernel_roofline(name, avg_ms, n_pix, D, qbytes, k, terms, n_win, n_f):
     return None
 
 
+def kernel_source_sha(kernel):
+    """sha256 of the source file that holds `kernel` (traffic figures are tied to it)."""
+    import hashlib
+    src = {"assign_bf16_refined": "k_assign.hip", "assign_fp32_plain": "k_assign.hip",
+           "score_partial": "k_score.hip", "score_combine": "k_score.hip"}.get(kernel)
+    if src is None:
+        return None
+    path = os.path.join(ROOT, "paper_2306_15010_amd", "csrc", src)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy of known
+    size), or None when there is none or the kernel source changed since."""
+    import glob
+    import re
+    for path in glob.glob(os.path.join(ROOT, "profiles", f"traffic__{kernel}__{workload}*.md")):
+        text = open(path).read()
+        m = re.search(r"```json\n(.*?)\n```", text, re.S)
+        if not m:
+            continue
+        d = json.loads(m.group(1))
+        if d.get("kernel_source_sha256") != kernel_source_sha(kernel):
+            return None
+        return d.get("hbm_bytes_per_launch")
+    return None
+
+
+def copy_probe(n_bytes=1 << 30, reps=3):
+    """A plain device copy of known size: the reference the HBM byte counters
+    are scaled by (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on this run)."""
+    import torch
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n_bytes, "reps": reps}), flush=True)
+
+
+def secondary(name, ctx, B, synth, steps):
+    """Both paths on another workload (device-resident, same timing as the main line)."""
+    import torch
+    wl = synth.make_config(name)
+    qm, t = wl.maps[0], wl.templates[0][0]
+    h, w, D = t.data.shape
+    tpl = B.vqnnf_codebook(ctx, t.data, t.k, 20, 0, B.default_bank(w, h, t.grid))
+    if qm.dtype == "f32":
+        qd = torch.from_numpy(np.ascontiguousarray(qm.data)).cuda()
+    else:
+        qd = torch.from_numpy(qm.data.view(np.int16)).cuda()
+    fm = B.device_fmap(qd, qm.dtype)
+    heat = torch.empty((qm.H - h + 1) * (qm.W - w + 1), device="cuda")
+    out = {"workload": workload_desc(name, wl)}
+    for key, prec in (("bf16_refined", B.VQNNF_PREC_BF16_REFINED), ("fp32_plain", B.VQNNF_PREC_FP32_PLAIN)):
+        for _ in range(3):
+            B.vqnnf_match(ctx, tpl, fm, prec, heat, want_best=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            B.vqnnf_match(ctx, tpl, fm, prec, heat, want_best=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        out[key] = {"value": qm.H * qm.W / (ms / 1e3), "ms_per_step": ms}
+    best, _ = B.vqnnf_match(ctx, tpl, fm, B.VQNNF_PREC_BF16_REFINED, heat)
+    out["best"] = {"x": best[0], "y": best[1], "planted": [t.x0, t.y0]}
+    return out
+
+
 def cpu_baseline(wl, budget_px=256 * 256):
     """The oracle as it stands on a bounded sample of the same workload: the
     top-left 256x256 pixels of the query (assign, integral image, filter bank,
@@ -97,6 +168,9 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the hot path shards "
@@ -110,6 +184,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe()
+        return
     log(f"generating workload {args.workload}")
     wl = synth.make_config(args.workload)
     qm, t = wl.maps[0], wl.templates[0][0]
@@ -164,7 +241,7 @@ def main():
     roof = kernel_roofline(dom, kernels[dom]["avg_ms"], n_pix, D, qbytes, t.k, 2, oh * ow, n_f)
     roof = dict(roof) if roof else {}
     roof["kernel"] = dom
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom, args.workload)
     others = {}
     for k2 in kernels:
         r2 = kernel_roofline(k2, kernels[k2]["avg_ms"], n_pix, D, qbytes, t.k, 2, oh * ow, n_f)
@@ -183,6 +260,11 @@ def main():
         fp32 = {"value": n_pix / (ms32 / 1e3), "ms_per_step": ms32,
                 "label_mismatches_vs_refined": mism,
                 "kernels_avg_ms": {k: v[1] / max(1, v[0]) for k, v in kt32.items()}}
+
+    sec = None
+    if not args.no_secondary and args.workload == "c3":
+        log("timing the 512x512 D=64 FP32 workload (both paths)")
+        sec = secondary("c2", ctx, B, synth, max(5, args.steps))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -205,6 +287,7 @@ def main():
         "kernel_rooflines": others,
         "ms_per_step_with_kernel_events": ms_ev,
         "template_prep_s": prep_s,
+        "secondary": sec,
     }
     print(json.dumps(out), flush=True)
 

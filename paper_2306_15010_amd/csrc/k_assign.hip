@@ -336,6 +336,9 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
 
   // epilogue of a finished tile: s_j = ||c_j||^2 + (-2 q.c_j), the norm
   // added once after the products were accumulated from zero
+  const __amdgpu_buffer_rsrc_t lab_rs = raw_rsrc(p.labels);
+  const __amdgpu_buffer_rsrc_t wlp_rs = raw_rsrc(p.wl_pix);
+  const __amdgpu_buffer_rsrc_t wlm_rs = raw_rsrc(p.wl_mask);
   auto finish = [&](int64_t tile) {
 #pragma unroll
     for (int mb = 0; mb < KB; ++mb) {
@@ -375,7 +378,8 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
       const bool flagged = (v2 - v1) <= thr;
       const int64_t pix = tile * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
       const bool owner = (g == 0) && (pix < p.n_pix);
-      if (owner) p.labels[pix] = (uint8_t)j1;
+      // stores through buffer resources: 32-bit offsets, scalar bases
+      if (owner) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)j1, lab_rs, (int)pix, 0, 0);
       const bool fl = owner && flagged;
       const unsigned long long bal = __ballot(fl);
       if (bal) {
@@ -397,9 +401,10 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
         base = __shfl(base, 0);
         if (fl) {
           const uint32_t slot = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-          p.wl_pix[slot] = (uint32_t)pix;
+          __builtin_amdgcn_raw_buffer_store_b32((uint32_t)pix, wlp_rs, (int)(slot * 4), 0, 0);
 #pragma unroll
-          for (int w = 0; w < MW; ++w) p.wl_mask[(int64_t)slot * MW + w] = mw[w];
+          for (int w = 0; w < MW; ++w)
+            __builtin_amdgcn_raw_buffer_store_b32(mw[w], wlm_rs, (int)((slot * MW + w) * 4), 0, 0);
         }
       }
     }
