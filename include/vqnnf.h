@@ -186,6 +186,26 @@ vqnnf_status vqnnf_score_integral(vqnnf_ctx* ctx, const vqnnf_template* t,
 vqnnf_status vqnnf_match(vqnnf_ctx* ctx, const vqnnf_template* t, const vqnnf_fmap* query,
                          int32_t prec, float* heatmap, int32_t* best_xy, float* best_score);
 
+/* A batch of independent (template, query map) pairs, the whole path for
+ * each: t[i] is matched against q[i] into heatmaps[i] (device,
+ * (H_i - h_i + 1) x (W_i - w_i + 1) FP32, caller owned), with the same
+ * precision for every pair.  Templates and maps may differ in size, k, D
+ * and storage, and the same map may appear in several pairs.  best_xy
+ * (host, 2*n_pairs) and best_score (host, n_pairs) receive each pair's
+ * localisation (Sec. 4); both NULL skips the synchronisation.  Every pair
+ * is validated before anything is enqueued (EINVAL names the pair).  With
+ * graph mode on (vqnnf_ctx_set_graph) the batch's kernels are captured into
+ * one HIP graph and later calls with the same arguments (handles, pointers,
+ * sizes, precision) replay it as a single launch; the inputs' contents may
+ * change between calls, the handles and buffers must stay alive. */
+vqnnf_status vqnnf_match_batched(vqnnf_ctx* ctx, int32_t n_pairs, const vqnnf_template* const* t,
+                                 const vqnnf_fmap* const* q, int32_t prec, float* const* heatmaps,
+                                 int32_t* best_xy, float* best_score);
+
+/* Graph mode for vqnnf_match_batched (0 = off, the default: kernels are
+ * launched one by one).  Turning it off releases the captured graph. */
+vqnnf_status vqnnf_ctx_set_graph(vqnnf_ctx* ctx, int32_t enable);
+
 /* Per-kernel timing.  When enabled, the library brackets every kernel it
  * launches with HIP events on the context stream.  vqnnf_ctx_kernel_times
  * synchronises, then reports for each kernel name (up to max_entries)

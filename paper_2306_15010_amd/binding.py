@@ -25,7 +25,8 @@ EXPORTED = [
     "vqnnf_template_from_codebook", "vqnnf_template_free", "vqnnf_template_info",
     "vqnnf_template_codebook", "vqnnf_template_labels", "vqnnf_template_counts",
     "vqnnf_template_weights", "vqnnf_assign", "vqnnf_filter", "vqnnf_score",
-    "vqnnf_score_integral", "vqnnf_match", "vqnnf_ctx_set_timing", "vqnnf_ctx_kernel_times",
+    "vqnnf_score_integral", "vqnnf_match", "vqnnf_match_batched", "vqnnf_ctx_set_graph",
+    "vqnnf_ctx_set_timing", "vqnnf_ctx_kernel_times",
     "vqnnf_ctx_reset_times", "vqnnf_last_error", "vqnnf_version",
 ]
 
@@ -77,6 +78,8 @@ def lib() -> C.CDLL:
         "vqnnf_score": (st, [vp, vp, vp, i32, i32, vp, P(i32), P(C.c_float)]),
         "vqnnf_score_integral": (st, [vp, vp, vp, i32, i32, vp, P(i32), P(C.c_float)]),
         "vqnnf_match": (st, [vp, vp, P(FMap), i32, vp, P(i32), P(C.c_float)]),
+        "vqnnf_match_batched": (st, [vp, i32, P(vp), P(P(FMap)), i32, P(vp), P(i32), P(C.c_float)]),
+        "vqnnf_ctx_set_graph": (st, [vp, i32]),
         "vqnnf_ctx_set_timing": (st, [vp, i32]),
         "vqnnf_ctx_kernel_times": (st, [vp, i32, P(C.c_char_p), P(i64), P(C.c_double), P(i32)]),
         "vqnnf_ctx_reset_times": (st, [vp]),
@@ -291,6 +294,29 @@ def vqnnf_match(ctx: Context, tpl: Template, query: FMap, prec: int, heatmap, wa
     st = lib().vqnnf_match(ctx.h, tpl.h, C.byref(query), prec, C.c_void_p(heatmap.data_ptr()),
                            xy, C.byref(sc))
     return _best_out(st, xy, sc)
+
+
+def vqnnf_match_batched(ctx: Context, templates: Sequence[Template], queries: Sequence[FMap],
+                        prec: int, heatmaps, want_best=True):
+    """Pairs (templates[i], queries[i]) -> heatmaps[i]; returns [((x, y), score)] or None."""
+    n = len(templates)
+    if len(queries) != n or len(heatmaps) != n:
+        raise ValueError("templates, queries and heatmaps must have the same length")
+    th = (C.c_void_p * n)(*[t.h for t in templates])
+    qarr = (FMap * n)(*queries)
+    qp = (C.POINTER(FMap) * n)(*[C.pointer(qarr[i]) for i in range(n)])
+    hp = (C.c_void_p * n)(*[h.data_ptr() for h in heatmaps])
+    if not want_best:
+        _check(lib().vqnnf_match_batched(ctx.h, n, th, qp, prec, hp, None, None))
+        return None
+    xy = (C.c_int32 * (2 * n))()
+    sc = (C.c_float * n)()
+    _check(lib().vqnnf_match_batched(ctx.h, n, th, qp, prec, hp, xy, sc))
+    return [((xy[2 * i], xy[2 * i + 1]), sc[i]) for i in range(n)]
+
+
+def vqnnf_ctx_set_graph(ctx: Context, enable: bool) -> None:
+    _check(lib().vqnnf_ctx_set_graph(ctx.h, 1 if enable else 0))
 
 
 def vqnnf_version() -> str:

@@ -70,6 +70,12 @@ struct vqnnf_ctx {
   Buffer int_side;     // integral side arrays
   Buffer int_p;        // integral image for the integral score path
   Buffer partials;     // per channel group partial sums of the on-chip score
+  Buffer keys;         // u64 [n_pairs] best keys of a batched call
+  // batched calls captured into a graph (vqnnf_ctx_set_graph)
+  bool graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint64_t> gsig;
   // timing
   bool timing = false;
   std::vector<TimingRecord> pending;
@@ -411,6 +417,89 @@ vqnnf_status check_score_dims(const vqnnf_template* tp, int H, int W) {
   return ok();
 }
 
+vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* labels,
+                                  const int32_t* P, int32_t H, int32_t W, float* heatmap,
+                                  unsigned long long* best, bool zeroed) {
+  ScoreArgs a{};
+  a.t = &t->t;
+  a.labels = labels;
+  a.P = P;
+  a.H = H;
+  a.W = W;
+  a.heatmap = heatmap;
+  a.best = best;
+  a.partials = c->partials.p;
+  a.n_cu = c->n_cu;
+  if (!zeroed) HIP_TRY(launch_zero_u64(a.best, c->stream));
+  if (labels) {
+    size_t lds = 0;
+    HIP_TRY(launch_score_fused(a, c->stream, &lds));
+  } else {
+    HIP_TRY(launch_score_integral(a, c->stream));
+  }
+  return ok();
+}
+
+// Scratch for matching the given pairs one after another (sized for the largest).
+vqnnf_status pair_scratch(vqnnf_ctx* c, const vqnnf_template* const* t, const vqnnf_fmap* const* q,
+                          int n, int prec, size_t control) {
+  size_t lab = 0, wp = 0, wm = 0, side = 0, pbytes = 0, partb = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t np = (int64_t)q[i]->H * q[i]->W;
+    const DeviceTemplate& d = t[i]->t;
+    lab = std::max(lab, (size_t)np);
+    if (prec == VQNNF_PREC_BF16_REFINED) {
+      wp = std::max(wp, (size_t)np * 4);
+      wm = std::max(wm, (size_t)np * 4 * mask_words(d));
+    }
+    if (fused_supported(d)) {
+      partb = std::max(partb, fused_partial_bytes(d, q[i]->H, q[i]->W));
+    } else {
+      const int64_t R = (q[i]->H + kIntTile - 1) / kIntTile, S = (q[i]->W + kIntTile - 1) / kIntTile;
+      side = std::max(side, (size_t)((int64_t)q[i]->H * S + R * q[i]->W + R * S) * d.k * 4);
+      pbytes = std::max(pbytes, (size_t)(q[i]->H + 1) * (q[i]->W + 1) * d.k * 4);
+    }
+  }
+  vqnnf_status s = check_cap(c, {{&c->control, control}, {&c->labels, lab}, {&c->wl_pix, wp},
+                                 {&c->wl_mask, wm}, {&c->int_side, side}, {&c->int_p, pbytes},
+                                 {&c->partials, partb}});
+  if (s) return s;
+  if ((s = need_device(c))) return s;
+  if ((s = ensure(c, c->control, control, "control block"))) return s;
+  if ((s = ensure(c, c->labels, lab, "label map"))) return s;
+  if (wp && (s = ensure(c, c->wl_pix, wp, "re-score worklist"))) return s;
+  if (wm && (s = ensure(c, c->wl_mask, wm, "re-score candidate masks"))) return s;
+  if (partb && (s = ensure(c, c->partials, partb, "score partial sums"))) return s;
+  if (side && (s = ensure(c, c->int_side, side, "integral-image side arrays"))) return s;
+  if (pbytes && (s = ensure(c, c->int_p, pbytes, "integral image"))) return s;
+  return ok();
+}
+
+// Enqueues the whole path of one pair on the context stream: assignment
+// (+ re-score), then the on-chip score, or the integral image and the
+// integral score for banks the on-chip kernel does not take.  The best key
+// must be zero; the worklist counter is cleared here unless the caller did.
+vqnnf_status enqueue_pair(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap* q, int prec,
+                          float* heatmap, unsigned long long* key, bool counter_zeroed) {
+  uint8_t* lab = (uint8_t*)c->labels.p;
+  vqnnf_status s = run_assign(c, t, q, prec, lab, counter_zeroed);
+  if (s) return s;
+  if (fused_supported(t->t)) return enqueue_score(c, t, lab, nullptr, q->H, q->W, heatmap, key, true);
+  const int k = t->t.k;
+  const int64_t R = (q->H + kIntTile - 1) / kIntTile, S = (q->W + kIntTile - 1) / kIntTile;
+  IntegralArgs a{};
+  a.labels = lab;
+  a.H = q->H;
+  a.W = q->W;
+  a.k = k;
+  a.P = (int32_t*)c->int_p.p;
+  a.rsh = (int32_t*)c->int_side.p;
+  a.cbh = a.rsh + (size_t)q->H * S * k;
+  a.th = a.cbh + (size_t)R * q->W * k;
+  HIP_TRY(launch_integral(a, c->stream));
+  return enqueue_score(c, t, nullptr, a.P, q->H, q->W, heatmap, key, true);
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -451,8 +540,10 @@ void vqnnf_ctx_destroy(vqnnf_ctx* c) {
   if (!c || c->magic != kCtxMagic) return;
   if (c->has_device) {
     hipStreamSynchronize(c->stream);
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     Buffer* bs[] = {&c->control, &c->labels, &c->wl_pix, &c->wl_mask, &c->int_side, &c->int_p,
-                    &c->partials};
+                    &c->partials, &c->keys};
     for (Buffer* b : bs)
       if (b->p) hipFree(b->p);
     for (auto& r : c->pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
@@ -619,23 +710,9 @@ vqnnf_status vqnnf_filter(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* 
 static vqnnf_status score_common(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* labels,
                                  const int32_t* P, int32_t H, int32_t W, float* heatmap,
                                  int32_t* best_xy, float* best_score, bool zeroed) {
-  ScoreArgs a{};
-  a.t = &t->t;
-  a.labels = labels;
-  a.P = P;
-  a.H = H;
-  a.W = W;
-  a.heatmap = heatmap;
-  a.best = (unsigned long long*)c->control.p;
-  a.partials = c->partials.p;
-  a.n_cu = c->n_cu;
-  if (!zeroed) HIP_TRY(launch_zero_u64(a.best, c->stream));
-  if (labels) {
-    size_t lds = 0;
-    HIP_TRY(launch_score_fused(a, c->stream, &lds));
-  } else {
-    HIP_TRY(launch_score_integral(a, c->stream));
-  }
+  vqnnf_status s = enqueue_score(c, t, labels, P, H, W, heatmap, (unsigned long long*)c->control.p,
+                                 zeroed);
+  if (s) return s;
   return read_best(c, W - t->t.w + 1, best_xy, best_score);
 }
 
@@ -677,41 +754,111 @@ vqnnf_status vqnnf_match(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap
   if ((s = check_ctx(c)) || (s = check_tpl(c, t)) || (s = check_query(c, t, q, prec))) return s;
   if (!heatmap) return fail(VQNNF_EINVAL, "null heatmap");
   if ((s = check_score_dims(t, q->H, q->W))) return s;
-  const int64_t n = (int64_t)q->H * q->W;
-  const bool fused = fused_supported(t->t);
-  const int k = t->t.k;
-  const int64_t R = (q->H + kIntTile - 1) / kIntTile, S = (q->W + kIntTile - 1) / kIntTile;
-  size_t side = fused ? 0 : (size_t)((int64_t)q->H * S + R * q->W + R * S) * k * 4;
-  size_t pbytes = fused ? 0 : (size_t)(q->H + 1) * (q->W + 1) * k * 4;
-  size_t partb = fused ? fused_partial_bytes(t->t, q->H, q->W) : 0;
-  if ((s = check_cap(c, {{&c->control, 64}, {&c->labels, (size_t)n},
-                         {&c->wl_pix, prec ? (size_t)n * 4 : 0},
-                         {&c->wl_mask, prec ? (size_t)n * 4 * mask_words(t->t) : 0},
-                         {&c->int_side, side}, {&c->int_p, pbytes}, {&c->partials, partb}})))
-    return s;
-  if ((s = assign_scratch(c, t, n, prec, true))) return s;
-  if (fused && (s = ensure(c, c->partials, partb, "score partial sums"))) return s;
-  if (!fused) {
-    if ((s = ensure(c, c->int_side, side, "integral-image side arrays"))) return s;
-    if ((s = ensure(c, c->int_p, pbytes, "integral image"))) return s;
-  }
+  if ((s = pair_scratch(c, &t, &q, 1, prec, 64))) return s;
   HookScope hs(c);
   // one fill clears the best-location key and the worklist counter
   HIP_TRY(launch_fill_u32((uint32_t*)c->control.p, 0u, 4, c->stream));
-  uint8_t* lab = (uint8_t*)c->labels.p;
-  if ((s = run_assign(c, t, q, prec, lab, true))) return s;
-  if (fused) return score_common(c, t, lab, nullptr, q->H, q->W, heatmap, best_xy, best_score, true);
-  IntegralArgs a{};
-  a.labels = lab;
-  a.H = q->H;
-  a.W = q->W;
-  a.k = k;
-  a.P = (int32_t*)c->int_p.p;
-  a.rsh = (int32_t*)c->int_side.p;
-  a.cbh = a.rsh + (size_t)q->H * S * k;
-  a.th = a.cbh + (size_t)R * q->W * k;
-  HIP_TRY(launch_integral(a, c->stream));
-  return score_common(c, t, nullptr, a.P, q->H, q->W, heatmap, best_xy, best_score, true);
+  if ((s = enqueue_pair(c, t, q, prec, heatmap, (unsigned long long*)c->control.p, true))) return s;
+  return read_best(c, q->W - t->t.w + 1, best_xy, best_score);
+}
+
+vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* const* t,
+                                 const vqnnf_fmap* const* q, int32_t prec, float* const* heatmaps,
+                                 int32_t* best_xy, float* best_score) {
+  vqnnf_status s;
+  if ((s = check_ctx(c))) return s;
+  if (n < 1) return fail(VQNNF_EINVAL, "n_pairs must be >= 1 (got %d)", n);
+  if (!t || !q || !heatmaps) return fail(VQNNF_EINVAL, "null template, map or heatmap array");
+  for (int i = 0; i < n; ++i) {
+    if ((s = check_tpl(c, t[i])) || (s = check_query(c, t[i], q[i], prec)) ||
+        (s = check_score_dims(t[i], q[i]->H, q[i]->W))) {
+      std::string m = g_err;
+      return fail(s, "pair %d: %s", i, m.c_str());
+    }
+    if (!heatmaps[i]) return fail(VQNNF_EINVAL, "pair %d: null heatmap", i);
+  }
+  if ((s = pair_scratch(c, t, q, n, prec, 64))) return s;
+  if ((s = check_cap(c, {{&c->keys, (size_t)n * 8}}))) return s;
+  if ((s = ensure(c, c->keys, (size_t)n * 8, "best-location keys"))) return s;
+  unsigned long long* keys = (unsigned long long*)c->keys.p;
+  auto enqueue_all = [&]() -> vqnnf_status {
+    HIP_TRY(launch_fill_u32((uint32_t*)keys, 0u, 2 * (int64_t)n, c->stream));
+    for (int i = 0; i < n; ++i) {
+      vqnnf_status st = enqueue_pair(c, t[i], q[i], prec, heatmaps[i], keys + i, false);
+      if (st) return st;
+    }
+    return ok();
+  };
+  if (!c->graph) {
+    HookScope hs(c);
+    if ((s = enqueue_all())) return s;
+  } else {
+    // every argument the captured kernels depend on, scratch addresses included
+    std::vector<uint64_t> sig = {(uint64_t)n, (uint64_t)prec, (uint64_t)(uintptr_t)c->stream,
+                                 (uint64_t)(uintptr_t)c->control.p, (uint64_t)(uintptr_t)c->labels.p,
+                                 (uint64_t)(uintptr_t)c->wl_pix.p, (uint64_t)(uintptr_t)c->wl_mask.p,
+                                 (uint64_t)(uintptr_t)c->partials.p, (uint64_t)(uintptr_t)c->int_side.p,
+                                 (uint64_t)(uintptr_t)c->int_p.p, (uint64_t)(uintptr_t)keys};
+    for (int i = 0; i < n; ++i) {
+      const vqnnf_fmap& m = *q[i];
+      sig.insert(sig.end(), {(uint64_t)(uintptr_t)t[i], (uint64_t)(uintptr_t)m.data, (uint64_t)m.dtype,
+                             (uint64_t)m.H, (uint64_t)m.W, (uint64_t)m.D, (uint64_t)m.pixel_stride,
+                             (uint64_t)(uintptr_t)m.channel_scale, (uint64_t)(uintptr_t)heatmaps[i]});
+    }
+    if (!(c->gexec && sig == c->gsig)) {
+      if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      // the capture stream waits for earlier work on the context stream
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+      hipStream_t user = c->stream;
+      c->stream = c->cap_stream;
+      vqnnf_status st = enqueue_all();
+      c->stream = user;
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+      if (st) {
+        if (g) hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(VQNNF_EHIP, "graph capture: %s", hipGetErrorString(e));
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(VQNNF_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+      if (c->gexec) hipGraphExecDestroy(c->gexec);
+      c->gexec = ex;
+      c->gsig = sig;
+    }
+    HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+  }
+  if (!best_xy && !best_score) return ok();
+  std::vector<unsigned long long> hk((size_t)n);
+  HIP_TRY(hipMemcpyAsync(hk.data(), keys, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < n; ++i) {
+    const uint32_t ow = (uint32_t)(q[i]->W - t[i]->t.w + 1);
+    const uint32_t idx = 0xFFFFFFFFu - (uint32_t)(hk[i] & 0xFFFFFFFFu);
+    if (best_xy) {
+      best_xy[2 * i] = (int32_t)(idx % ow);
+      best_xy[2 * i + 1] = (int32_t)(idx / ow);
+    }
+    if (best_score) best_score[i] = unpack_score(hk[i]);
+  }
+  return ok();
+}
+
+vqnnf_status vqnnf_ctx_set_graph(vqnnf_ctx* c, int32_t enable) {
+  vqnnf_status s = check_ctx(c);
+  if (s) return s;
+  if ((s = need_device(c))) return s;
+  c->graph = enable != 0;
+  if (!c->graph && c->gexec) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->gsig.clear();
+  }
+  return ok();
 }
 
 vqnnf_status vqnnf_ctx_set_timing(vqnnf_ctx* c, int32_t enable) {

@@ -121,6 +121,18 @@ def test_argument_errors_on_host_context():
     q_small = B.FMap(0x1000, B.VQNNF_BF16, 7, 32, 4, 4, None)
     assert _status_of(lambda: B.vqnnf_match(ctx, tpl, q_small, 1, FakeTensor(0x3000))) == B.VQNNF_EINVAL
     assert _status_of(lambda: B.vqnnf_score(ctx, tpl, lab, 32, 7, FakeTensor(0x3000))) == B.VQNNF_EINVAL
+    # batched: every pair is validated before anything runs; errors name the pair
+    with pytest.raises(B.VqnnfError) as ei:
+        B.vqnnf_match_batched(ctx, [tpl, tpl], [q, q_bad_d], 1, [FakeTensor(0x3000)] * 2)
+    assert ei.value.status == B.VQNNF_EINVAL and "pair 1" in str(ei.value)
+    with pytest.raises(B.VqnnfError) as ei:
+        B.vqnnf_match_batched(ctx, [tpl], [q_small], 1, [FakeTensor(0x3000)])
+    assert ei.value.status == B.VQNNF_EINVAL and "pair 0" in str(ei.value)
+    assert L.vqnnf_match_batched(ctx.h, 0, None, None, 1, None, None, None) == B.VQNNF_EINVAL
+    with pytest.raises(B.VqnnfError) as ei:   # valid pairs: needs a device
+        B.vqnnf_match_batched(ctx, [tpl, tpl], [q, q], 1, [FakeTensor(0x3000)] * 2)
+    assert ei.value.status == B.VQNNF_ENOTSUP
+    assert L.vqnnf_ctx_set_graph(ctx.h, 1) == B.VQNNF_ENOTSUP
     # freed handles
     tpl.free()
     h = C.c_void_p(0)
