@@ -116,15 +116,17 @@ def host_fmap(arr: np.ndarray) -> Tuple[FMap, np.ndarray]:
 
 
 def device_fmap(t, dtype: str, channel_scale: Optional[np.ndarray] = None) -> FMap:
-    """Device map from a torch tensor [H][W][D(+pad)] (float32 / uint16 bits /
-    bfloat16 / uint8 codes); the last dimension may exceed D via `stride`."""
+    """Device map from a torch tensor [H][W][D] (float32 / uint16 bits /
+    bfloat16 / uint8 E4M3FN codes with host FP32 channel_scale[D])."""
     H, W, S = t.shape[0], t.shape[1], t.shape[2]
     assert t.is_contiguous()
     scale = None
     if channel_scale is not None:
         channel_scale = np.ascontiguousarray(channel_scale, dtype=np.float32)
         scale = channel_scale.ctypes.data
-    return FMap(t.data_ptr(), _DT[dtype], H, W, S, S, scale)
+    fm = FMap(t.data_ptr(), _DT[dtype], H, W, S, S, scale)
+    fm._scale = channel_scale   # the host scales stay alive with the map
+    return fm
 
 
 def bank_descs(bank: Sequence[Tuple[int, int, int, int, int, int, float]]):

@@ -132,6 +132,22 @@ __device__ __forceinline__ void load_query(const void* q, int64_t off, int d0, i
   }
 }
 
+// Query storage of a kernel instance.
+constexpr int kQBF16 = 0, kQF32 = 1, kQFP8 = 2;
+
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// Eight E4M3FN codes (two words, element 0 in the low byte) to FP32, exactly
+// (gfx950's conversion follows the OCP E4M3FN encoding).
+__device__ __forceinline__ void fp8x8_to_f32(uint32_t w0, uint32_t w1, float (&x)[8]) {
+  const f32x2_t a = __builtin_amdgcn_cvt_pk_f32_fp8((int)w0, false);
+  const f32x2_t b = __builtin_amdgcn_cvt_pk_f32_fp8((int)w0, true);
+  const f32x2_t c = __builtin_amdgcn_cvt_pk_f32_fp8((int)w1, false);
+  const f32x2_t d = __builtin_amdgcn_cvt_pk_f32_fp8((int)w1, true);
+  x[0] = a[0]; x[1] = a[1]; x[2] = b[0]; x[3] = b[1];
+  x[4] = c[0]; x[5] = c[1]; x[6] = d[0]; x[7] = d[1];
+}
+
 __device__ __forceinline__ f32x4_t mfma_bf16(uint4 a, uint4 b, f32x4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
                                                  __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
@@ -191,16 +207,17 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-template <int KB, int NB, bool QF32, bool FAST>
+template <int KB, int NB, int QT, bool FAST>
 __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
+  constexpr bool QF32 = QT == kQF32, QF8 = QT == kQFP8;
   constexpr int NT = kWPB * 64;
   constexpr int GF = 2 * KB * 64;                  // uint4 per load group (hi + lo)
   constexpr int CPT = (GF + NT - 1) / NT;          // copies per thread per group
   constexpr int NEL = 8;                           // elements per lane per group
-  constexpr int QW = QF32 ? NEL : NEL / 2;         // 32-bit words per lane per group
+  constexpr int EB = QF32 ? 4 : QF8 ? 1 : 2;       // bytes per query element
+  constexpr int QW = NEL * EB / 4;                 // 32-bit words per lane per group
   constexpr int QN = FAST ? NB * (QF32 ? 2 : 1) : 0;  // vector loads per query request
   constexpr int MW = (KB + 1) / 2;                 // candidate mask words
-  constexpr int EB = QF32 ? 4 : 2;                 // bytes per query element
   // stages padded to whole copies (the padding receives duplicate data)
   __shared__ uint4 st0[CPT * NT], st1[CPT * NT];
   __shared__ float cn_s[16 * KB];
@@ -250,17 +267,38 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
   uint32_t qa[NB][QW], qb[NB][QW];
   // query elements of group gi for the tile whose base set_tile returned
   auto load_q = [&](const char* tb, int gi, uint32_t (&dst)[NB][QW]) {
-    if (FAST) {
+    if constexpr (FAST) {
       const __amdgpu_buffer_rsrc_t rs = raw_rsrc(tb);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
+      for (int nb = 0; nb < NB; ++nb) {
+        if constexpr (QW == 2) {
+          const uint2 v = __builtin_bit_cast(
+              uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, qoff[nb], gi * 32 * EB, 0));
+          dst[nb][0] = v.x;
+          dst[nb][QW - 1] = v.y;
+        } else {
 #pragma unroll
-        for (int i = 0; i < QW / 4; ++i) {
-          const uint4 v = __builtin_bit_cast(
-              uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, qoff[nb] + 16 * i, gi * 32 * EB, 0));
-          dst[nb][4 * i] = v.x; dst[nb][4 * i + 1] = v.y;
-          dst[nb][4 * i + 2] = v.z; dst[nb][4 * i + 3] = v.w;
+          for (int i = 0; i < QW / 4; ++i) {
+            const uint4 v = __builtin_bit_cast(
+                uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, qoff[nb] + 16 * i, gi * 32 * EB, 0));
+            dst[nb][4 * i] = v.x; dst[nb][4 * i + 1] = v.y;
+            dst[nb][4 * i + 2] = v.z; dst[nb][4 * i + 3] = v.w;
+          }
         }
+      }
+    } else if constexpr (QF8) {
+      // byte loads with bounds checks, relative to the pixel row start
+      const int d0 = gi * 32 + NEL * g;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const uint8_t* src = (const uint8_t*)tb + (qoff[nb] - (uint32_t)(NEL * g)) + d0;
+        uint32_t w[2] = {0u, 0u};
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (d0 + i < p.D) w[i / 4] |= (uint32_t)src[i] << (8 * (i % 4));
+        dst[nb][0] = w[0];
+        dst[nb][QW - 1] = w[1];
+      }
     } else {
       // element loads with bounds checks (D not a multiple of 64 or
       // unaligned rows), relative to the pixel row start
@@ -295,7 +333,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
     uint4 bhi[NB], blo[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      if (QF32) {
+      if constexpr (QF32) {
         uint32_t h[8], l[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -310,6 +348,18 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
                              h[6] | (h[7] << 16));
         blo[nb] = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16),
                              l[6] | (l[7] << 16));
+      } else if constexpr (QF8) {
+        // E4M3 codes are exact in BF16: the FP32 value's top half
+        float x[8];
+        fp8x8_to_f32(cur[nb][0], cur[nb][QW - 1], x);
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          qn2[nb] = fmaf(x[2 * i], x[2 * i], qn2[nb]);
+          qn2[nb] = fmaf(x[2 * i + 1], x[2 * i + 1], qn2[nb]);
+          w[i] = (__float_as_uint(x[2 * i]) >> 16) | (__float_as_uint(x[2 * i + 1]) & 0xFFFF0000u);
+        }
+        bhi[nb] = make_uint4(w[0], w[1], w[2], w[3]);
       } else {
         const uint32_t ws[4] = {cur[nb][0], cur[nb][1], cur[nb][2], cur[nb][3]};
         bhi[nb] = make_uint4(ws[0], ws[1], ws[2], ws[3]);
@@ -329,7 +379,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
       for (int nb = 0; nb < NB; ++nb) {
         acc[mb][nb] = mfma_bf16(ahi, bhi[nb], acc[mb][nb]);
         acc[mb][nb] = mfma_bf16(alo, bhi[nb], acc[mb][nb]);
-        if (QF32) acc[mb][nb] = mfma_bf16(ahi, blo[nb], acc[mb][nb]);
+        if constexpr (QF32) acc[mb][nb] = mfma_bf16(ahi, blo[nb], acc[mb][nb]);
       }
     }
   };
@@ -456,13 +506,14 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
 // s of the group uses element E*g + s.  Same pipeline as the refined kernel:
 // 8 waves, codebook groups double-buffered in LDS, query prefetched one group
 // ahead, persistent blocks.
-template <int KB, int NB, int E, bool QF32, bool VEC>
+template <int KB, int NB, int E, int QT, bool VEC>
 __global__ __launch_bounds__(kWPB * 64) void assign_plain_kernel(KParams p) {
+  constexpr bool QF32 = QT == kQF32, QF8 = QT == kQFP8;
   extern __shared__ float4 ldsf[];
   constexpr int NT = kWPB * 64;
   constexpr int GF = E * KB * 64 / 4;              // float4 per load group
   constexpr int CPT = (GF + NT - 1) / NT;
-  constexpr int QW = QF32 ? E : E / 2;
+  constexpr int QW = QF32 ? E : QF8 ? (E + 3) / 4 : E / 2;   // 32-bit words per lane per group
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int n = lane & 15, g = lane >> 4;
@@ -490,7 +541,29 @@ __global__ __launch_bounds__(kWPB * 64) void assign_plain_kernel(KParams p) {
   auto load_q = [&](int64_t tl, int gi, uint32_t (&dst)[NB][QW]) {
     const int d0 = gi * 4 * E + E * g;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) load_query<QF32, VEC, E>(p.q, pix_off(tl, nb), d0, p.D, dst[nb]);
+    for (int nb = 0; nb < NB; ++nb) {
+      if constexpr (QF8) {
+        // E codes of one pixel (element 0 in the low byte)
+        const uint8_t* src = (const uint8_t*)p.q + pix_off(tl, nb) + d0;
+        if (VEC && d0 + E <= p.D) {
+          if constexpr (E == 8) {
+            const uint2 v = *(const uint2*)src;
+            dst[nb][0] = v.x;
+            dst[nb][QW - 1] = v.y;
+          } else {
+            dst[nb][0] = *(const uint32_t*)src;
+          }
+        } else {
+#pragma unroll
+          for (int w = 0; w < QW; ++w) dst[nb][w] = 0u;
+#pragma unroll
+          for (int i = 0; i < E; ++i)
+            if (d0 + i < p.D) dst[nb][i / 4] |= (uint32_t)src[i] << (8 * (i % 4));
+        }
+      } else {
+        load_query<QF32, VEC, E>(p.q, pix_off(tl, nb), d0, p.D, dst[nb]);
+      }
+    }
   };
   load_cb(0);
   load_q(tile, 0, cur);
@@ -521,9 +594,19 @@ __global__ __launch_bounds__(kWPB * 64) void assign_plain_kernel(KParams p) {
       float x[NB][E];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        if (QF32) {
+        if constexpr (QF32) {
 #pragma unroll
           for (int i = 0; i < E; ++i) x[nb][i] = __uint_as_float(cur[nb][i]);
+        } else if constexpr (QF8) {
+#pragma unroll
+          for (int w = 0; w < E / 4; ++w) {
+            const f32x2_t lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)cur[nb][w], false);
+            const f32x2_t hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)cur[nb][w], true);
+            x[nb][4 * w] = lo[0];
+            x[nb][4 * w + 1] = lo[1];
+            x[nb][4 * w + 2] = hi[0];
+            x[nb][4 * w + 3] = hi[1];
+          }
         } else {
 #pragma unroll
           for (int i = 0; i < E / 2; ++i) {
@@ -593,6 +676,7 @@ struct RParams {
   int64_t stride;
   int D, k, mask_words;
   const float* codebook;
+  const float* scale;      // FP8 maps: [D] channel scales
   const uint32_t* wl_count;
   const uint32_t* wl_pix;
   const uint32_t* wl_mask;
@@ -603,10 +687,17 @@ constexpr int kRPix = 32;    // worklist pixels per wave
 constexpr int kRStep = 8;    // elements per load step
 constexpr int kRPF = 4;      // steps per prefetch block
 
-template <bool QF32>
-__device__ __forceinline__ double q_elem(const void* q, int64_t off, int t) {
-  if (QF32) return (double)((const float*)q)[off + t];
-  return (double)bf16_bits_to_f32(((const uint16_t*)q)[off + t]);
+// Query element t as the FP64 value the oracle uses: FP32, BF16, or an
+// E4M3FN code times its channel scale (exact in FP64).
+template <int QT>
+__device__ __forceinline__ double q_elem(const void* q, int64_t off, int t, const float* scale) {
+  if constexpr (QT == kQF32) return (double)((const float*)q)[off + t];
+  else if constexpr (QT == kQFP8) {
+    const f32x2_t v = __builtin_amdgcn_cvt_pk_f32_fp8((int)((const uint8_t*)q)[off + t], false);
+    return (double)v[0] * (double)scale[t];
+  } else {
+    return (double)bf16_bits_to_f32(((const uint16_t*)q)[off + t]);
+  }
 }
 
 // Candidate j < k of a mask word w.
@@ -630,70 +721,93 @@ __device__ __forceinline__ int nth_candidate(const uint32_t* m, int mw, int k, u
 
 // Sequential FP64 distance of one query row to one codeword row.  VEC: both
 // rows 16-byte aligned; steps of kRStep elements, then a scalar tail.
-template <bool QF32, bool VEC>
-__device__ double seq_dist(const void* q, int64_t qoff, const float* c, int D) {
+template <int QT, bool VEC>
+__device__ double seq_dist(const void* q, int64_t qoff, const float* c, int D, const float* scale) {
 #pragma clang fp contract(off)
-  constexpr int QV = QF32 ? 2 : 1;   // uint4 per step of the query row
+  constexpr bool QF32 = QT == kQF32, QF8 = QT == kQFP8;
+  constexpr int QV = QF32 ? 2 : 1;   // uint4 per step of the query row (FP8: one uint2)
+  constexpr int SV = QF8 ? 2 : 1;    // uint4 of scales per step
   double acc = 0.0;
   const int nst = VEC ? D / kRStep : 0;
   if (nst > 0) {
-    const uint4* qp = (const uint4*)((const char*)q + qoff * (QF32 ? 4 : 2));
+    const char* qb8 = (const char*)q + qoff * (QF32 ? 4 : QF8 ? 1 : 2);
+    const uint4* qp = (const uint4*)qb8;
+    const uint2* qp8 = (const uint2*)qb8;
     const uint4* cp = (const uint4*)c;
+    const uint4* sp = (const uint4*)scale;
     uint4 qa[kRPF][QV], ca[kRPF][2], qb[kRPF][QV], cb[kRPF][2];
+    uint4 sa[kRPF][SV], sb[kRPF][SV];
     // requests of a block are clamped to the last step: always in bounds
-    auto load_blk = [&](int s0, uint4 (&qd)[kRPF][QV], uint4 (&cd)[kRPF][2]) {
+    auto load_blk = [&](int s0, uint4 (&qd)[kRPF][QV], uint4 (&cd)[kRPF][2], uint4 (&sd)[kRPF][SV]) {
 #pragma unroll
       for (int i = 0; i < kRPF; ++i) {
         const int st = min(s0 + i, nst - 1);
+        if constexpr (QF8) {
+          const uint2 v = qp8[st];
+          qd[i][0] = make_uint4(v.x, v.y, 0u, 0u);
+          sd[i][0] = sp[st * 2];
+          sd[i][SV - 1] = sp[st * 2 + 1];
+        } else {
 #pragma unroll
-        for (int v = 0; v < QV; ++v) qd[i][v] = qp[st * QV + v];
+          for (int v = 0; v < QV; ++v) qd[i][v] = qp[st * QV + v];
+        }
         cd[i][0] = cp[st * 2];
         cd[i][1] = cp[st * 2 + 1];
       }
     };
-    auto sum_blk = [&](int s0, const uint4 (&qd)[kRPF][QV], const uint4 (&cd)[kRPF][2]) {
+    auto sum_blk = [&](int s0, const uint4 (&qd)[kRPF][QV], const uint4 (&cd)[kRPF][2],
+                       const uint4 (&sd)[kRPF][SV]) {
 #pragma unroll
       for (int i = 0; i < kRPF; ++i) {
         if (s0 + i >= nst) break;
         const uint32_t cw[8] = {cd[i][0].x, cd[i][0].y, cd[i][0].z, cd[i][0].w,
                                 cd[i][1].x, cd[i][1].y, cd[i][1].z, cd[i][1].w};
-        uint32_t qw[8];
-        if (QF32) {
-          qw[0] = qd[i][0].x; qw[1] = qd[i][0].y; qw[2] = qd[i][0].z; qw[3] = qd[i][0].w;
-          qw[4] = qd[i][QV - 1].x; qw[5] = qd[i][QV - 1].y; qw[6] = qd[i][QV - 1].z; qw[7] = qd[i][QV - 1].w;
+        double qv[8];
+        if constexpr (QF32) {
+          const uint32_t qw[8] = {qd[i][0].x, qd[i][0].y, qd[i][0].z, qd[i][0].w,
+                                  qd[i][QV - 1].x, qd[i][QV - 1].y, qd[i][QV - 1].z, qd[i][QV - 1].w};
+#pragma unroll
+          for (int e = 0; e < 8; ++e) qv[e] = (double)__uint_as_float(qw[e]);
+        } else if constexpr (QF8) {
+          float x[8];
+          fp8x8_to_f32(qd[i][0].x, qd[i][0].y, x);
+          const uint32_t sw[8] = {sd[i][0].x, sd[i][0].y, sd[i][0].z, sd[i][0].w,
+                                  sd[i][SV - 1].x, sd[i][SV - 1].y, sd[i][SV - 1].z, sd[i][SV - 1].w};
+#pragma unroll
+          for (int e = 0; e < 8; ++e) qv[e] = (double)x[e] * (double)__uint_as_float(sw[e]);
         } else {
           const uint32_t ws[4] = {qd[i][0].x, qd[i][0].y, qd[i][0].z, qd[i][0].w};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            qw[2 * e] = ws[e] << 16;
-            qw[2 * e + 1] = ws[e] & 0xFFFF0000u;
+            qv[2 * e] = (double)__uint_as_float(ws[e] << 16);
+            qv[2 * e + 1] = (double)__uint_as_float(ws[e] & 0xFFFF0000u);
           }
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const double dq = (double)__uint_as_float(qw[e]) - (double)__uint_as_float(cw[e]);
+          const double dq = qv[e] - (double)__uint_as_float(cw[e]);
           const double sq = dq * dq;
           acc = acc + sq;
         }
       }
     };
-    load_blk(0, qa, ca);
+    load_blk(0, qa, ca, sa);
     for (int s0 = 0; s0 < nst; s0 += 2 * kRPF) {
-      load_blk(s0 + kRPF, qb, cb);
-      sum_blk(s0, qa, ca);
-      load_blk(s0 + 2 * kRPF, qa, ca);
-      sum_blk(s0 + kRPF, qb, cb);
+      load_blk(s0 + kRPF, qb, cb, sb);
+      sum_blk(s0, qa, ca, sa);
+      load_blk(s0 + 2 * kRPF, qa, ca, sa);
+      sum_blk(s0 + kRPF, qb, cb, sb);
     }
   }
   for (int t = nst * kRStep; t < D; ++t) {
-    const double dq = q_elem<QF32>(q, qoff, t) - (double)c[t];
+    const double dq = q_elem<QT>(q, qoff, t, scale) - (double)c[t];
     const double sq = dq * dq;
     acc = acc + sq;
   }
   return acc;
 }
 
-template <bool QF32, bool VEC>
+template <int QT, bool VEC>
 __global__ __launch_bounds__(64) void rescore_kernel(RParams p) {
   __shared__ uint32_t pfx[kRPix + 1];   // exclusive prefix of candidate counts
   __shared__ double rd[64];
@@ -726,7 +840,7 @@ __global__ __launch_bounds__(64) void rescore_kernel(RParams p) {
           if (pfx[s + step] <= P) s += step;
         j = nth_candidate(p.wl_mask + (int64_t)(g0 + s) * mw, mw, p.k, P - pfx[s]);
         const int64_t qoff = (int64_t)p.wl_pix[g0 + s] * p.stride;
-        d = seq_dist<QF32, VEC>(p.q, qoff, p.codebook + (int64_t)j * p.D, p.D);
+        d = seq_dist<QT, VEC>(p.q, qoff, p.codebook + (int64_t)j * p.D, p.D, p.scale);
       }
       rd[lane] = d;
       rj[lane] = j;
@@ -751,28 +865,36 @@ __global__ __launch_bounds__(64) void rescore_kernel(RParams p) {
 // ============================================================ launchers
 namespace {
 
-bool rows_aligned(const AssignArgs& a, int elem_bytes) {
+// Query rows start `align`-byte aligned (base and pixel stride).
+bool rows_aligned(const AssignArgs& a, int elem_bytes, int align) {
   uintptr_t base = (uintptr_t)a.q;
-  return (base % 16 == 0) && ((a.stride * elem_bytes) % 16 == 0);
+  return (base % align == 0) && ((a.stride * elem_bytes) % align == 0);
 }
 
-template <int KB, int NB, bool QF32, bool FAST>
+int qtype(int dtype) { return dtype == VQNNF_F32 ? kQF32 : dtype == VQNNF_FP8_E4M3 ? kQFP8 : kQBF16; }
+int qbytes(int qt) { return qt == kQF32 ? 4 : qt == kQFP8 ? 1 : 2; }
+
+template <int KB, int NB, int QT, bool FAST>
 hipError_t go_refined(const KParams& kp, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((assign_refined_kernel<KB, NB, QF32, FAST>), dim3(grid), dim3(kWPB * 64), 0, s, kp);
+  hipLaunchKernelGGL((assign_refined_kernel<KB, NB, QT, FAST>), dim3(grid), dim3(kWPB * 64), 0, s, kp);
   return hipGetLastError();
 }
 
-template <int KB, int NB>
-hipError_t go_refined_q(const KParams& kp, int grid, bool qf32, bool fast, hipStream_t s) {
-  if (qf32) return fast ? go_refined<KB, NB, true, true>(kp, grid, s)
-                        : go_refined<KB, NB, true, false>(kp, grid, s);
-  return fast ? go_refined<KB, NB, false, true>(kp, grid, s)
-              : go_refined<KB, NB, false, false>(kp, grid, s);
+template <int KB, int NB, int QT>
+hipError_t go_refined_f(const KParams& kp, int grid, bool fast, hipStream_t s) {
+  return fast ? go_refined<KB, NB, QT, true>(kp, grid, s) : go_refined<KB, NB, QT, false>(kp, grid, s);
 }
 
-template <int KB, int NB, int E, bool QF32, bool VEC>
+template <int KB, int NB>
+hipError_t go_refined_q(const KParams& kp, int grid, int qt, bool fast, hipStream_t s) {
+  if (qt == kQF32) return go_refined_f<KB, NB, kQF32>(kp, grid, fast, s);
+  if (qt == kQFP8) return go_refined_f<KB, NB, kQFP8>(kp, grid, fast, s);
+  return go_refined_f<KB, NB, kQBF16>(kp, grid, fast, s);
+}
+
+template <int KB, int NB, int E, int QT, bool VEC>
 hipError_t go_plain(const KParams& kp, size_t lds, int grid, hipStream_t s) {
-  auto kern = assign_plain_kernel<KB, NB, E, QF32, VEC>;
+  auto kern = assign_plain_kernel<KB, NB, E, QT, VEC>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -781,19 +903,26 @@ hipError_t go_plain(const KParams& kp, size_t lds, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int KB, int NB, int QT>
+hipError_t go_plain_e(const KParams& kp, size_t lds, int grid, int E, bool vec, hipStream_t s) {
+  if (E == 8) return vec ? go_plain<KB, NB, 8, QT, true>(kp, lds, grid, s)
+                         : go_plain<KB, NB, 8, QT, false>(kp, lds, grid, s);
+  return vec ? go_plain<KB, NB, 4, QT, true>(kp, lds, grid, s)
+             : go_plain<KB, NB, 4, QT, false>(kp, lds, grid, s);
+}
+
 template <int KB, int NB>
-hipError_t go_plain_s(const KParams& kp, size_t lds, int grid, int E, bool qf32, bool vec,
-                      hipStream_t s) {
-  if (qf32) {
-    if (E == 8) return vec ? go_plain<KB, NB, 8, true, true>(kp, lds, grid, s)
-                           : go_plain<KB, NB, 8, true, false>(kp, lds, grid, s);
-    return vec ? go_plain<KB, NB, 4, true, true>(kp, lds, grid, s)
-               : go_plain<KB, NB, 4, true, false>(kp, lds, grid, s);
-  }
-  if (E == 8) return vec ? go_plain<KB, NB, 8, false, true>(kp, lds, grid, s)
-                         : go_plain<KB, NB, 8, false, false>(kp, lds, grid, s);
-  return vec ? go_plain<KB, NB, 4, false, true>(kp, lds, grid, s)
-             : go_plain<KB, NB, 4, false, false>(kp, lds, grid, s);
+hipError_t go_plain_s(const KParams& kp, size_t lds, int grid, int E, int qt, bool vec, hipStream_t s) {
+  if (qt == kQF32) return go_plain_e<KB, NB, kQF32>(kp, lds, grid, E, vec, s);
+  if (qt == kQFP8) return go_plain_e<KB, NB, kQFP8>(kp, lds, grid, E, vec, s);
+  return go_plain_e<KB, NB, kQBF16>(kp, lds, grid, E, vec, s);
+}
+
+template <int QT>
+hipError_t go_rescore(const RParams& rp, int grid, bool vec, hipStream_t s) {
+  if (vec) hipLaunchKernelGGL((rescore_kernel<QT, true>), dim3(grid), dim3(64), 0, s, rp);
+  else hipLaunchKernelGGL((rescore_kernel<QT, false>), dim3(grid), dim3(64), 0, s, rp);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -809,7 +938,7 @@ hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu) {
   kp.stride = a.stride;
   kp.n_pix = a.n_pix;
   kp.D = a.D;
-  kp.frag = t.d_frag_bf16;
+  kp.frag = a.frag_bf16;
   kp.cnorm = t.d_cnorm;
   kp.n_groups = g.d_pad_bf16 / (32 * g.s_bf16);
   kp.labels = a.labels;
@@ -819,9 +948,11 @@ hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu) {
   kp.a0 = a.bound.a0;
   kp.a1 = a.bound.a1;
   kp.a2 = a.bound.a2;
-  const bool qf32 = a.dtype == VQNNF_F32;
-  // full load groups: D a multiple of two K-steps of 32, rows 16-byte aligned
-  const bool fast = rows_aligned(a, qf32 ? 4 : 2) && (a.D % 64 == 0) && g.s_bf16 == 1;
+  const int qt = qtype(a.dtype);
+  // full load groups: D a multiple of two K-steps of 32, rows aligned to the
+  // query load width (16 bytes; 8 for FP8 codes)
+  const bool fast = rows_aligned(a, qbytes(qt), qt == kQFP8 ? 8 : 16) && (a.D % 64 == 0) &&
+                    g.s_bf16 == 1;
   const int NB = pick_nb(g.kb);
   const int64_t tile_px = (int64_t)kWPB * NB * 16;
   kp.n_tiles = (a.n_pix + tile_px - 1) / tile_px;
@@ -830,12 +961,12 @@ hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu) {
   timing_begin(K_ASSIGN_REFINED);
   hipError_t e;
   switch (g.kb) {
-    case 1: e = go_refined_q<1, 4>(kp, grid, qf32, fast, s); break;
-    case 2: e = go_refined_q<2, 4>(kp, grid, qf32, fast, s); break;
-    case 3: e = go_refined_q<3, 4>(kp, grid, qf32, fast, s); break;
-    case 4: e = go_refined_q<4, 4>(kp, grid, qf32, fast, s); break;
-    case 8: e = go_refined_q<8, 4>(kp, grid, qf32, fast, s); break;
-    case 16: e = go_refined_q<16, 2>(kp, grid, qf32, fast, s); break;
+    case 1: e = go_refined_q<1, 4>(kp, grid, qt, fast, s); break;
+    case 2: e = go_refined_q<2, 4>(kp, grid, qt, fast, s); break;
+    case 3: e = go_refined_q<3, 4>(kp, grid, qt, fast, s); break;
+    case 4: e = go_refined_q<4, 4>(kp, grid, qt, fast, s); break;
+    case 8: e = go_refined_q<8, 4>(kp, grid, qt, fast, s); break;
+    case 16: e = go_refined_q<16, 2>(kp, grid, qt, fast, s); break;
     default: e = hipErrorInvalidValue; break;
   }
   timing_end(K_ASSIGN_REFINED);
@@ -850,12 +981,12 @@ hipError_t launch_assign_plain(const AssignArgs& a, hipStream_t s, int n_cu) {
   kp.stride = a.stride;
   kp.n_pix = a.n_pix;
   kp.D = a.D;
-  kp.frag = t.d_frag_f32;
+  kp.frag = a.frag_f32;
   kp.cnorm = t.d_cnorm;
   kp.n_groups = g.d_pad_f32 / (4 * g.e_f32);
   kp.labels = a.labels;
-  const bool qf32 = a.dtype == VQNNF_F32;
-  const bool vec = rows_aligned(a, qf32 ? 4 : 2);
+  const int qt = qtype(a.dtype);
+  const bool vec = rows_aligned(a, qbytes(qt), qt == kQFP8 ? 8 : 16);
   const size_t lds = 2 * (size_t)g.e_f32 * g.kb * 64 * 4;
   const int NB = pick_nb(g.kb);
   const int64_t tile_px = (int64_t)kWPB * NB * 16;
@@ -865,12 +996,12 @@ hipError_t launch_assign_plain(const AssignArgs& a, hipStream_t s, int n_cu) {
   hipError_t e;
   const int E = g.e_f32;
   switch (g.kb) {
-    case 1: e = go_plain_s<1, 4>(kp, lds, grid, E, qf32, vec, s); break;
-    case 2: e = go_plain_s<2, 4>(kp, lds, grid, E, qf32, vec, s); break;
-    case 3: e = go_plain_s<3, 4>(kp, lds, grid, E, qf32, vec, s); break;
-    case 4: e = go_plain_s<4, 4>(kp, lds, grid, E, qf32, vec, s); break;
-    case 8: e = go_plain_s<8, 4>(kp, lds, grid, E, qf32, vec, s); break;
-    case 16: e = go_plain_s<16, 2>(kp, lds, grid, E, qf32, vec, s); break;
+    case 1: e = go_plain_s<1, 4>(kp, lds, grid, E, qt, vec, s); break;
+    case 2: e = go_plain_s<2, 4>(kp, lds, grid, E, qt, vec, s); break;
+    case 3: e = go_plain_s<3, 4>(kp, lds, grid, E, qt, vec, s); break;
+    case 4: e = go_plain_s<4, 4>(kp, lds, grid, E, qt, vec, s); break;
+    case 8: e = go_plain_s<8, 4>(kp, lds, grid, E, qt, vec, s); break;
+    case 16: e = go_plain_s<16, 2>(kp, lds, grid, E, qt, vec, s); break;
     default: e = hipErrorInvalidValue; break;
   }
   timing_end(K_ASSIGN_PLAIN);
@@ -886,23 +1017,22 @@ hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu) {
   rp.k = t.k;
   rp.mask_words = (t.geom.kpad + 31) / 32;
   rp.codebook = t.d_codebook;
+  rp.scale = a.scale;
   rp.wl_count = a.wl_count;
   rp.wl_pix = a.wl_pix;
   rp.wl_mask = a.wl_mask;
   rp.labels = a.labels;
-  const bool qf32 = a.dtype == VQNNF_F32;
-  // 16-byte steps of the query row and of every codeword row
-  const bool vec = rows_aligned(a, qf32 ? 4 : 2) && (a.D % 4 == 0);
+  const int qt = qtype(a.dtype);
+  // whole steps of 8 elements: query rows aligned to the step width (16 bytes;
+  // 8 for FP8 codes) and codeword rows 16-byte aligned
+  const bool vec = rows_aligned(a, qbytes(qt), qt == kQFP8 ? 8 : 16) && (a.D % 4 == 0);
   const int grid = n_cu * 4;   // one wave per block; waves stride over the worklist
   timing_begin(K_RESCORE);
-  if (qf32) {
-    if (vec) hipLaunchKernelGGL((rescore_kernel<true, true>), dim3(grid), dim3(64), 0, s, rp);
-    else hipLaunchKernelGGL((rescore_kernel<true, false>), dim3(grid), dim3(64), 0, s, rp);
-  } else {
-    if (vec) hipLaunchKernelGGL((rescore_kernel<false, true>), dim3(grid), dim3(64), 0, s, rp);
-    else hipLaunchKernelGGL((rescore_kernel<false, false>), dim3(grid), dim3(64), 0, s, rp);
-  }
+  hipError_t e;
+  if (qt == kQF32) e = go_rescore<kQF32>(rp, grid, vec, s);
+  else if (qt == kQFP8) e = go_rescore<kQFP8>(rp, grid, vec, s);
+  else e = go_rescore<kQBF16>(rp, grid, vec, s);
   timing_end(K_RESCORE);
-  return hipGetLastError();
+  return e;
 }
 }  // namespace vqnnf

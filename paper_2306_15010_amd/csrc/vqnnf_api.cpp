@@ -219,8 +219,12 @@ vqnnf_status check_map(const vqnnf_fmap* m, const char* what) {
   if ((int64_t)m->H * m->W >= (1ll << 31)) return fail(VQNNF_EINVAL, "%s: H*W must be < 2^31", what);
   if (st * (int64_t)dtype_size(m->dtype) > (1ll << 22))
     return fail(VQNNF_EINVAL, "%s: a pixel row (pixel_stride * element size) must be <= 4 MiB", what);
-  if (m->dtype == VQNNF_FP8_E4M3 && !m->channel_scale)
-    return fail(VQNNF_EINVAL, "%s: FP8 map needs channel_scale", what);
+  if (m->dtype == VQNNF_FP8_E4M3) {
+    if (!m->channel_scale) return fail(VQNNF_EINVAL, "%s: FP8 map needs channel_scale", what);
+    for (int d = 0; d < m->D; ++d)
+      if (!std::isfinite(m->channel_scale[d]) || m->channel_scale[d] < 0.0f)
+        return fail(VQNNF_EINVAL, "%s: channel_scale[%d] must be finite and >= 0", what, d);
+  }
   return ok();
 }
 
@@ -286,6 +290,46 @@ void free_device(DeviceTemplate& t) {
     if (p) hipFree(p);
   t.d_codebook = nullptr; t.d_frag_bf16 = nullptr; t.d_frag_f32 = nullptr; t.d_cnorm = nullptr;
   t.d_counts = nullptr; t.d_counts16 = nullptr; t.d_weights = nullptr; t.d_boxes = nullptr;
+  for (ScaledSet& ss : t.scaled) {
+    if (ss.d_frag_bf16) hipFree(ss.d_frag_bf16);
+    if (ss.d_frag_f32) hipFree(ss.d_frag_f32);
+    if (ss.d_scale) hipFree(ss.d_scale);
+  }
+  t.scaled.clear();
+}
+
+// The FP8 tables of template t for the map's channel scales: found by value,
+// else built on the host and uploaded (synchronously, before any launch that
+// reads them).  Sets are kept for the life of the template.
+vqnnf_status prepare_scaled(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap* q,
+                            const ScaledSet** out) {
+  *out = nullptr;
+  if (q->dtype != VQNNF_FP8_E4M3) return ok();
+  DeviceTemplate& t = const_cast<vqnnf_template*>(tp)->t;
+  const int D = t.D;
+  for (const ScaledSet& ss : t.scaled)
+    if (std::memcmp(ss.scale.data(), q->channel_scale, sizeof(float) * D) == 0) {
+      *out = &ss;
+      return ok();
+    }
+  ScaledSet ss;
+  ss.scale.assign(q->channel_scale, q->channel_scale + D);
+  std::vector<uint16_t> fb16;
+  std::vector<float> ff;
+  build_scaled_tables(t, q->channel_scale, fb16, ff, ss.bound);
+  std::vector<uint4> fb(fb16.size() / 8);
+  std::memcpy(fb.data(), fb16.data(), fb16.size() * 2);
+  vqnnf_status s;
+  if ((s = upload(c, &ss.d_frag_bf16, fb)) || (s = upload(c, &ss.d_frag_f32, ff)) ||
+      (s = upload(c, &ss.d_scale, ss.scale))) {
+    if (ss.d_frag_bf16) hipFree(ss.d_frag_bf16);
+    if (ss.d_frag_f32) hipFree(ss.d_frag_f32);
+    if (ss.d_scale) hipFree(ss.d_scale);
+    return s;
+  }
+  t.scaled.push_back(std::move(ss));
+  *out = &t.scaled.back();
+  return ok();
 }
 
 vqnnf_status finish_template(vqnnf_ctx* ctx, vqnnf_template* tp, const vqnnf_fmap* tmpl) {
@@ -331,8 +375,6 @@ vqnnf_status check_query(const vqnnf_ctx* c, const vqnnf_template* t, const vqnn
   if (q->D != t->t.D) return fail(VQNNF_EINVAL, "query D=%d differs from template D=%d", q->D, t->t.D);
   if (prec != VQNNF_PREC_FP32_PLAIN && prec != VQNNF_PREC_BF16_REFINED)
     return fail(VQNNF_EINVAL, "unknown precision %d", prec);
-  if (q->dtype == VQNNF_FP8_E4M3)
-    return fail(VQNNF_ENOTSUP, "FP8 query maps are not supported by this version");
   (void)c;
   return ok();
 }
@@ -378,6 +420,15 @@ vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap
   a.dtype = q->dtype;
   a.t = &t;
   a.labels = labels;
+  const ScaledSet* ss = nullptr;
+  if (q->dtype == VQNNF_FP8_E4M3) {
+    for (const ScaledSet& x : t.scaled)
+      if (std::memcmp(x.scale.data(), q->channel_scale, sizeof(float) * t.D) == 0) ss = &x;
+    if (!ss) return fail(VQNNF_EINVAL, "FP8 tables were not prepared for this map");
+  }
+  a.frag_bf16 = ss ? ss->d_frag_bf16 : t.d_frag_bf16;
+  a.frag_f32 = ss ? ss->d_frag_f32 : t.d_frag_f32;
+  a.scale = ss ? ss->d_scale : nullptr;
   if (prec == VQNNF_PREC_FP32_PLAIN) {
     HIP_TRY(launch_assign_plain(a, c->stream, c->n_cu));
     return ok();
@@ -385,7 +436,7 @@ vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap
   a.wl_count = (uint32_t*)((char*)c->control.p + 8);
   a.wl_pix = (uint32_t*)c->wl_pix.p;
   a.wl_mask = (uint32_t*)c->wl_mask.p;
-  a.bound = (q->dtype == VQNNF_F32) ? t.bound_f32q : t.bound_bf16q;
+  a.bound = ss ? ss->bound : (q->dtype == VQNNF_F32) ? t.bound_f32q : t.bound_bf16q;
   if (!counter_zeroed) HIP_TRY(launch_fill_u32(a.wl_count, 0u, 1, c->stream));
   HIP_TRY(launch_assign_refined(a, c->stream, c->n_cu));
   HIP_TRY(launch_rescore(a, c->stream, c->n_cu));
@@ -667,6 +718,8 @@ vqnnf_status vqnnf_assign(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fma
   if (!labels) return fail(VQNNF_EINVAL, "null labels");
   int64_t n = (int64_t)q->H * q->W;
   if ((s = assign_scratch(c, t, n, prec, false))) return s;
+  const ScaledSet* ss;
+  if ((s = prepare_scaled(c, t, q, &ss))) return s;
   HookScope hs(c);
   if ((s = run_assign(c, t, q, prec, labels, false))) return s;
   if (n_flagged) {
@@ -755,6 +808,8 @@ vqnnf_status vqnnf_match(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap
   if (!heatmap) return fail(VQNNF_EINVAL, "null heatmap");
   if ((s = check_score_dims(t, q->H, q->W))) return s;
   if ((s = pair_scratch(c, &t, &q, 1, prec, 64))) return s;
+  const ScaledSet* ss;
+  if ((s = prepare_scaled(c, t, q, &ss))) return s;
   HookScope hs(c);
   // one fill clears the best-location key and the worklist counter
   HIP_TRY(launch_fill_u32((uint32_t*)c->control.p, 0u, 4, c->stream));
@@ -778,6 +833,9 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     if (!heatmaps[i]) return fail(VQNNF_EINVAL, "pair %d: null heatmap", i);
   }
   if ((s = pair_scratch(c, t, q, n, prec, 64))) return s;
+  std::vector<const ScaledSet*> sets((size_t)n);
+  for (int i = 0; i < n; ++i)
+    if ((s = prepare_scaled(c, t[i], q[i], &sets[i]))) return s;
   if ((s = check_cap(c, {{&c->keys, (size_t)n * 8}}))) return s;
   if ((s = ensure(c, c->keys, (size_t)n * 8, "best-location keys"))) return s;
   unsigned long long* keys = (unsigned long long*)c->keys.p;
@@ -803,7 +861,7 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
       const vqnnf_fmap& m = *q[i];
       sig.insert(sig.end(), {(uint64_t)(uintptr_t)t[i], (uint64_t)(uintptr_t)m.data, (uint64_t)m.dtype,
                              (uint64_t)m.H, (uint64_t)m.W, (uint64_t)m.D, (uint64_t)m.pixel_stride,
-                             (uint64_t)(uintptr_t)m.channel_scale, (uint64_t)(uintptr_t)heatmaps[i]});
+                             (uint64_t)(uintptr_t)sets[i], (uint64_t)(uintptr_t)heatmaps[i]});
     }
     if (!(c->gexec && sig == c->gsig)) {
       if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));

@@ -48,6 +48,16 @@ struct GridBank {
   int ye[9];   // row edges
 };
 
+// Assignment tables for FP8 maps of one channel-scale vector: the scale is
+// folded into the codebook (c' = s*c), so they are built per distinct scale.
+struct ScaledSet {
+  std::vector<float> scale;          // the scales these tables belong to
+  uint4* d_frag_bf16 = nullptr;      // fragments of c' (BF16 hi/lo), scaled by -2
+  float* d_frag_f32 = nullptr;       // fragments of c' (FP32), scaled by -2
+  float* d_scale = nullptr;          // [D] device copy of the scales
+  BoundCoef bound{};
+};
+
 struct DeviceTemplate {
   int w = 0, h = 0, D = 0, k = 0, n_filters = 0;
   AssignGeom geom{};
@@ -61,6 +71,8 @@ struct DeviceTemplate {
   GridBank grid{};
   BoundCoef bound_bf16q{};           // BF16-stored query, codebook hi+lo
   BoundCoef bound_f32q{};            // FP32-stored query, both split hi+lo
+  std::vector<float> cnorm32;        // [k] ||c||^2 rounded to FP32
+  std::vector<ScaledSet> scaled;     // FP8 tables, one per distinct scale vector
   // device copies
   float* d_codebook = nullptr;       // [k][D] FP32
   uint4* d_frag_bf16 = nullptr;      // A fragments, BF16 hi/lo, scaled by -2
@@ -89,6 +101,8 @@ struct HostTables {
   std::vector<uint32_t> counts16;    // [nf][kpad/2]
 };
 void build_tables(DeviceTemplate& t, HostTables& ht);
+void build_scaled_tables(const DeviceTemplate& t, const float* scale, std::vector<uint16_t>& frag_bf16,
+                         std::vector<float>& frag_f32, BoundCoef& bound);
 
 // ---------------------------------------------------------------- launches
 // All launchers enqueue on `stream` and return hipSuccess or the first error.
@@ -100,6 +114,9 @@ struct AssignArgs {
   int D;
   int dtype;             // vqnnf_dtype
   const DeviceTemplate* t;
+  const uint4* frag_bf16;  // codebook fragments (the template's, or its FP8 ScaledSet's)
+  const float* frag_f32;
+  const float* scale;      // FP8 maps: [D] device channel scales; else null
   uint8_t* labels;
   // refined path only
   uint32_t* wl_count;    // worklist counter (must be 0 on entry)

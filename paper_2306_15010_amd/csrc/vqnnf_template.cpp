@@ -222,9 +222,13 @@ float round_up_f32(double v) {
   return f;
 }
 
-// Error-bound constants of the refined path (see BoundCoef).
-BoundCoef make_bound(const DeviceTemplate& t, const std::vector<float>& hi,
-                     const std::vector<float>& lo, const std::vector<float>& cn32, bool f32_query) {
+// Error-bound constants of the refined path (see BoundCoef).  cmul is the
+// vector the stored query values multiply (the codebook itself, or s*c for
+// FP8 maps whose per-channel scale s is folded into the codebook); hi/lo are
+// its BF16 split.  smax >= |s_d| bounds ||q|| by smax*||stored values||.
+BoundCoef make_bound(const DeviceTemplate& t, const std::vector<double>& cmul,
+                     const std::vector<float>& hi, const std::vector<float>& lo,
+                     const std::vector<float>& cn32, bool f32_query, double smax) {
   const int D = t.D, k = t.k;
   const double u = 0x1.0p-23;  // per-addend relative error allowed to the accumulator
   const double n_add = (double)(f32_query ? 3 : 2) * t.geom.d_pad_bf16;
@@ -241,7 +245,7 @@ BoundCoef make_bound(const DeviceTemplate& t, const std::vector<float>& hi,
     for (int d = 0; d < D; ++d) {
       double c = t.codebook[(size_t)j * D + d];
       double h = hi[(size_t)j * D + d], l = lo[(size_t)j * D + d];
-      double r = c - h - l;
+      double r = cmul[(size_t)j * D + d] - h - l;   // exact: both sides fit 53 bits
       cn2 = cn2 + c * c;
       r2 = r2 + r * r;
       double a = std::fabs(h) + std::fabs(l);
@@ -266,10 +270,70 @@ BoundCoef make_bound(const DeviceTemplate& t, const std::vector<float>& hi,
   A0 += 1e-30;
   BoundCoef b;
   const double s = 1.0 + 0x1.0p-10;
+  // 2*E64 with ||q|| <= smax*||e||: 2*gam64*(smax*||e|| + ||c||)^2
   b.a0 = round_up_f32(s * (2.0 * A0 + 2.0 * gam64 * cmax * cmax));
-  b.a1 = round_up_f32(s * (2.0 * A1 + 4.0 * gam64 * cmax));
-  b.a2 = round_up_f32(s * (2.0 * gam64));
+  b.a1 = round_up_f32(s * (2.0 * A1 + 4.0 * gam64 * cmax * smax));
+  b.a2 = round_up_f32(s * (2.0 * gam64 * smax * smax));
   return b;
+}
+
+// BF16 hi/lo split of x (hi = x rounded to BF16 through FP32, lo = the rest
+// rounded to BF16); the residual x - hi - lo is accounted for by make_bound.
+void split_bf16(const std::vector<double>& x, std::vector<float>& hi, std::vector<float>& lo) {
+  hi.resize(x.size());
+  lo.resize(x.size());
+  for (size_t i = 0; i < x.size(); ++i) {
+    const float hf = bf16_to_f32(bf16_rne((float)x[i]));
+    hi[i] = hf;
+    lo[i] = bf16_to_f32(bf16_rne((float)(x[i] - (double)hf)));
+  }
+}
+
+// MFMA A-operand fragments (-2 * hi, -2 * lo) in lane order.
+void pack_frag_bf16(const DeviceTemplate& t, const std::vector<float>& hi, const std::vector<float>& lo,
+                    std::vector<uint16_t>& out) {
+  const int D = t.D, k = t.k;
+  const AssignGeom& g = t.geom;
+  const int S = g.s_bf16, KB = g.kb;
+  const int steps = g.d_pad_bf16 / 32;
+  out.assign((size_t)steps * 2 * KB * 64 * 8, 0);
+  for (int st = 0; st < steps; ++st) {
+    int gi = st / S, sp = st % S;
+    for (int term = 0; term < 2; ++term)
+      for (int mb = 0; mb < KB; ++mb)
+        for (int l = 0; l < 64; ++l) {
+          int m = l % 16, lg = l / 16;
+          int j = 16 * mb + m;
+          size_t base = ((((size_t)st * 2 + term) * KB + mb) * 64 + l) * 8;
+          for (int i = 0; i < 8; ++i) {
+            int d = 32 * S * gi + 8 * S * lg + 8 * sp + i;
+            float v = 0.0f;
+            if (j < k && d < D) v = -2.0f * (term == 0 ? hi : lo)[(size_t)j * D + d];
+            out[base + i] = bf16_rne(v);
+          }
+        }
+  }
+}
+
+// FP32 fragments (-2 * x) of the plain path in lane order.
+void pack_frag_f32(const DeviceTemplate& t, const std::vector<float>& x, std::vector<float>& out) {
+  const int D = t.D, k = t.k;
+  const AssignGeom& g = t.geom;
+  const int KB = g.kb, E = g.e_f32;
+  const int fsteps = g.d_pad_f32 / 4;
+  out.assign((size_t)fsteps * KB * 64, 0.0f);
+  for (int st = 0; st < fsteps; ++st) {
+    int gi = st / E, sp = st % E;
+    for (int mb = 0; mb < KB; ++mb)
+      for (int l = 0; l < 64; ++l) {
+        int m = l % 16, lg = l / 16;
+        int j = 16 * mb + m;
+        int d = 4 * E * gi + E * lg + sp;
+        float v = 0.0f;
+        if (j < k && d < D) v = -2.0f * x[(size_t)j * D + d];
+        out[((size_t)st * KB + mb) * 64 + l] = v;
+      }
+  }
 }
 
 }  // namespace
@@ -299,16 +363,9 @@ void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_st
 void build_tables(DeviceTemplate& t, HostTables& ht) {
   const int D = t.D, k = t.k;
   const AssignGeom& g = t.geom;
-  std::vector<float> hi((size_t)k * D), lo((size_t)k * D);
-  for (size_t i = 0; i < hi.size(); ++i) {
-    float c = t.codebook[i];
-    uint16_t hb = bf16_rne(c);
-    float hf = bf16_to_f32(hb);
-    float r = c - hf;  // exact (Sterbenz)
-    uint16_t lb = bf16_rne(r);
-    hi[i] = hf;
-    lo[i] = bf16_to_f32(lb);
-  }
+  std::vector<double> c64(t.codebook.begin(), t.codebook.end());
+  std::vector<float> hi, lo;
+  split_bf16(c64, hi, lo);
   // ||c||^2: FP64 sequential sum of squares, rounded to FP32
   ht.cnorm.assign(g.kpad, 3.0e38f);
   for (int j = 0; j < k; ++j) {
@@ -319,42 +376,8 @@ void build_tables(DeviceTemplate& t, HostTables& ht) {
     }
     ht.cnorm[j] = (float)s;
   }
-  // BF16 fragments
-  const int S = g.s_bf16, KB = g.kb;
-  const int steps = g.d_pad_bf16 / 32;
-  ht.frag_bf16.assign((size_t)steps * 2 * KB * 64 * 8, 0);
-  for (int st = 0; st < steps; ++st) {
-    int gi = st / S, sp = st % S;
-    for (int term = 0; term < 2; ++term)
-      for (int mb = 0; mb < KB; ++mb)
-        for (int l = 0; l < 64; ++l) {
-          int m = l % 16, lg = l / 16;
-          int j = 16 * mb + m;
-          size_t base = ((((size_t)st * 2 + term) * KB + mb) * 64 + l) * 8;
-          for (int i = 0; i < 8; ++i) {
-            int d = 32 * S * gi + 8 * S * lg + 8 * sp + i;
-            float v = 0.0f;
-            if (j < k && d < D) v = -2.0f * (term == 0 ? hi : lo)[(size_t)j * D + d];
-            ht.frag_bf16[base + i] = bf16_rne(v);
-          }
-        }
-  }
-  // FP32 fragments
-  const int E = g.e_f32;
-  const int fsteps = g.d_pad_f32 / 4;
-  ht.frag_f32.assign((size_t)fsteps * KB * 64, 0.0f);
-  for (int st = 0; st < fsteps; ++st) {
-    int gi = st / E, sp = st % E;
-    for (int mb = 0; mb < KB; ++mb)
-      for (int l = 0; l < 64; ++l) {
-        int m = l % 16, lg = l / 16;
-        int j = 16 * mb + m;
-        int d = 4 * E * gi + E * lg + sp;
-        float v = 0.0f;
-        if (j < k && d < D) v = -2.0f * t.codebook[(size_t)j * D + d];
-        ht.frag_f32[((size_t)st * KB + mb) * 64 + l] = v;
-      }
-  }
+  pack_frag_bf16(t, hi, lo, ht.frag_bf16);
+  pack_frag_f32(t, t.codebook, ht.frag_f32);
   // counts padded to kpad
   ht.counts.assign((size_t)t.n_filters * g.kpad, 0);
   ht.counts16.assign((size_t)t.n_filters * g.kpad / 2, 0);
@@ -364,8 +387,28 @@ void build_tables(DeviceTemplate& t, HostTables& ht) {
       ht.counts[(size_t)f * g.kpad + j] = v;
       ht.counts16[(size_t)f * g.kpad / 2 + j / 2] |= ((uint32_t)v & 0xFFFFu) << (16 * (j & 1));
     }
-  t.bound_bf16q = make_bound(t, hi, lo, ht.cnorm, false);
-  t.bound_f32q = make_bound(t, hi, lo, ht.cnorm, true);
+  t.bound_bf16q = make_bound(t, c64, hi, lo, ht.cnorm, false, 1.0);
+  t.bound_f32q = make_bound(t, c64, hi, lo, ht.cnorm, true, 1.0);
+  t.cnorm32 = ht.cnorm;
+}
+
+// Tables for FP8 maps with per-channel scale s: the query codes e multiply
+// c' = s*c (exact in FP64), split into BF16 hi/lo; q.c = e.c'.
+void build_scaled_tables(const DeviceTemplate& t, const float* scale, std::vector<uint16_t>& frag_bf16,
+                         std::vector<float>& frag_f32, BoundCoef& bound) {
+  const int D = t.D, k = t.k;
+  std::vector<double> cs((size_t)k * D);
+  double smax = 0.0;
+  for (int d = 0; d < D; ++d) smax = std::max(smax, std::fabs((double)scale[d]));
+  for (int j = 0; j < k; ++j)
+    for (int d = 0; d < D; ++d)
+      cs[(size_t)j * D + d] = (double)scale[d] * (double)t.codebook[(size_t)j * D + d];
+  std::vector<float> hi, lo, cs32(cs.size());
+  split_bf16(cs, hi, lo);
+  for (size_t i = 0; i < cs.size(); ++i) cs32[i] = (float)cs[i];
+  pack_frag_bf16(t, hi, lo, frag_bf16);
+  pack_frag_f32(t, cs32, frag_f32);
+  bound = make_bound(t, cs, hi, lo, t.cnorm32, false, smax);
 }
 
 }  // namespace vqnnf

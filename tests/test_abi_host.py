@@ -121,6 +121,17 @@ def test_argument_errors_on_host_context():
     q_small = B.FMap(0x1000, B.VQNNF_BF16, 7, 32, 4, 4, None)
     assert _status_of(lambda: B.vqnnf_match(ctx, tpl, q_small, 1, FakeTensor(0x3000))) == B.VQNNF_EINVAL
     assert _status_of(lambda: B.vqnnf_score(ctx, tpl, lab, 32, 7, FakeTensor(0x3000))) == B.VQNNF_EINVAL
+    # FP8 maps: the host channel scales must be present, finite and >= 0
+    sc = np.ones(4, np.float32)
+    q8 = B.FMap(0x1000, B.VQNNF_FP8_E4M3, 32, 32, 4, 4, None)
+    assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q8, 1, lab)) == B.VQNNF_EINVAL
+    for bad_s in (np.float32(-1.0), np.float32(np.nan), np.float32(np.inf)):
+        sc_bad = sc.copy()
+        sc_bad[2] = bad_s
+        q8b = B.FMap(0x1000, B.VQNNF_FP8_E4M3, 32, 32, 4, 4, sc_bad.ctypes.data)
+        assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q8b, 1, lab)) == B.VQNNF_EINVAL
+    q8ok = B.FMap(0x1000, B.VQNNF_FP8_E4M3, 32, 32, 4, 4, sc.ctypes.data)
+    assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q8ok, 1, lab)) == B.VQNNF_ENOTSUP
     # batched: every pair is validated before anything runs; errors name the pair
     with pytest.raises(B.VqnnfError) as ei:
         B.vqnnf_match_batched(ctx, [tpl, tpl], [q, q_bad_d], 1, [FakeTensor(0x3000)] * 2)
