@@ -130,12 +130,108 @@ def secondary(name, ctx, B, synth, steps):
     return out
 
 
+def batched_bench(args, ctx, B, synth, torch):
+    """Batched workloads: every (template, map) pair in one vqnnf_match_batched
+    call, replayed as one captured HIP graph, against the same pairs as
+    sequential vqnnf_match calls."""
+    log(f"generating workload {args.workload} (map sides / {args.scale_down})")
+    t0 = time.perf_counter()
+    wl = synth.make_config(args.workload, scale_down=args.scale_down)
+    log(f"  {time.perf_counter() - t0:.1f} s")
+    tp0 = time.perf_counter()
+    tpls, fms, heats, devs = [], [], [], []
+    for qm, row in zip(wl.maps, wl.templates):
+        if qm.dtype == "f32":
+            dev = torch.from_numpy(np.ascontiguousarray(qm.data)).cuda()
+        elif qm.dtype == "bf16":
+            dev = torch.from_numpy(qm.data.view(np.int16)).cuda()
+        else:
+            dev = torch.from_numpy(qm.data).cuda()
+        devs.append(dev)
+        for t in row:
+            h, w, _ = t.data.shape
+            tpls.append(B.vqnnf_codebook(ctx, t.data, t.k, 20, 0, B.default_bank(w, h, t.grid)))
+            fms.append(B.device_fmap(dev, qm.dtype, qm.scale))
+            heats.append(torch.empty((qm.H - h + 1) * (qm.W - w + 1), device="cuda"))
+    prep_s = time.perf_counter() - tp0
+    log(f"  {len(tpls)} templates prepared in {prep_s:.1f} s")
+    pair_px = sum(qm.H * qm.W * len(row) for qm, row in zip(wl.maps, wl.templates))
+    map_px = sum(qm.H * qm.W for qm in wl.maps)
+    P = B.VQNNF_PREC_BF16_REFINED
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    def seq():
+        for tp, fm, ht in zip(tpls, fms, heats):
+            B.vqnnf_match(ctx, tp, fm, P, ht, want_best=False)
+
+    def bat():
+        B.vqnnf_match_batched(ctx, tpls, fms, P, heats, want_best=False)
+
+    log("timing: graph-captured batch")
+    B.vqnnf_ctx_set_graph(ctx, True)
+    ms_graph = timed(bat, args.steps, args.warmup)
+    out = B.vqnnf_match_batched(ctx, tpls, fms, P, heats)
+    B.vqnnf_ctx_set_graph(ctx, False)
+    log("timing: eager batch")
+    ms_eager = timed(bat, args.steps, args.warmup)
+    log("timing: sequential vqnnf_match calls")
+    ms_seq = timed(seq, args.steps, args.warmup)
+    ctx.reset_times()
+    ctx.set_timing(True)
+    bat()
+    torch.cuda.synchronize()
+    kt = ctx.kernel_times()
+    ctx.set_timing(False)
+    found = 0
+    i = 0
+    for row in wl.templates:
+        for t in row:
+            found += int(out[i][0] == (t.x0, t.y0))
+            i += 1
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(wl)
+    value = pair_px / (ms_graph / 1e3)
+    res = {
+        "metric": METRIC, "value": value, "unit": "px/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp8" if wl.maps[0].dtype == "fp8" else "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {len(wl.maps)} map(s), {len(tpls)} (template, map) "
+                               f"pairs, D={wl.maps[0].D} {wl.maps[0].dtype}, map sides / {args.scale_down}",
+                   "global_batch": len(tpls), "pair_pixels": pair_px, "map_pixels": map_px,
+                   "prec": "bf16_refined"},
+        "roofline": None,
+        "cpu_baseline": cpu,
+        "map_px_per_s": map_px / (ms_graph / 1e3),
+        "graph_batch_ms": ms_graph, "eager_batch_ms": ms_eager, "sequential_ms": ms_seq,
+        "speedup_vs_sequential": ms_seq / ms_graph,
+        "planted_found": f"{found} of {len(tpls)}",
+        "kernels_total_ms": {k: round(v[1], 4) for k, v in kt.items()},
+        "kernel_launches": {k: v[0] for k, v in kt.items()},
+        "template_prep_s": prep_s,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def cpu_baseline(wl, budget_px=256 * 256):
     """The oracle as it stands on a bounded sample of the same workload: the
     top-left 256x256 pixels of the query (assign, integral image, filter bank,
-    scores of every window inside the sample, argmax)."""
+    scores of every window inside the sample, argmax).  Batched workloads use
+    the pair with the smallest template (its k-means is not timed)."""
     from oracle import vqnnf_oracle as O
-    qm, t = wl.maps[0], wl.templates[0][0]
+    pairs = [(qm, t) for qm, row in zip(wl.maps, wl.templates) for t in row]
+    qm, t = min(pairs, key=lambda p: p[1].data.size * p[1].k)
     h, w, D = t.data.shape
     side = int(np.sqrt(budget_px))
     side = max(side, max(h, w))
@@ -169,6 +265,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--scale-down", type=int, default=1,
+                    help="batched workloads: divide map sides by this factor")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -186,6 +284,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload in ("c4", "c5"):
+        batched_bench(args, B.Context(stream=torch.cuda.current_stream()), B, synth, torch)
         return
     log(f"generating workload {args.workload}")
     wl = synth.make_config(args.workload)

@@ -87,7 +87,8 @@ def mixture_features(z: np.ndarray, means: np.ndarray, sigma: float,
     for y0 in range(0, H, rows):
         y1 = min(H, y0 + rows)
         eps = rng.standard_normal(size=(y1 - y0, W, D), dtype=np.float32)
-        out[y0:y1] = mu32[z[y0:y1]] + np.float32(sigma) * eps
+        np.multiply(eps, np.float32(sigma), out=eps)
+        np.add(np.take(mu32, z[y0:y1], axis=0), eps, out=out[y0:y1])
     return out
 
 
@@ -126,19 +127,20 @@ _E4M3_POS = _E4M3[:0x7F]  # codes 0x00..0x7E, increasing, 0 .. 448
 
 
 def f32_to_e4m3fn(x: np.ndarray) -> np.ndarray:
-    """Encode finite values to OCP E4M3FN codes: RNE, saturating at +-448."""
+    """Encode finite values to OCP E4M3FN codes: round to nearest even,
+    saturating at +-448.  |x| = m * 2^e with m in [1, 2): normal codes
+    (e >= -6) keep rint(8m) in [8, 16] (16 carries into the exponent),
+    subnormals rint(|x| * 2^9) on the 2^-9 grid."""
     x = np.asarray(x, dtype=np.float64)
     a = np.minimum(np.abs(x), 448.0)
-    hi = np.searchsorted(_E4M3_POS, a, side="left")  # first code with value >= a
-    hi = np.minimum(hi, 0x7E)
-    lo = np.maximum(hi - 1, 0)
-    vhi = _E4M3_POS[hi]
-    vlo = _E4M3_POS[lo]
-    dlo = a - vlo
-    dhi = vhi - a
-    pick_hi = (dhi < dlo) | ((dhi == dlo) & ((hi & 1) == 0))
-    pick_hi |= (vhi == a)
-    code = np.where(pick_hi, hi, lo).astype(np.uint8)
+    m, e = np.frexp(a)                          # a = m * 2^e, m in [0.5, 1)
+    e = e - 1
+    q = np.rint(np.ldexp(m, 4))                 # 8 * (2m), in [8, 16]
+    carry = q == 16
+    q = np.where(carry, 8, q).astype(np.int64)
+    e = np.where(carry, e + 1, e)
+    code = np.where(e >= -6, ((e + 7) << 3) + (q - 8), np.rint(np.ldexp(a, 9)).astype(np.int64))
+    code = np.where(a == 0, 0, np.minimum(code, 0x7E)).astype(np.uint8)
     neg = (x < 0) & (code != 0)
     return np.where(neg, code | np.uint8(0x80), code).astype(np.uint8)
 
@@ -317,32 +319,51 @@ def make_multi_template(seed, H, W, D, M, sigma, dtype, n_t, side_rng, k_choices
     return Workload("c4", seed, [qm], [tpls])
 
 
+def _multi_map_one(job):
+    """One map of make_multi_map and its templates (a process-pool job)."""
+    map_seed, H, W, D, M, sigma, dtype, means, t_per_map, tside_rng, k, grid, noise = job
+    r_lab, r_feat, r_place, r_tnoise = _streams(map_seed, 4)
+    z = smooth_label_field(H, W, M, r_lab)
+    qm = encode(mixture_features(z, means, sigma, r_feat), dtype)
+    row = []
+    tlo, thi = tside_rng
+    thi = min(thi, H, W)
+    tlo = min(tlo, thi)
+    for _ in range(t_per_map):
+        side = int(r_place.integers(tlo, thi + 1))
+        x0 = int(r_place.integers(0, W - side + 1))
+        y0 = int(r_place.integers(0, H - side + 1))
+        t = _crop(qm, x0, y0, side, side)
+        t = t + np.float32(noise) * r_tnoise.standard_normal(size=t.shape, dtype=np.float32)
+        row.append(Template(np.ascontiguousarray(t, dtype=np.float32), x0, y0, 0, k, grid))
+    return qm, row
+
+
 def make_multi_map(seed, n_maps, side_rng, D, M, sigma, dtype, t_per_map, tside_rng, k, grid,
                    noise=0.1) -> Workload:
     r_means, r_sizes, *r_maps = _streams(seed, 2 + n_maps)
     means = r_means.standard_normal(size=(M, D))
     lo, hi = side_rng
     sides = np.arange(lo, hi + 1, 64) if lo % 64 == 0 and hi % 64 == 0 else np.arange(lo, hi + 1)
-    maps, tpls = [], []
+    jobs = []
     for i in range(n_maps):
         H = int(r_sizes.choice(sides))
         W = int(r_sizes.choice(sides))
-        r_lab, r_feat, r_place, r_tnoise = _streams(int(r_maps[i].integers(0, 2**62)), 4)
-        z = smooth_label_field(H, W, M, r_lab)
-        qm = encode(mixture_features(z, means, sigma, r_feat), dtype)
-        row = []
-        tlo, thi = tside_rng
-        thi = min(thi, H, W)
-        tlo = min(tlo, thi)
-        for _ in range(t_per_map):
-            side = int(r_place.integers(tlo, thi + 1))
-            x0 = int(r_place.integers(0, W - side + 1))
-            y0 = int(r_place.integers(0, H - side + 1))
-            t = _crop(qm, x0, y0, side, side)
-            t = t + np.float32(noise) * r_tnoise.standard_normal(size=t.shape, dtype=np.float32)
-            row.append(Template(np.ascontiguousarray(t, dtype=np.float32), x0, y0, 0, k, grid))
-        maps.append(qm)
-        tpls.append(row)
+        jobs.append((int(r_maps[i].integers(0, 2**62)), H, W, D, M, sigma, dtype, means, t_per_map,
+                     tside_rng, k, grid, noise))
+    # every map has its own streams, so maps can be made in any order; large
+    # workloads use a pool of fresh interpreters
+    total = sum(j[1] * j[2] for j in jobs) * D
+    if total > (1 << 28) and n_maps > 1:
+        import multiprocessing as mp
+        import os
+        n = max(1, min(16, len(os.sched_getaffinity(0)), n_maps))
+        with mp.get_context("spawn").Pool(n) as pool:
+            done = pool.map(_multi_map_one, jobs, chunksize=1)
+    else:
+        done = [_multi_map_one(j) for j in jobs]
+    maps = [d[0] for d in done]
+    tpls = [d[1] for d in done]
     return Workload("c5", seed, maps, tpls)
 
 
