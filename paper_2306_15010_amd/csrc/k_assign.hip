@@ -17,11 +17,9 @@
 //    exact sequential FP64 distance, lowest index on ties.
 #include "vqnnf_internal.h"
 #include "dev_common.h"
+#include "assign_common.h"
 
 namespace vqnnf {
-
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ timing
 namespace {
@@ -29,7 +27,7 @@ thread_local TimingHook g_hook{nullptr, nullptr, nullptr};
 const char* const kNames[K_COUNT] = {
     "fill",           "assign_fp32_plain", "assign_bf16_refined", "rescore_fp64",
     "integral_edges", "integral_prefix",   "integral_main",       "score_partial",
-    "score_combine",  "score_integral"};
+    "score_combine",  "score_integral", "assign_multi"};
 }  // namespace
 
 void set_timing_hook(const TimingHook* h) {
@@ -60,14 +58,6 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s) {
   return launch_fill_u32((uint32_t*)p, 0u, 2, s);
-}
-
-// ------------------------------------------------------------------ helpers
-__device__ __forceinline__ float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
-
-__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
 }
 
 struct KParams {
@@ -132,40 +122,6 @@ __device__ __forceinline__ void load_query(const void* q, int64_t off, int d0, i
   }
 }
 
-// Query storage of a kernel instance.
-constexpr int kQBF16 = 0, kQF32 = 1, kQFP8 = 2;
-
-typedef float f32x2_t __attribute__((ext_vector_type(2)));
-
-// Eight E4M3FN codes (two words, element 0 in the low byte) to FP32, exactly
-// (gfx950's conversion follows the OCP E4M3FN encoding).
-__device__ __forceinline__ void fp8x8_to_f32(uint32_t w0, uint32_t w1, float (&x)[8]) {
-  const f32x2_t a = __builtin_amdgcn_cvt_pk_f32_fp8((int)w0, false);
-  const f32x2_t b = __builtin_amdgcn_cvt_pk_f32_fp8((int)w0, true);
-  const f32x2_t c = __builtin_amdgcn_cvt_pk_f32_fp8((int)w1, false);
-  const f32x2_t d = __builtin_amdgcn_cvt_pk_f32_fp8((int)w1, true);
-  x[0] = a[0]; x[1] = a[1]; x[2] = b[0]; x[3] = b[1];
-  x[4] = c[0]; x[5] = c[1]; x[6] = d[0]; x[7] = d[1];
-}
-
-__device__ __forceinline__ f32x4_t mfma_bf16(uint4 a, uint4 b, f32x4_t c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
-                                                 __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
-}
-
-// Top-2 merge of (best value, best index, second value) triples; ties in the
-// best value keep the lower index and make the second equal to the best.
-__device__ __forceinline__ void merge_top2(float& v1, int& j1, float& v2, float o1, int oj1,
-                                           float o2) {
-  if (o1 < v1 || (o1 == v1 && oj1 < j1)) {
-    v2 = fminf(v1, o2);
-    v1 = o1;
-    j1 = oj1;
-  } else {
-    v2 = fminf(v2, o1);
-  }
-}
-
 // ============================================================ BF16 refined
 // Template parameters: KB codeword blocks of 16, NB pixel blocks of 16 per
 // wave, QF32: FP32-stored query (hi/lo split in registers), FAST: 16-byte
@@ -183,29 +139,10 @@ __device__ __forceinline__ void merge_top2(float& v1, int& j1, float& v2, float 
 //   consumed (two buffers: even and odd groups).
 // Memory counters drain in issue order, so the wait for the codebook copy of
 // step s leaves exactly the query loads of step s+1 outstanding.
-constexpr int kWPB = 8;
-
 struct StepCursor {
   int64_t tile;
   int gi;
 };
-
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-// Raw buffer resource over [base, base + 4 GiB): stride 0, 32-bit data
-// format, so a load's address is base + voffset + soffset and the uniform part
-// of every address stays in scalar registers.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
-}
-
-// s_waitcnt with only the vector-memory counter limited to N (gfx9 encoding:
-// vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt at their no-wait maxima).
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
 
 template <int KB, int NB, int QT, bool FAST>
 __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {

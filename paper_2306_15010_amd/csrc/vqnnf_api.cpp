@@ -71,6 +71,18 @@ struct vqnnf_ctx {
   Buffer int_p;        // integral image for the integral score path
   Buffer partials;     // per channel group partial sums of the on-chip score
   Buffer keys;         // u64 [n_pairs] best keys of a batched call
+  // fused multi-template assignment of a batch (per map group)
+  Buffer m_labels;     // uint8 [n_templates][n_pix]
+  Buffer m_count;      // u32 [n_templates] worklist counters
+  Buffer m_wl_pix;     // u32 [n_templates][n_pix]
+  Buffer m_wl_mask;    // u32 [n_templates][n_pix][4]
+  struct MultiPlan {
+    std::vector<uint64_t> sig;
+    Buffer frag, cnorm, passes, outs;
+    int n_pass = 0;
+    std::vector<int> slot_pair;        // output slot -> index in the map group
+  };
+  std::vector<MultiPlan> mplans;       // one per map group of the last batch
   // batched calls captured into a graph (vqnnf_ctx_set_graph)
   bool graph = false;
   hipStream_t cap_stream = nullptr;
@@ -491,6 +503,26 @@ vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t*
   return ok();
 }
 
+// Score of one pair from a label map: the on-chip kernel, or the integral
+// image and the integral score for banks the on-chip kernel does not take.
+vqnnf_status enqueue_score_labels(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* lab, int H,
+                                  int W, float* heatmap, unsigned long long* key) {
+  if (fused_supported(t->t)) return enqueue_score(c, t, lab, nullptr, H, W, heatmap, key, true);
+  const int k = t->t.k;
+  const int64_t R = (H + kIntTile - 1) / kIntTile, S = (W + kIntTile - 1) / kIntTile;
+  IntegralArgs a{};
+  a.labels = lab;
+  a.H = H;
+  a.W = W;
+  a.k = k;
+  a.P = (int32_t*)c->int_p.p;
+  a.rsh = (int32_t*)c->int_side.p;
+  a.cbh = a.rsh + (size_t)H * S * k;
+  a.th = a.cbh + (size_t)R * W * k;
+  HIP_TRY(launch_integral(a, c->stream));
+  return enqueue_score(c, t, nullptr, a.P, H, W, heatmap, key, true);
+}
+
 // Scratch for matching the given pairs one after another (sized for the largest).
 vqnnf_status pair_scratch(vqnnf_ctx* c, const vqnnf_template* const* t, const vqnnf_fmap* const* q,
                           int n, int prec, size_t control) {
@@ -535,20 +567,7 @@ vqnnf_status enqueue_pair(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fma
   uint8_t* lab = (uint8_t*)c->labels.p;
   vqnnf_status s = run_assign(c, t, q, prec, lab, counter_zeroed);
   if (s) return s;
-  if (fused_supported(t->t)) return enqueue_score(c, t, lab, nullptr, q->H, q->W, heatmap, key, true);
-  const int k = t->t.k;
-  const int64_t R = (q->H + kIntTile - 1) / kIntTile, S = (q->W + kIntTile - 1) / kIntTile;
-  IntegralArgs a{};
-  a.labels = lab;
-  a.H = q->H;
-  a.W = q->W;
-  a.k = k;
-  a.P = (int32_t*)c->int_p.p;
-  a.rsh = (int32_t*)c->int_side.p;
-  a.cbh = a.rsh + (size_t)q->H * S * k;
-  a.th = a.cbh + (size_t)R * q->W * k;
-  HIP_TRY(launch_integral(a, c->stream));
-  return enqueue_score(c, t, nullptr, a.P, q->H, q->W, heatmap, key, true);
+  return enqueue_score_labels(c, t, lab, q->H, q->W, heatmap, key);
 }
 
 }  // namespace
@@ -594,9 +613,12 @@ void vqnnf_ctx_destroy(vqnnf_ctx* c) {
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     Buffer* bs[] = {&c->control, &c->labels, &c->wl_pix, &c->wl_mask, &c->int_side, &c->int_p,
-                    &c->partials, &c->keys};
+                    &c->partials, &c->keys, &c->m_labels, &c->m_count, &c->m_wl_pix, &c->m_wl_mask};
     for (Buffer* b : bs)
       if (b->p) hipFree(b->p);
+    for (auto& mp : c->mplans)
+      for (Buffer* b : {&mp.frag, &mp.cnorm, &mp.passes, &mp.outs})
+        if (b->p) hipFree(b->p);
     for (auto& r : c->pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
     for (auto e : c->pool) hipEventDestroy(e);
   }
@@ -817,6 +839,176 @@ vqnnf_status vqnnf_match(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap
   return read_best(c, q->W - t->t.w + 1, best_xy, best_score);
 }
 
+namespace {
+
+// Pairs that share one query map (same pointer, layout and scales).
+std::vector<std::vector<int>> group_by_map(int n, const vqnnf_fmap* const* q) {
+  std::vector<std::vector<int>> groups;
+  auto same = [](const vqnnf_fmap* a, const vqnnf_fmap* b) {
+    const int64_t sa = a->pixel_stride ? a->pixel_stride : a->D;
+    const int64_t sb = b->pixel_stride ? b->pixel_stride : b->D;
+    return a->data == b->data && a->dtype == b->dtype && a->H == b->H && a->W == b->W &&
+           a->D == b->D && sa == sb && a->channel_scale == b->channel_scale;
+  };
+  for (int i = 0; i < n; ++i) {
+    bool placed = false;
+    for (auto& gr : groups)
+      if (same(q[gr[0]], q[i])) {
+        gr.push_back(i);
+        placed = true;
+        break;
+      }
+    if (!placed) groups.push_back({i});
+  }
+  return groups;
+}
+
+int pow2_blocks(int kb) { return kb <= 1 ? 1 : kb <= 2 ? 2 : kb <= 4 ? 4 : 8; }
+
+// Can the group's assignment run as one fused multi-template launch?
+bool multi_ok(const std::vector<int>& gr, const vqnnf_template* const* t, const vqnnf_fmap* q0,
+              int prec) {
+  if (gr.size() < 2 || prec != VQNNF_PREC_BF16_REFINED) return false;
+  if (q0->dtype != VQNNF_BF16 && q0->dtype != VQNNF_FP8_E4M3) return false;
+  if (q0->D % 64 != 0) return false;
+  const int eb = q0->dtype == VQNNF_BF16 ? 2 : 1, al = q0->dtype == VQNNF_BF16 ? 16 : 8;
+  const int64_t st = q0->pixel_stride ? q0->pixel_stride : q0->D;
+  if ((uintptr_t)q0->data % al != 0 || (st * eb) % al != 0) return false;
+  int per_sb[9] = {};
+  for (int i : gr) {
+    if (t[i]->t.geom.kb > 8) return false;
+    per_sb[pow2_blocks(t[i]->t.geom.kb)]++;
+  }
+  int passes = 0;   // templates of one block size share passes of 8 blocks
+  for (int sb : {1, 2, 4, 8}) passes += (per_sb[sb] * sb + 7) / 8;
+  return passes <= kMultiMaxPass && gr.size() <= 1024;
+}
+
+// Pass plan of one map group: templates sorted by padded block count, packed
+// 8 blocks per pass; fragments, norms, pass and output tables on the device.
+vqnnf_status build_multi_plan(vqnnf_ctx* c, vqnnf_ctx::MultiPlan& mp, const std::vector<int>& gr,
+                              const vqnnf_template* const* t, const vqnnf_fmap* q0,
+                              const std::vector<const ScaledSet*>& sets, int64_t n_pix) {
+  std::vector<uint64_t> sig = {(uint64_t)q0->D, (uint64_t)q0->dtype, (uint64_t)n_pix,
+                               (uint64_t)(uintptr_t)c->m_labels.p, (uint64_t)(uintptr_t)c->m_count.p,
+                               (uint64_t)(uintptr_t)c->m_wl_pix.p, (uint64_t)(uintptr_t)c->m_wl_mask.p};
+  for (int i : gr) sig.insert(sig.end(), {(uint64_t)(uintptr_t)t[i], (uint64_t)(uintptr_t)sets[i]});
+  if (sig == mp.sig) return ok();
+  // order: largest blocks first, stable within a size
+  std::vector<int> order(gr.size());
+  for (size_t k = 0; k < gr.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return pow2_blocks(t[gr[a]]->t.geom.kb) > pow2_blocks(t[gr[b]]->t.geom.kb);
+  });
+  std::vector<MultiPass> passes;
+  std::vector<int> slot_pair;
+  for (size_t k = 0; k < order.size();) {
+    const int sb = pow2_blocks(t[gr[order[k]]]->t.geom.kb);
+    MultiPass ps{sb, (int)slot_pair.size(), 0, 0};
+    while (k < order.size() && pow2_blocks(t[gr[order[k]]]->t.geom.kb) == sb && ps.n_seg < 8 / sb) {
+      slot_pair.push_back(order[k]);
+      ++ps.n_seg;
+      ++k;
+    }
+    passes.push_back(ps);
+  }
+  // kernels of an earlier batch may still read the plan being replaced
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const int ngr = t[gr[0]]->t.geom.d_pad_bf16 / 32;
+  const int np = (int)passes.size();
+  const size_t fbytes = (size_t)np * ngr * 2 * 8 * 64 * 16;
+  vqnnf_status s;
+  if ((s = ensure(c, mp.frag, fbytes, "batched codebook fragments")) ||
+      (s = ensure(c, mp.cnorm, (size_t)np * 128 * 4, "batched codeword norms")) ||
+      (s = ensure(c, mp.passes, (size_t)np * sizeof(MultiPass), "batched pass table")) ||
+      (s = ensure(c, mp.outs, slot_pair.size() * sizeof(MultiOut), "batched output table")))
+    return s;
+  HIP_TRY(hipMemset(mp.frag.p, 0, fbytes));
+  std::vector<float> pad((size_t)np * 128, 3.0e38f);
+  HIP_TRY(hipMemcpy(mp.cnorm.p, pad.data(), pad.size() * 4, hipMemcpyHostToDevice));
+  std::vector<MultiOut> outs(slot_pair.size());
+  for (int pi = 0; pi < np; ++pi) {
+    const MultiPass& ps = passes[pi];
+    for (int sg = 0; sg < ps.n_seg; ++sg) {
+      const int slot = ps.tmpl0 + sg;
+      const int i = gr[slot_pair[slot]];
+      const DeviceTemplate& d = t[i]->t;
+      const ScaledSet* ss = sets[i];
+      const int kb = d.geom.kb;
+      // rows (group, term) of kb*64 fragments, placed at block sg*sb of the pass
+      const uint4* src = ss ? ss->d_frag_bf16 : d.d_frag_bf16;
+      uint4* dst = (uint4*)mp.frag.p + (size_t)pi * ngr * 2 * 8 * 64 + (size_t)sg * ps.sb * 64;
+      HIP_TRY(hipMemcpy2D(dst, 8 * 64 * 16, src, (size_t)kb * 64 * 16, (size_t)kb * 64 * 16,
+                          (size_t)ngr * 2, hipMemcpyDeviceToDevice));
+      HIP_TRY(hipMemcpy((float*)mp.cnorm.p + (size_t)pi * 128 + sg * ps.sb * 16, d.d_cnorm,
+                        (size_t)kb * 16 * 4, hipMemcpyDeviceToDevice));
+      const BoundCoef& b = ss ? ss->bound : d.bound_bf16q;
+      MultiOut& o = outs[slot];
+      o.labels = (uint8_t*)c->m_labels.p + (size_t)slot * n_pix;
+      o.wl_count = (uint32_t*)c->m_count.p + slot;
+      o.wl_pix = (uint32_t*)c->m_wl_pix.p + (size_t)slot * n_pix;
+      o.wl_mask = (uint32_t*)c->m_wl_mask.p + (size_t)slot * n_pix * 4;
+      o.a0 = b.a0;
+      o.a1 = b.a1;
+      o.a2 = b.a2;
+    }
+  }
+  HIP_TRY(hipMemcpy(mp.passes.p, passes.data(), passes.size() * sizeof(MultiPass), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(mp.outs.p, outs.data(), outs.size() * sizeof(MultiOut), hipMemcpyHostToDevice));
+  mp.n_pass = np;
+  mp.slot_pair = slot_pair;
+  mp.sig = sig;
+  return ok();
+}
+
+// Enqueues a fused map group: one multi-template assignment, then per
+// template its FP64 re-score and its score.
+vqnnf_status enqueue_multi(vqnnf_ctx* c, const vqnnf_ctx::MultiPlan& mp, const std::vector<int>& gr,
+                           const vqnnf_template* const* t, const vqnnf_fmap* const* q,
+                           const std::vector<const ScaledSet*>& sets, float* const* heatmaps,
+                           unsigned long long* keys) {
+  const vqnnf_fmap* q0 = q[gr[0]];
+  const int64_t n_pix = (int64_t)q0->H * q0->W;
+  const int nt = (int)gr.size();
+  HIP_TRY(launch_fill_u32((uint32_t*)c->m_count.p, 0u, nt, c->stream));
+  MultiArgs ma{};
+  ma.kp.q = q0->data;
+  ma.kp.stride = q0->pixel_stride ? q0->pixel_stride : q0->D;
+  ma.kp.n_pix = n_pix;
+  ma.kp.D = q0->D;
+  ma.kp.frag = (const uint4*)mp.frag.p;
+  ma.kp.cnorm = (const float*)mp.cnorm.p;
+  ma.kp.n_groups = t[gr[0]]->t.geom.d_pad_bf16 / 32;
+  ma.kp.n_pass = mp.n_pass;
+  ma.kp.passes = (const MultiPass*)mp.passes.p;
+  ma.kp.outs = (const MultiOut*)mp.outs.p;
+  ma.fp8 = q0->dtype == VQNNF_FP8_E4M3;
+  HIP_TRY(launch_assign_multi(ma, c->stream, c->n_cu));
+  for (int slot = 0; slot < nt; ++slot) {
+    const int i = gr[mp.slot_pair[slot]];
+    const DeviceTemplate& d = t[i]->t;
+    uint8_t* lab = (uint8_t*)c->m_labels.p + (size_t)slot * n_pix;
+    AssignArgs a{};
+    a.q = q0->data;
+    a.stride = ma.kp.stride;
+    a.n_pix = n_pix;
+    a.D = q0->D;
+    a.dtype = q0->dtype;
+    a.t = &d;
+    a.scale = sets[i] ? sets[i]->d_scale : nullptr;
+    a.labels = lab;
+    a.wl_count = (uint32_t*)c->m_count.p + slot;
+    a.wl_pix = (uint32_t*)c->m_wl_pix.p + (size_t)slot * n_pix;
+    a.wl_mask = (uint32_t*)c->m_wl_mask.p + (size_t)slot * n_pix * 4;
+    HIP_TRY(launch_rescore(a, c->stream, c->n_cu));
+    vqnnf_status s = enqueue_score_labels(c, t[i], lab, q0->H, q0->W, heatmaps[i], keys + i);
+    if (s) return s;
+  }
+  return ok();
+}
+
+}  // namespace
+
 vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* const* t,
                                  const vqnnf_fmap* const* q, int32_t prec, float* const* heatmaps,
                                  int32_t* best_xy, float* best_score) {
@@ -838,12 +1030,43 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     if ((s = prepare_scaled(c, t[i], q[i], &sets[i]))) return s;
   if ((s = check_cap(c, {{&c->keys, (size_t)n * 8}}))) return s;
   if ((s = ensure(c, c->keys, (size_t)n * 8, "best-location keys"))) return s;
+  // map groups that take the fused multi-template assignment
+  const std::vector<std::vector<int>> groups = group_by_map(n, q);
+  std::vector<char> fused(groups.size(), 0);
+  size_t ml = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    fused[gi] = multi_ok(groups[gi], t, q[groups[gi][0]], prec);
+    if (fused[gi]) ml = std::max(ml, groups[gi].size() * (size_t)q[groups[gi][0]]->H * q[groups[gi][0]]->W);
+  }
+  if (ml) {
+    if ((s = check_cap(c, {{&c->m_labels, ml}, {&c->m_count, 4096}, {&c->m_wl_pix, ml * 4},
+                           {&c->m_wl_mask, ml * 16}})) ||
+        (s = ensure(c, c->m_labels, ml, "batched label maps")) ||
+        (s = ensure(c, c->m_count, 4096, "batched worklist counters")) ||
+        (s = ensure(c, c->m_wl_pix, ml * 4, "batched re-score worklists")) ||
+        (s = ensure(c, c->m_wl_mask, ml * 16, "batched candidate masks")))
+      return s;
+  }
+  if (c->mplans.size() < groups.size()) c->mplans.resize(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    if (!fused[gi]) continue;
+    const vqnnf_fmap* q0 = q[groups[gi][0]];
+    if ((s = build_multi_plan(c, c->mplans[gi], groups[gi], t, q0, sets, (int64_t)q0->H * q0->W)))
+      return s;
+  }
   unsigned long long* keys = (unsigned long long*)c->keys.p;
   auto enqueue_all = [&]() -> vqnnf_status {
     HIP_TRY(launch_fill_u32((uint32_t*)keys, 0u, 2 * (int64_t)n, c->stream));
-    for (int i = 0; i < n; ++i) {
-      vqnnf_status st = enqueue_pair(c, t[i], q[i], prec, heatmaps[i], keys + i, false);
-      if (st) return st;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      if (fused[gi]) {
+        vqnnf_status st = enqueue_multi(c, c->mplans[gi], groups[gi], t, q, sets, heatmaps, keys);
+        if (st) return st;
+        continue;
+      }
+      for (int i : groups[gi]) {
+        vqnnf_status st = enqueue_pair(c, t[i], q[i], prec, heatmaps[i], keys + i, false);
+        if (st) return st;
+      }
     }
     return ok();
   };
@@ -851,12 +1074,23 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     HookScope hs(c);
     if ((s = enqueue_all())) return s;
   } else {
-    // every argument the captured kernels depend on, scratch addresses included
+    // every argument the captured kernels depend on, scratch and plans included
     std::vector<uint64_t> sig = {(uint64_t)n, (uint64_t)prec, (uint64_t)(uintptr_t)c->stream,
                                  (uint64_t)(uintptr_t)c->control.p, (uint64_t)(uintptr_t)c->labels.p,
                                  (uint64_t)(uintptr_t)c->wl_pix.p, (uint64_t)(uintptr_t)c->wl_mask.p,
                                  (uint64_t)(uintptr_t)c->partials.p, (uint64_t)(uintptr_t)c->int_side.p,
-                                 (uint64_t)(uintptr_t)c->int_p.p, (uint64_t)(uintptr_t)keys};
+                                 (uint64_t)(uintptr_t)c->int_p.p, (uint64_t)(uintptr_t)keys,
+                                 (uint64_t)(uintptr_t)c->m_labels.p, (uint64_t)(uintptr_t)c->m_count.p,
+                                 (uint64_t)(uintptr_t)c->m_wl_pix.p, (uint64_t)(uintptr_t)c->m_wl_mask.p};
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      sig.push_back(fused[gi] ? 1u : 0u);
+      if (fused[gi]) {
+        const auto& mp = c->mplans[gi];
+        sig.insert(sig.end(), {(uint64_t)(uintptr_t)mp.frag.p, (uint64_t)(uintptr_t)mp.cnorm.p,
+                               (uint64_t)(uintptr_t)mp.passes.p, (uint64_t)(uintptr_t)mp.outs.p});
+        sig.insert(sig.end(), mp.sig.begin(), mp.sig.end());
+      }
+    }
     for (int i = 0; i < n; ++i) {
       const vqnnf_fmap& m = *q[i];
       sig.insert(sig.end(), {(uint64_t)(uintptr_t)t[i], (uint64_t)(uintptr_t)m.data, (uint64_t)m.dtype,

@@ -125,6 +125,36 @@ struct AssignArgs {
   BoundCoef bound;
 };
 
+// Fused assignment of several templates against one map (batched matching).
+constexpr int kMultiMaxPass = 32;    // passes of 128 codewords per launch
+struct MultiPass {                   // one pass: n_seg templates of sb blocks each
+  int sb, tmpl0, n_seg, pad;
+};
+struct MultiOut {                    // per template: outputs and error bound
+  uint8_t* labels;
+  uint32_t* wl_count;
+  uint32_t* wl_pix;
+  uint32_t* wl_mask;                 // [n_pix][(sb+1)/2]
+  float a0, a1, a2, pad;
+};
+struct MultiParams {
+  const void* q;
+  int64_t stride;
+  int64_t n_pix;
+  int D;
+  const uint4* frag;                 // [n_pass][n_groups][2][8][64] BF16 fragment pairs
+  const float* cnorm;                // [n_pass][128] ||c||^2 (pad 3e38)
+  int n_groups, n_pass;
+  int64_t n_tiles;
+  const MultiPass* passes;
+  const MultiOut* outs;
+};
+struct MultiArgs {
+  MultiParams kp;
+  bool fp8;
+};
+hipError_t launch_assign_multi(const MultiArgs& a, hipStream_t s, int n_cu);
+
 hipError_t launch_assign_plain(const AssignArgs& a, hipStream_t s, int n_cu);
 hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu);
 hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu);
@@ -162,7 +192,7 @@ hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
 // Kernel-name registry for timing.
 enum KernelId {
   K_FILL = 0, K_ASSIGN_PLAIN, K_ASSIGN_REFINED, K_RESCORE, K_INT_EDGE, K_INT_PREFIX,
-  K_INT_MAIN, K_SCORE_FUSED, K_SCORE_COMBINE, K_SCORE_INTEGRAL, K_COUNT
+  K_INT_MAIN, K_SCORE_FUSED, K_SCORE_COMBINE, K_SCORE_INTEGRAL, K_ASSIGN_MULTI, K_COUNT
 };
 const char* kernel_name(int id);
 

@@ -100,6 +100,23 @@ def test_batched_one_map_many_templates(ctx, prec):
             check_oracle(wl, tpls[i], *meta[i], heats[i])
 
 
+def test_batched_fused_pass_packing(ctx):
+    """13 templates on one map: k = 48 pads to 4 blocks, k = 128 fills a pass,
+    k = 16 templates spill into a second pass of their size."""
+    wl = synth.make_multi_template(53, 96, 112, 128, 32, 0.3, "bf16", 13, (10, 32), (16, 48, 128, 32), 2)
+    ks = sorted(t.k for t in wl.templates[0])
+    log("k per template:", ks)
+    tpls, fms, heats, meta, _ = make_pairs(ctx, wl)
+    P = B.VQNNF_PREC_BF16_REFINED
+    out = B.vqnnf_match_batched(ctx, tpls, fms, P, heats)
+    refs, bests = per_pair(ctx, tpls, fms, heats, P)
+    for i in range(len(tpls)):
+        assert torch.equal(heats[i], refs[i]), f"pair {i} (k={tpls[i].k})"
+        assert out[i] == bests[i]
+    for i in (ks.index(128) if 128 in ks else 0, len(tpls) - 1):
+        check_oracle(wl, tpls[i], *meta[i], heats[i])
+
+
 def test_batched_uneven_maps(ctx):
     wl = synth.make_multi_map(43, 3, (64, 192), 48, 32, 0.3, "bf16", 2, (16, 40), 32, 3)
     tpls, fms, heats, meta, _ = make_pairs(ctx, wl)
