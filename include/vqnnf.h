@@ -202,6 +202,14 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* ctx, int32_t n_pairs, const vqnnf_te
                                  const vqnnf_fmap* const* q, int32_t prec, float* const* heatmaps,
                                  int32_t* best_xy, float* best_score);
 
+/* Autotuning of the on-chip score's tile height (1 = on, the default): the
+ * first call for a shape (template size, grid, codebook size, map size)
+ * times a few tile heights on that call's own data (each run writes the same
+ * result) and keeps the fastest; calls made while a graph is captured use the
+ * tuned value if there is one, else the default sizing.  0 turns it off and
+ * forgets tuned values. */
+vqnnf_status vqnnf_ctx_set_autotune(vqnnf_ctx* ctx, int32_t enable);
+
 /* Graph mode for vqnnf_match_batched (0 = off, the default: kernels are
  * launched one by one).  Turning it off releases the captured graph. */
 vqnnf_status vqnnf_ctx_set_graph(vqnnf_ctx* ctx, int32_t enable);

@@ -26,6 +26,7 @@ EXPORTED = [
     "vqnnf_template_codebook", "vqnnf_template_labels", "vqnnf_template_counts",
     "vqnnf_template_weights", "vqnnf_assign", "vqnnf_filter", "vqnnf_score",
     "vqnnf_score_integral", "vqnnf_match", "vqnnf_match_batched", "vqnnf_ctx_set_graph",
+    "vqnnf_ctx_set_autotune",
     "vqnnf_ctx_set_timing", "vqnnf_ctx_kernel_times",
     "vqnnf_ctx_reset_times", "vqnnf_last_error", "vqnnf_version",
 ]
@@ -80,6 +81,7 @@ def lib() -> C.CDLL:
         "vqnnf_match": (st, [vp, vp, P(FMap), i32, vp, P(i32), P(C.c_float)]),
         "vqnnf_match_batched": (st, [vp, i32, P(vp), P(P(FMap)), i32, P(vp), P(i32), P(C.c_float)]),
         "vqnnf_ctx_set_graph": (st, [vp, i32]),
+        "vqnnf_ctx_set_autotune": (st, [vp, i32]),
         "vqnnf_ctx_set_timing": (st, [vp, i32]),
         "vqnnf_ctx_kernel_times": (st, [vp, i32, P(C.c_char_p), P(i64), P(C.c_double), P(i32)]),
         "vqnnf_ctx_reset_times": (st, [vp]),
@@ -315,6 +317,10 @@ def vqnnf_match_batched(ctx: Context, templates: Sequence[Template], queries: Se
     sc = (C.c_float * n)()
     _check(lib().vqnnf_match_batched(ctx.h, n, th, qp, prec, hp, xy, sc))
     return [((xy[2 * i], xy[2 * i + 1]), sc[i]) for i in range(n)]
+
+
+def vqnnf_ctx_set_autotune(ctx: Context, enable: bool) -> None:
+    _check(lib().vqnnf_ctx_set_autotune(ctx.h, 1 if enable else 0))
 
 
 def vqnnf_ctx_set_graph(ctx: Context, enable: bool) -> None:

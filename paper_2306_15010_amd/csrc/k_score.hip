@@ -411,14 +411,10 @@ hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_byt
   if (!t.grid.valid || !a.partials) return hipErrorInvalidValue;
   TilePlan pl = plan_tile(t);
   if (!pl.ok) return hipErrorInvalidConfiguration;
-  // equal tile widths; tile height so that the blocks fill whole rounds of
-  // two blocks per compute unit
+  // equal tile widths; tile height from the caller (autotuned) or the default
   const int nx = (ow + pl.txw - 1) / pl.txw;
   pl.txw = (ow + nx - 1) / nx;
-  const int per_row = nx * (t.geom.kpad / kKG);
-  const int slots = 2 * std::max(a.n_cu, 1);
-  const int ny = std::max(1, (slots + per_row - 1) / per_row);
-  pl.tyw = std::max(8, (oh + ny - 1) / ny);
+  pl.tyw = a.tyw > 0 ? std::min(a.tyw, oh) : fused_default_tyw(t, a.H, a.W, a.n_cu);
   TileParams tp{};
   tp.labels = a.labels;
   tp.H = a.H;
@@ -473,6 +469,17 @@ hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_byt
 }
 
 bool fused_supported(const DeviceTemplate& t) { return plan_tile(t).ok; }
+
+// Tiles fill whole rounds of two blocks per compute unit (at least 8 rows).
+int fused_default_tyw(const DeviceTemplate& t, int H, int W, int n_cu) {
+  TilePlan pl = plan_tile(t);
+  const int ow = W - t.w + 1, oh = H - t.h + 1;
+  const int nx = (ow + pl.txw - 1) / std::max(pl.txw, 1);
+  const int per_row = nx * (t.geom.kpad / kKG);
+  const int slots = 2 * std::max(n_cu, 1);
+  const int ny = std::max(1, (slots + per_row - 1) / per_row);
+  return std::min(std::max(8, (oh + ny - 1) / ny), std::max(oh, 1));
+}
 
 hipError_t launch_score_integral(const ScoreArgs& a, hipStream_t s) {
   const DeviceTemplate& t = *a.t;

@@ -10,6 +10,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "vqnnf_internal.h"
@@ -83,6 +84,10 @@ struct vqnnf_ctx {
     std::vector<int> slot_pair;        // output slot -> index in the map group
   };
   std::vector<MultiPlan> mplans;       // one per map group of the last batch
+  // autotuned window rows per score tile, by shape (w, h, g, kpad, H, W, uniform bins)
+  bool autotune = true;
+  bool capturing = false;
+  std::map<std::vector<int>, int> tyw_cache;
   // batched calls captured into a graph (vqnnf_ctx_set_graph)
   bool graph = false;
   hipStream_t cap_stream = nullptr;
@@ -496,6 +501,47 @@ vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t*
   if (!zeroed) HIP_TRY(launch_zero_u64(a.best, c->stream));
   if (labels) {
     size_t lds = 0;
+    const DeviceTemplate& d = t->t;
+    bool uni = true;
+    for (int f = 2; f < d.n_filters; ++f) uni = uni && d.weights[f] == d.weights[1];
+    const std::vector<int> key = {d.w, d.h, d.grid.g, d.geom.kpad, H, W, uni ? 1 : 0};
+    auto it = c->tyw_cache.find(key);
+    if (it != c->tyw_cache.end()) {
+      a.tyw = it->second;
+    } else if (c->autotune && !c->capturing) {
+      // time each candidate tile height twice on this very call (every run
+      // writes the same heatmap and key), keep the fastest for the shape
+      const int oh = H - d.h + 1;
+      const int def = fused_default_tyw(d, H, W, c->n_cu);
+      std::vector<int> cand = {def};
+      for (int v : {16, 32, 64, 128, 256})
+        if (v <= oh && std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
+      set_timing_hook(nullptr);
+      std::vector<hipEvent_t> ev(2 * cand.size());
+      for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+      for (int rep = 0; rep < 2; ++rep)
+        for (size_t ci = 0; ci < cand.size(); ++ci) {
+          a.tyw = cand[ci];
+          if (rep == 1) HIP_TRY(hipEventRecord(ev[2 * ci], c->stream));
+          HIP_TRY(launch_score_fused(a, c->stream, &lds));
+          if (rep == 1) HIP_TRY(hipEventRecord(ev[2 * ci + 1], c->stream));
+        }
+      HIP_TRY(hipEventSynchronize(ev.back()));
+      float best_ms = 1e30f;
+      int best = def;
+      for (size_t ci = 0; ci < cand.size(); ++ci) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[2 * ci], ev[2 * ci + 1]));
+        if (ms < best_ms) { best_ms = ms; best = cand[ci]; }
+      }
+      for (auto& e : ev) hipEventDestroy(e);
+      if (c->timing) {
+        TimingHook h{hook_begin, hook_end, c};
+        set_timing_hook(&h);
+      }
+      c->tyw_cache[key] = best;
+      return ok();   // the last candidate's run already produced the result
+    }
     HIP_TRY(launch_score_fused(a, c->stream, &lds));
   } else {
     HIP_TRY(launch_score_integral(a, c->stream));
@@ -1030,8 +1076,30 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     if ((s = prepare_scaled(c, t[i], q[i], &sets[i]))) return s;
   if ((s = check_cap(c, {{&c->keys, (size_t)n * 8}}))) return s;
   if ((s = ensure(c, c->keys, (size_t)n * 8, "best-location keys"))) return s;
-  // map groups that take the fused multi-template assignment
-  const std::vector<std::vector<int>> groups = group_by_map(n, q);
+  // map groups that take the fused multi-template assignment; a group whose
+  // templates need more passes than one launch holds is split
+  std::vector<std::vector<int>> groups;
+  for (auto& gr : group_by_map(n, q)) {
+    std::vector<int> cur;
+    int per_sb[9] = {};
+    auto passes = [&]() {
+      int p = 0;
+      for (int sb : {1, 2, 4, 8}) p += (per_sb[sb] * sb + 7) / 8;
+      return p;
+    };
+    for (int i : gr) {
+      const int sb = pow2_blocks(std::min(t[i]->t.geom.kb, 8));
+      per_sb[sb]++;
+      if (passes() > kMultiMaxPass || cur.size() >= 1024) {
+        groups.push_back(cur);
+        cur.clear();
+        for (int& v : per_sb) v = 0;
+        per_sb[sb] = 1;
+      }
+      cur.push_back(i);
+    }
+    groups.push_back(cur);
+  }
   std::vector<char> fused(groups.size(), 0);
   size_t ml = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -1098,13 +1166,26 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
                              (uint64_t)(uintptr_t)sets[i], (uint64_t)(uintptr_t)heatmaps[i]});
     }
     if (!(c->gexec && sig == c->gsig)) {
+      // shapes not tuned yet are tuned by one eager run before the capture
+      bool untuned = false;
+      for (int i = 0; i < n && c->autotune; ++i) {
+        const DeviceTemplate& d = t[i]->t;
+        if (!fused_supported(d)) continue;
+        bool uni = true;
+        for (int f = 2; f < d.n_filters; ++f) uni = uni && d.weights[f] == d.weights[1];
+        const std::vector<int> key = {d.w, d.h, d.grid.g, d.geom.kpad, q[i]->H, q[i]->W, uni ? 1 : 0};
+        untuned = untuned || c->tyw_cache.find(key) == c->tyw_cache.end();
+      }
+      if (untuned && (s = enqueue_all())) return s;
       if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
       // the capture stream waits for earlier work on the context stream
       HIP_TRY(hipStreamSynchronize(c->stream));
       HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
       hipStream_t user = c->stream;
       c->stream = c->cap_stream;
+      c->capturing = true;
       vqnnf_status st = enqueue_all();
+      c->capturing = false;
       c->stream = user;
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -1136,6 +1217,14 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     }
     if (best_score) best_score[i] = unpack_score(hk[i]);
   }
+  return ok();
+}
+
+vqnnf_status vqnnf_ctx_set_autotune(vqnnf_ctx* c, int32_t enable) {
+  vqnnf_status s = check_ctx(c);
+  if (s) return s;
+  c->autotune = enable != 0;
+  if (!c->autotune) c->tyw_cache.clear();
   return ok();
 }
 

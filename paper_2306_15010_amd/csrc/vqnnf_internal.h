@@ -126,7 +126,7 @@ struct AssignArgs {
 };
 
 // Fused assignment of several templates against one map (batched matching).
-constexpr int kMultiMaxPass = 32;    // passes of 128 codewords per launch
+constexpr int kMultiMaxPass = 96;    // passes of 128 codewords per launch (norms in LDS)
 struct MultiPass {                   // one pass: n_seg templates of sb blocks each
   int sb, tmpl0, n_seg, pad;
 };
@@ -180,6 +180,7 @@ struct ScoreArgs {
   unsigned long long* best;    // packed (orderable score, ~index), must be 0
   void* partials;              // on-chip path: per channel group partial sums
   int n_cu;                    // compute units (tile sizing)
+  int tyw;                     // on-chip path: window rows per tile, 0 = default sizing
 };
 hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out);
 hipError_t launch_score_integral(const ScoreArgs& a, hipStream_t s);
@@ -187,6 +188,8 @@ hipError_t launch_score_integral(const ScoreArgs& a, hipStream_t s);
 bool fused_supported(const DeviceTemplate& t);
 // Scratch bytes of the on-chip path's per-channel-group partial sums.
 size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W);
+// Default window rows per tile of the on-chip score for this shape.
+int fused_default_tyw(const DeviceTemplate& t, int H, int W, int n_cu);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
 
 // Kernel-name registry for timing.

@@ -170,3 +170,27 @@ def test_batched_graph_replays(ctx):
     assert out_flip == bests
     for i in range(len(heats)):
         assert torch.equal(heats2[i], refs[i])
+
+
+def test_autotune_keeps_results(ctx):
+    """The tile height changes only the schedule: the default, the tuning call
+    and the cached choice give the same heatmap bit for bit, and so does a
+    graph captured right after its tuning run."""
+    wl = synth.make_multi_template(59, 200, 176, 64, 32, 0.3, "bf16", 2, (20, 40), (32, 64), 3)
+    tpls, fms, heats, meta, _ = make_pairs(ctx, wl)
+    P = B.VQNNF_PREC_BF16_REFINED
+    B.vqnnf_ctx_set_autotune(ctx, False)
+    ref = B.vqnnf_match_batched(ctx, tpls, fms, P, heats)
+    ref_h = [h.clone() for h in heats]
+    B.vqnnf_ctx_set_graph(ctx, True)
+    try:
+        B.vqnnf_ctx_set_autotune(ctx, True)     # empty cache: an eager run tunes, then capture
+        assert B.vqnnf_match_batched(ctx, tpls, fms, P, heats) == ref
+        assert all(torch.equal(a, b) for a, b in zip(heats, ref_h))
+    finally:
+        B.vqnnf_ctx_set_graph(ctx, False)
+    for rep in range(2):                        # first: tunes on this call, then cached
+        for h in heats:
+            h.fill_(float("nan"))
+        assert B.vqnnf_match_batched(ctx, tpls, fms, P, heats) == ref, rep
+        assert all(torch.equal(a, b) for a, b in zip(heats, ref_h)), rep
