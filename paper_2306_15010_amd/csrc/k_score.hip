@@ -105,7 +105,8 @@ struct TileParams {
   int kpad;
   int xe[5], ye[5];
   const uint32_t* t16;  // [nf][kpad/2] template counts, u16 pairs
-  uint32_t* part;       // [n_groups][nacc][oh*ow] sums of min(T_j, C_j)
+  uint32_t* part;       // [n_groups][nacc][pstride] sums of min(T_j, C_j)
+  int64_t pstride;      // windows per partial row, oh*ow rounded up to 4
 };
 
 typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
@@ -141,7 +142,6 @@ __global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
   const int txv = min(p.txw, p.ow - x0), tyv = min(p.tyw, p.oh - y0);
   const int cols = txv + p.w - 1;
   const int nseg = cols / kSL + 1;                   // segments cover [0, cols]
-  const int64_t nwin = (int64_t)p.ow * p.oh;
   uint32_t* Q32 = (uint32_t*)&Qs[0][0];
   // channel jl of the group lives in row b*kPQ + jl/8, word (jl/2)%4, half jl%2
   auto qword = [&](int b, int jl, int c) -> uint32_t* {
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
   auto store_row = [&](int yy) {  // pair group 0 adds group 1's sums
     const int64_t win = (int64_t)yy * p.ow + x0 + xl;
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) p.part[((int64_t)grp * NACC + a) * nwin + win] = acc[a] + red[a][xl];
+    for (int a = 0; a < NACC; ++a) p.part[((int64_t)grp * NACC + a) * p.pstride + win] = acc[a] + red[a][xl];
   };
   for (int dy = 0; dy < tyv; ++dy) {
     const int y = y0 + dy;
@@ -266,7 +266,8 @@ __global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
 // Adds the groups' integer sums, forms eq. 2 and the argmax.
 struct CombineParams {
   const uint32_t* part;
-  int64_t nwin;
+  int64_t nwin, pstride;
+  bool vec_out;       // heatmap 16-byte aligned
   int ngroups;
   float wt[17];       // per accumulator weight
   int area2[17];      // per accumulator: twice the summed bin areas
@@ -274,24 +275,46 @@ struct CombineParams {
   unsigned long long* best;
 };
 
+// Four consecutive windows per thread: 16-byte loads of every partial row
+// (rows are padded to a multiple of four windows).
 template <int NACC>
 __global__ __launch_bounds__(256) void score_combine_kernel(CombineParams p) {
-  const int64_t win = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t w0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
   unsigned long long key = 0ull;
-  if (win < p.nwin) {
-    uint32_t m[NACC];
+  if (w0 < p.nwin) {
+    uint4 m[NACC];
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) m[a] = 0u;
-    for (int g = 0; g < p.ngroups; ++g)
+    for (int a = 0; a < NACC; ++a) m[a] = make_uint4(0u, 0u, 0u, 0u);
+    for (int g = 0; g < p.ngroups; ++g) {
+      uint4 v[NACC];
 #pragma unroll
-      for (int a = 0; a < NACC; ++a) m[a] += p.part[((int64_t)g * NACC + a) * p.nwin + win];
+      for (int a = 0; a < NACC; ++a) v[a] = *(const uint4*)(p.part + ((int64_t)g * NACC + a) * p.pstride + w0);
+#pragma unroll
+      for (int a = 0; a < NACC; ++a)
+        m[a] = make_uint4(m[a].x + v[a].x, m[a].y + v[a].y, m[a].z + v[a].z, m[a].w + v[a].w);
+    }
     // sum_j |T_j - C_j| = 2A - 2 sum_j min(T_j, C_j), exact in integers
-    float s = 0.f;
+    float sc[4];
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) s = fmaf(p.wt[a], (float)(p.area2[a] - 2 * (int)m[a]), s);
-    const float score = -s;
-    p.heatmap[win] = score;
-    key = best_key(score, (uint32_t)win);
+    for (int i = 0; i < 4; ++i) {
+      float s = 0.f;
+#pragma unroll
+      for (int a = 0; a < NACC; ++a) {
+        const uint32_t mi = i == 0 ? m[a].x : i == 1 ? m[a].y : i == 2 ? m[a].z : m[a].w;
+        s = fmaf(p.wt[a], (float)(p.area2[a] - 2 * (int)mi), s);
+      }
+      sc[i] = -s;
+    }
+    const int nv = (int)min((int64_t)4, p.nwin - w0);
+    if (nv == 4 && p.vec_out) {
+      *(float4*)(p.heatmap + w0) = make_float4(sc[0], sc[1], sc[2], sc[3]);
+    } else {
+      for (int i = 0; i < nv; ++i) p.heatmap[w0 + i] = sc[i];
+    }
+    for (int i = 0; i < nv; ++i) {
+      const unsigned long long k2 = best_key(sc[i], (uint32_t)(w0 + i));
+      key = k2 > key ? k2 : key;
+    }
   }
   block_max_to(key, p.best);
 }
@@ -385,7 +408,7 @@ hipError_t go_tile_u(const TileParams& tp, bool uni, hipStream_t s) {
 }
 
 hipError_t go_combine(const CombineParams& cp, int nacc, hipStream_t s) {
-  const dim3 grid((unsigned)((cp.nwin + 255) / 256)), blk(256);
+  const dim3 grid((unsigned)((cp.nwin + 1023) / 1024)), blk(256);
   switch (nacc) {
     case 2: hipLaunchKernelGGL((score_combine_kernel<2>), grid, blk, 0, s, cp); break;
     case 5: hipLaunchKernelGGL((score_combine_kernel<5>), grid, blk, 0, s, cp); break;
@@ -402,7 +425,7 @@ size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W) {
   TilePlan pl = plan_tile(t);
   if (!pl.ok) return 0;
   const int64_t nwin = (int64_t)(H - t.h + 1) * (W - t.w + 1);
-  return (size_t)(t.geom.kpad / kKG) * pl.nacc * nwin * 4;
+  return (size_t)(t.geom.kpad / kKG) * pl.nacc * ((nwin + 3) / 4 * 4) * 4;
 }
 
 hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out) {
@@ -433,6 +456,7 @@ hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_byt
   }
   tp.t16 = t.d_counts16;
   tp.part = (uint32_t*)a.partials;
+  tp.pstride = ((int64_t)ow * oh + 3) / 4 * 4;
   if (lds_bytes_out) {
     const int NR = G * kPQ;
     *lds_bytes_out = (size_t)2 * NR * kHS * 16 + (size_t)pl.nacc * kTXW * 4;
@@ -451,6 +475,8 @@ hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_byt
   CombineParams cp{};
   cp.part = tp.part;
   cp.nwin = (int64_t)ow * oh;
+  cp.pstride = tp.pstride;
+  cp.vec_out = ((uintptr_t)a.heatmap % 16) == 0;
   cp.ngroups = tp.kpad / kKG;
   // accumulator a covers filters: UNI -> {0}, {1..NF-1}; else {a}
   for (int f = 0; f < t.n_filters; ++f) {
