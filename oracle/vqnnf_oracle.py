@@ -17,7 +17,9 @@ Contents and the passages they follow:
       computation", Sec. 5.2 "Codebook and NNF Generation")
   O3  nearest-codeword assignment (Alg. 1, Sec. 3.1; exact L2 NN, Sec. 5.2)
   O4  one-hot integral image (Sec. 3.1; Supp. S.2, definition and box sum)
-  O5  filter regions and Alg. 2's dilation filter (Sec. 3.2.1, Supp. S.4)
+  O5  filter regions and Alg. 2's dilation filter (Sec. 3.2.1, Supp. S.4);
+      O5b the paper's Gaussian / Haar coarse filters and sub-scale regions
+      (Sec. 3.2.2, Sec. 3.3, Sec. 5.2 "Filtering")
   O6  template representation R(tau) (Sec. 3.3)
   O7  similarity, eq. 2 (Sec. 3.3)
   O8  localisation: argmax of the heatmap (Sec. 4 "Target Localization")
@@ -350,6 +352,73 @@ def dilated_response(P: np.ndarray, x: int, y: int, fd: np.ndarray,
 
 
 # --------------------------------------------------------------------------
+# O5b: the paper's coarse filters and sub-scale aggregation (Sec. 3.2.2,
+# Sec. 3.3, Sec. 5.2 "Filtering"; Supp. S.3 option c).
+#
+# Readings (the paper gives names and sigma only):
+#   * the Gaussian is the unnormalised 3x3 kernel exp(-(a^2 + b^2) / (2 sigma^2))
+#     at a, b in {-1, 0, 1}, sigma = 2;
+#   * Haar-2x has column factors [+1, 0, -1] and Haar-3x [+1, -2, +1], each
+#     multiplied elementwise by the Gaussian; the y filters are the transposes;
+#   * scale s uses the centred sub-window of floor(w/s) x floor(h/s) starting at
+#     (floor((w - floor(w/s)) / 2), floor((h - floor(h/s)) / 2)) with a 3x3 grid;
+#   * w_{s,f} = w_f / s with w_f = 1 for the Gaussian and 0.25 for Haar filters;
+#   * a filter's response is sum_bins f(a,b) * count(bin) / area(region).
+
+PAPER_FILTER_SETS = {
+    "gauss": ("gauss",),
+    "2rect": ("gauss", "haar2x", "haar2y"),
+    "3rect": ("gauss", "haar3x", "haar3y"),
+    "23rect": ("gauss", "haar2x", "haar2y", "haar3x", "haar3y"),
+}
+
+
+def gaussian_coarse(sigma: float = 2.0) -> np.ndarray:
+    """3x3 coarse Gaussian, indexed [row b][column a], centre 1."""
+    g = np.zeros((3, 3), dtype=np.float64)
+    for b in range(3):
+        for a in range(3):
+            g[b, a] = np.exp(-float((a - 1) ** 2 + (b - 1) ** 2) / (2.0 * sigma * sigma))
+    return g
+
+
+def coarse_filter(name: str) -> np.ndarray:
+    """The 3x3 coarse filter of a filter name, indexed [row b][column a]."""
+    g = gaussian_coarse()
+    if name == "gauss":
+        return g
+    cols = {"haar2": np.array([1.0, 0.0, -1.0]), "haar3": np.array([1.0, -2.0, 1.0])}[name[:5]]
+    hx = g * cols[None, :]            # varies along x (columns)
+    if name.endswith("x"):
+        return hx
+    if name.endswith("y"):
+        return g * cols[:, None]      # varies along y (rows)
+    raise ValueError(name)
+
+
+def subscale_region(w: int, h: int, s: int) -> Tuple[int, int, int, int]:
+    """Centred sub-window of scale s: (x0, y0, x1, y1)."""
+    rw, rh = w // s, h // s
+    x0, y0 = (w - rw) // 2, (h - rh) // 2
+    return x0, y0, x0 + rw, y0 + rh
+
+
+def paper_bank(w: int, h: int, filter_set: str, n_scales: int) -> List[FilterDesc]:
+    """The filter bank of Sec. 5.2: every filter of the set at every scale
+    s = 1..n_scales, scale-major, each one weighted filter over a 3x3 grid."""
+    names = PAPER_FILTER_SETS[filter_set]
+    out: List[FilterDesc] = []
+    for s in range(1, n_scales + 1):
+        x0, y0, x1, y1 = subscale_region(w, h, s)
+        if x1 - x0 < 3 or y1 - y0 < 3:
+            raise ValueError(f"scale {s}: sub-window {x1 - x0}x{y1 - y0} has empty bins")
+        for name in names:
+            wf = 1.0 if name == "gauss" else 0.25
+            out.append(FilterDesc(x0, y0, x1, y1, 3, 3, coarse_filter(name), wf / float(s)))
+    return out
+
+
+# --------------------------------------------------------------------------
 # O6 / O7: filter responses, template representation and the similarity map.
 
 def filter_responses(P: np.ndarray, x: int, y: int, filters: Sequence[Filter]) -> np.ndarray:
@@ -408,9 +477,10 @@ def similarity_map(query_labels: np.ndarray, k: int, w: int, h: int,
 
 def similarity_map_fast(query_labels: np.ndarray, k: int, w: int, h: int,
                         filters: Sequence[Filter], rt: np.ndarray) -> np.ndarray:
-    """Same values as similarity_map for indicator filters, vectorised over
-    windows (per-filter box sums of P for all windows at once); the L1 over
-    channels and the weighted sum keep the same order."""
+    """Same values as similarity_map (indicator or weighted filters),
+    vectorised over windows: per-filter box sums of P for all windows at once,
+    with the boxes, the L1 over channels and the weighted sum in the same
+    order, so every window's value is the same float64 result."""
     H, W = query_labels.shape
     P = integral_image(query_labels, k)
     oh, ow = H - h + 1, W - w + 1
