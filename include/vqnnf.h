@@ -83,7 +83,12 @@ typedef struct {
  * x0 + floor(a*(x1-x0)/gx), y0 + floor(b*(y1-y0)/gy).
  *  - bin_weight == NULL: every bin is its own indicator filter (a k-channel
  *    histogram); its score weight is weight / (gx*gy*area(bin)).
- *  - bin_weight != NULL: not supported by this version (VQNNF_ENOTSUP). */
+ *  - bin_weight != NULL: one coarse filter (Sec. 3.2.1, eq. 1 with Alg. 2's
+ *    dilation taps on the bin corners): its response on channel j is
+ *    sum_{b,a} bin_weight[b*gx + a] * count_j(bin (a, b)) / area(region),
+ *    scored with weight `weight`.  gx and gy are at most 4 (else
+ *    VQNNF_ENOTSUP) and every bin weight must be finite; the array is read
+ *    during the call only.  Such banks are scored from the integral image. */
 typedef struct {
   int32_t x0, y0, x1, y1;
   int32_t gx, gy;
@@ -93,6 +98,34 @@ typedef struct {
 
 typedef struct vqnnf_ctx vqnnf_ctx;
 typedef struct vqnnf_template vqnnf_template;
+
+/* The paper's filter sets (Sec. 5.2 "Filtering"): a 3x3 coarse Gaussian
+ * (sigma 2, unnormalised: exp(-(a^2 + b^2)/8) for a, b in {-1, 0, 1}) alone
+ * or with Haar-like filters multiplied by it elementwise: 2-rectangle x / y
+ * (column / row factors +1, 0, -1) and 3-rectangle x / y (+1, -2, +1). */
+typedef enum {
+  VQNNF_BANK_GAUSS = 0,    /* Gaussian                       (1 per scale) */
+  VQNNF_BANK_2RECT = 1,    /* Gaussian, Haar-2x, Haar-2y     (3 per scale) */
+  VQNNF_BANK_3RECT = 2,    /* Gaussian, Haar-3x, Haar-3y     (3 per scale) */
+  VQNNF_BANK_23RECT = 3    /* Gaussian, 2x, 2y, 3x, 3y       (5 per scale) */
+} vqnnf_bank_set;
+
+/* Fills the paper's bank for a w x h template (Sec. 3.2.2, Sec. 3.3 eq. 2,
+ * Sec. 5.2; sub-scale aggregation is Supp. S.3's option c).  For every scale
+ * s = 1..n_scales: the centred sub-window of floor(w/s) x floor(h/s) pixels
+ * starting at (floor((w - floor(w/s))/2), floor((h - floor(h/s))/2)), a 3x3
+ * grid, one weighted filter per member of the set, weight w_f / s with
+ * w_f = 1 for the Gaussian and 0.25 for the Haar filters.  Order: scale by
+ * scale, within a scale Gaussian, 2x, 2y, 3x, 3y (members of the set only).
+ *  out: HOST array of `capacity` descs; bin_weights: HOST float[9*capacity];
+ *  desc i's bin_weight points at bin_weights + 9*i, so that array must stay
+ *  alive while the descs are used.  n_out: descs written.
+ * EINVAL (nothing written) for an unknown set, n_scales < 1, capacity below
+ * n_scales * set size, null pointers, or a sub-window under 3 x 3 pixels.
+ * Host only; needs no context. */
+vqnnf_status vqnnf_paper_bank(int32_t w, int32_t h, int32_t filter_set, int32_t n_scales,
+                              vqnnf_filter_desc* out, float* bin_weights, int32_t capacity,
+                              int32_t* n_out);
 
 /* Creates a context bound to the current HIP device and `hip_stream`
  * (a hipStream_t; NULL = the default stream).  scratch_cap_bytes bounds the
@@ -139,6 +172,13 @@ vqnnf_status vqnnf_template_codebook(const vqnnf_template* t, float* out);
 vqnnf_status vqnnf_template_labels(const vqnnf_template* t, uint8_t* out);
 vqnnf_status vqnnf_template_counts(const vqnnf_template* t, int32_t* out);
 vqnnf_status vqnnf_template_weights(const vqnnf_template* t, float* out);
+/* R(tau) as the score kernels read it: float[n_filters][k], each filter's
+ * FP32 response over the template (an indicator filter: its counts; a
+ * weighted filter: the FMA chain over its non-zero bins in row-major order,
+ * coefficient bin_weight / area(region) rounded to FP32).  Works for every
+ * bank; vqnnf_template_counts returns VQNNF_ENOTSUP for banks with weighted
+ * filters. */
+vqnnf_status vqnnf_template_responses(const vqnnf_template* t, float* out);
 
 /* NNF of a query map (Alg. 1): labels[y*W + x] = index of the nearest
  * codeword of pixel (y, x) (squared L2, lowest index on ties).
@@ -174,7 +214,10 @@ vqnnf_status vqnnf_score(vqnnf_ctx* ctx, const vqnnf_template* t, const uint8_t*
 
 /* Same heatmap computed from a one-hot integral image produced by
  * vqnnf_filter (the taps of Alg. 2's dilation filters read directly from
- * `integral`, DEVICE int32[(H+1)*(W+1)*k]). */
+ * `integral`, DEVICE int32[(H+1)*(W+1)*k]), for any bank.  With weighted
+ * filters, R_f,j(x,y) is the filter's response (bin counts exact in
+ * integers, then the FP32 FMA chain of vqnnf_template_responses) and the
+ * L1 over channels and the weighted sum are FP32. */
 vqnnf_status vqnnf_score_integral(vqnnf_ctx* ctx, const vqnnf_template* t,
                                   const int32_t* integral, int32_t H, int32_t W, float* heatmap,
                                   int32_t* best_xy, float* best_score);

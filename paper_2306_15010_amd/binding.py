@@ -24,7 +24,7 @@ EXPORTED = [
     "vqnnf_ctx_create", "vqnnf_ctx_create_host", "vqnnf_ctx_destroy", "vqnnf_codebook",
     "vqnnf_template_from_codebook", "vqnnf_template_free", "vqnnf_template_info",
     "vqnnf_template_codebook", "vqnnf_template_labels", "vqnnf_template_counts",
-    "vqnnf_template_weights", "vqnnf_assign", "vqnnf_filter", "vqnnf_score",
+    "vqnnf_template_weights", "vqnnf_template_responses", "vqnnf_paper_bank", "vqnnf_assign", "vqnnf_filter", "vqnnf_score",
     "vqnnf_score_integral", "vqnnf_match", "vqnnf_match_batched", "vqnnf_ctx_set_graph",
     "vqnnf_ctx_set_autotune",
     "vqnnf_ctx_set_timing", "vqnnf_ctx_kernel_times",
@@ -74,6 +74,8 @@ def lib() -> C.CDLL:
         "vqnnf_template_labels": (st, [vp, vp]),
         "vqnnf_template_counts": (st, [vp, vp]),
         "vqnnf_template_weights": (st, [vp, vp]),
+        "vqnnf_template_responses": (st, [vp, vp]),
+        "vqnnf_paper_bank": (st, [i32, i32, i32, i32, P(FilterDesc), vp, i32, P(i32)]),
         "vqnnf_assign": (st, [vp, vp, P(FMap), i32, vp, P(i64)]),
         "vqnnf_filter": (st, [vp, vp, vp, i32, i32, vp]),
         "vqnnf_score": (st, [vp, vp, vp, i32, i32, vp, P(i32), P(C.c_float)]),
@@ -131,16 +133,46 @@ def device_fmap(t, dtype: str, channel_scale: Optional[np.ndarray] = None) -> FM
     return fm
 
 
-def bank_descs(bank: Sequence[Tuple[int, int, int, int, int, int, float]]):
+def bank_descs(bank):
+    """Bank entries (x0, y0, x1, y1, gx, gy, weight[, bin_weight]) as C descs;
+    bin_weight (gy x gx, or None) makes the entry one weighted filter.  The
+    returned array keeps the weight arrays alive."""
     arr = (FilterDesc * len(bank))()
-    for i, (x0, y0, x1, y1, gx, gy, w) in enumerate(bank):
-        arr[i] = FilterDesc(x0, y0, x1, y1, gx, gy, None, w)
+    keep = []
+    for i, e in enumerate(bank):
+        x0, y0, x1, y1, gx, gy, w = e[:7]
+        bw = e[7] if len(e) > 7 else None
+        ptr = None
+        if bw is not None:
+            a = np.ascontiguousarray(np.asarray(bw, dtype=np.float32).reshape(gy, gx))
+            keep.append(a)
+            ptr = a.ctypes.data
+        arr[i] = FilterDesc(x0, y0, x1, y1, gx, gy, ptr, w)
+    arr._keep = keep
     return arr
 
 
 def default_bank(w: int, h: int, g: int):
     """Full window plus a g x g grid over it, each with weight 1."""
     return [(0, 0, w, h, 1, 1, 1.0), (0, 0, w, h, g, g, 1.0)]
+
+
+VQNNF_BANK_GAUSS, VQNNF_BANK_2RECT, VQNNF_BANK_3RECT, VQNNF_BANK_23RECT = range(4)
+_BANK_SETS = {"gauss": VQNNF_BANK_GAUSS, "2rect": VQNNF_BANK_2RECT, "3rect": VQNNF_BANK_3RECT,
+              "23rect": VQNNF_BANK_23RECT}
+
+
+def paper_bank(w: int, h: int, filter_set, n_scales: int):
+    """vqnnf_paper_bank: the paper's Gaussian / Haar bank with sub-scales, as
+    bank entries (x0, y0, x1, y1, 3, 3, weight, bin_weight[3][3])."""
+    fs = _BANK_SETS[filter_set] if isinstance(filter_set, str) else int(filter_set)
+    cap = 5 * max(n_scales, 1)
+    arr = (FilterDesc * cap)()
+    bw = np.zeros(9 * cap, dtype=np.float32)
+    n = C.c_int32()
+    _check(lib().vqnnf_paper_bank(w, h, fs, n_scales, arr, bw.ctypes.data, cap, C.byref(n)))
+    return [(d.x0, d.y0, d.x1, d.y1, d.gx, d.gy, float(d.weight), bw[9 * i:9 * i + 9].reshape(3, 3).copy())
+            for i, d in enumerate(arr[:n.value])]
 
 
 def _stream_ptr(stream):
@@ -229,6 +261,11 @@ class Template:
     def weights(self) -> np.ndarray:
         out = np.empty(self.n_filters, dtype=np.float32)
         _check(lib().vqnnf_template_weights(self.h, out.ctypes.data))
+        return out
+
+    def responses(self) -> np.ndarray:
+        out = np.empty((self.n_filters, self.k), dtype=np.float32)
+        _check(lib().vqnnf_template_responses(self.h, out.ctypes.data))
         return out
 
 

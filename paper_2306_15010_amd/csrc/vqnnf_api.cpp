@@ -245,11 +245,69 @@ vqnnf_status check_map(const vqnnf_fmap* m, const char* what) {
   return ok();
 }
 
+// Banks with weighted filters: region groups for the bank kernel (see
+// BankGroup); filters in desc order, a desc's bins row-major, as for
+// indicator banks.
+void expand_weighted(const vqnnf_filter_desc* bank, int n_desc, DeviceTemplate& t) {
+  t.groups.clear();
+  t.coef.clear();
+  t.weights.clear();
+  auto edge = [](int lo, int hi, int g, int a) { return lo + (int)((int64_t)a * (hi - lo) / g); };
+  auto add_filter = [&](double weight) {
+    t.coef.resize(t.coef.size() + 16, 0.0f);
+    t.weights.push_back((float)weight);
+    return (int)t.weights.size() - 1;
+  };
+  for (int i = 0; i < n_desc; ++i) {
+    const vqnnf_filter_desc& d = bank[i];
+    const bool small = d.gx <= kBankMaxG && d.gy <= kBankMaxG;
+    if (d.bin_weight || small) {
+      BankGroup g{};
+      g.gx = d.gx;
+      g.gy = d.gy;
+      for (int a = 0; a <= d.gx; ++a) g.xe[a] = edge(d.x0, d.x1, d.gx, a);
+      for (int b = 0; b <= d.gy; ++b) g.ye[b] = edge(d.y0, d.y1, d.gy, b);
+      g.f0 = (int)t.weights.size();
+      if (d.bin_weight) {
+        const double region = (double)(d.x1 - d.x0) * (double)(d.y1 - d.y0);
+        const int f = add_filter((double)d.weight);
+        for (int b = 0; b < d.gy; ++b)
+          for (int a = 0; a < d.gx; ++a)
+            t.coef[(size_t)f * 16 + b * 4 + a] = (float)((double)d.bin_weight[b * d.gx + a] / region);
+      } else {
+        for (int b = 0; b < d.gy; ++b)
+          for (int a = 0; a < d.gx; ++a) {
+            const double area = (double)(g.xe[a + 1] - g.xe[a]) * (double)(g.ye[b + 1] - g.ye[b]);
+            const int f = add_filter((double)d.weight / ((double)d.gx * d.gy * area));
+            t.coef[(size_t)f * 16 + b * 4 + a] = 1.0f;
+          }
+      }
+      g.f1 = (int)t.weights.size();
+      t.groups.push_back(g);
+    } else {
+      for (int b = 0; b < d.gy; ++b)
+        for (int a = 0; a < d.gx; ++a) {
+          BankGroup g{};
+          g.gx = g.gy = 1;
+          g.xe[0] = edge(d.x0, d.x1, d.gx, a);
+          g.xe[1] = edge(d.x0, d.x1, d.gx, a + 1);
+          g.ye[0] = edge(d.y0, d.y1, d.gy, b);
+          g.ye[1] = edge(d.y0, d.y1, d.gy, b + 1);
+          const double area = (double)(g.xe[1] - g.xe[0]) * (double)(g.ye[1] - g.ye[0]);
+          g.f0 = add_filter((double)d.weight / ((double)d.gx * d.gy * area));
+          g.f1 = g.f0 + 1;
+          t.coef[(size_t)g.f0 * 16] = 1.0f;
+          t.groups.push_back(g);
+        }
+    }
+  }
+  t.n_filters = (int)t.weights.size();
+}
+
 vqnnf_status expand_bank(const vqnnf_filter_desc* bank, int n_desc, int w, int h,
                          DeviceTemplate& t) {
   if (!bank || n_desc < 1) return fail(VQNNF_EINVAL, "filter bank: need n_desc >= 1 and a bank pointer");
-  t.boxes.clear();
-  t.weights.clear();
+  bool weighted = false;
   for (int i = 0; i < n_desc; ++i) {
     const vqnnf_filter_desc& d = bank[i];
     if (d.x0 < 0 || d.y0 < 0 || d.x1 > w || d.y1 > h || d.x0 >= d.x1 || d.y0 >= d.y1)
@@ -257,9 +315,30 @@ vqnnf_status expand_bank(const vqnnf_filter_desc* bank, int n_desc, int w, int h
                   i, d.x0, d.x1, d.y0, d.y1, w, h);
     if (d.gx < 1 || d.gy < 1 || d.gx > d.x1 - d.x0 || d.gy > d.y1 - d.y0)
       return fail(VQNNF_EINVAL, "filter %d: grid %dx%d leaves empty bins", i, d.gx, d.gy);
-    if (d.bin_weight)
-      return fail(VQNNF_ENOTSUP, "filter %d: weighted bins are not supported", i);
     if (!std::isfinite(d.weight)) return fail(VQNNF_EINVAL, "filter %d: weight not finite", i);
+    if (d.bin_weight) {
+      if (d.gx > kBankMaxG || d.gy > kBankMaxG)
+        return fail(VQNNF_ENOTSUP, "filter %d: weighted grids are at most %dx%d (got %dx%d)", i,
+                    kBankMaxG, kBankMaxG, d.gx, d.gy);
+      for (int b = 0; b < d.gx * d.gy; ++b)
+        if (!std::isfinite(d.bin_weight[b]))
+          return fail(VQNNF_EINVAL, "filter %d: bin_weight[%d] not finite", i, b);
+      weighted = true;
+    }
+  }
+  t.boxes.clear();
+  t.weights.clear();
+  t.groups.clear();
+  t.coef.clear();
+  t.weighted = weighted;
+  if (weighted) {
+    expand_weighted(bank, n_desc, t);
+    t.grid = GridBank{};
+    t.grid.valid = false;
+    return ok();
+  }
+  for (int i = 0; i < n_desc; ++i) {
+    const vqnnf_filter_desc& d = bank[i];
     for (int b = 0; b < d.gy; ++b)
       for (int a = 0; a < d.gx; ++a) {
         int bx0 = d.x0 + (int)((int64_t)a * (d.x1 - d.x0) / d.gx);
@@ -302,11 +381,12 @@ vqnnf_status upload(vqnnf_ctx* c, T** dst, const std::vector<T>& src) {
 
 void free_device(DeviceTemplate& t) {
   void* ps[] = {t.d_codebook, t.d_frag_bf16, t.d_frag_f32, t.d_cnorm, t.d_counts, t.d_counts16,
-                t.d_weights, t.d_boxes};
+                t.d_weights, t.d_boxes, t.d_groups, t.d_coef, t.d_resp};
   for (void* p : ps)
     if (p) hipFree(p);
   t.d_codebook = nullptr; t.d_frag_bf16 = nullptr; t.d_frag_f32 = nullptr; t.d_cnorm = nullptr;
   t.d_counts = nullptr; t.d_counts16 = nullptr; t.d_weights = nullptr; t.d_boxes = nullptr;
+  t.d_groups = nullptr; t.d_coef = nullptr; t.d_resp = nullptr;
   for (ScaledSet& ss : t.scaled) {
     if (ss.d_frag_bf16) hipFree(ss.d_frag_bf16);
     if (ss.d_frag_f32) hipFree(ss.d_frag_f32);
@@ -368,6 +448,9 @@ vqnnf_status finish_template(vqnnf_ctx* ctx, vqnnf_template* tp, const vqnnf_fma
   if ((s = upload(ctx, &t.d_counts16, ht.counts16))) return s;
   if ((s = upload(ctx, &t.d_weights, t.weights))) return s;
   if ((s = upload(ctx, &t.d_boxes, t.boxes))) return s;
+  if ((s = upload(ctx, &t.d_groups, t.groups))) return s;
+  if ((s = upload(ctx, &t.d_coef, t.coef))) return s;
+  if ((s = upload(ctx, &t.d_resp, ht.resp))) return s;
   return ok();
 }
 
@@ -543,6 +626,8 @@ vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t*
       return ok();   // the last candidate's run already produced the result
     }
     HIP_TRY(launch_score_fused(a, c->stream, &lds));
+  } else if (t->t.weighted) {
+    HIP_TRY(launch_score_bank(a, c->stream));
   } else {
     HIP_TRY(launch_score_integral(a, c->stream));
   }
@@ -767,7 +852,75 @@ vqnnf_status vqnnf_template_counts(const vqnnf_template* t, int32_t* out) {
   vqnnf_status s = check_tpl(nullptr, t);
   if (s) return s;
   if (!out) return fail(VQNNF_EINVAL, "null output");
+  if (t->t.weighted)
+    return fail(VQNNF_ENOTSUP, "the bank has weighted filters: use vqnnf_template_responses");
   std::memcpy(out, t->t.counts.data(), t->t.counts.size() * sizeof(int32_t));
+  return ok();
+}
+
+vqnnf_status vqnnf_template_responses(const vqnnf_template* t, float* out) {
+  vqnnf_status s = check_tpl(nullptr, t);
+  if (s) return s;
+  if (!out) return fail(VQNNF_EINVAL, "null output");
+  const DeviceTemplate& d = t->t;
+  if (d.weighted) {
+    std::memcpy(out, d.resp.data(), d.resp.size() * sizeof(float));
+  } else {
+    for (size_t i = 0; i < d.counts.size(); ++i) out[i] = (float)d.counts[i];
+  }
+  return ok();
+}
+
+vqnnf_status vqnnf_paper_bank(int32_t w, int32_t h, int32_t filter_set, int32_t n_scales,
+                              vqnnf_filter_desc* out, float* bin_weights, int32_t capacity,
+                              int32_t* n_out) {
+  enum { GAUSS, HAAR2X, HAAR2Y, HAAR3X, HAAR3Y };
+  static const int kMembers[4][5] = {{GAUSS}, {GAUSS, HAAR2X, HAAR2Y}, {GAUSS, HAAR3X, HAAR3Y},
+                                     {GAUSS, HAAR2X, HAAR2Y, HAAR3X, HAAR3Y}};
+  static const int kSize[4] = {1, 3, 3, 5};
+  if (!out || !bin_weights || !n_out) return fail(VQNNF_EINVAL, "null output pointer");
+  if (filter_set < VQNNF_BANK_GAUSS || filter_set > VQNNF_BANK_23RECT)
+    return fail(VQNNF_EINVAL, "unknown filter set %d", filter_set);
+  if (n_scales < 1) return fail(VQNNF_EINVAL, "n_scales must be >= 1 (got %d)", n_scales);
+  if (w < 1 || h < 1) return fail(VQNNF_EINVAL, "template sides must be >= 1");
+  const int per = kSize[filter_set];
+  if ((int64_t)n_scales * per > capacity)
+    return fail(VQNNF_EINVAL, "capacity %d < %d descs", capacity, n_scales * per);
+  for (int sc = 1; sc <= n_scales; ++sc)
+    if (w / sc < 3 || h / sc < 3)
+      return fail(VQNNF_EINVAL, "scale %d: the %dx%d sub-window has empty 3x3 bins", sc, w / sc, h / sc);
+  // 3x3 coarse Gaussian, sigma 2, centre 1; Haar factors per column (x) or row (y)
+  double g[3][3];
+  for (int b = 0; b < 3; ++b)
+    for (int a = 0; a < 3; ++a) g[b][a] = std::exp(-(double)((a - 1) * (a - 1) + (b - 1) * (b - 1)) / 8.0);
+  static const double kF2[3] = {1.0, 0.0, -1.0}, kF3[3] = {1.0, -2.0, 1.0};
+  int n = 0;
+  for (int sc = 1; sc <= n_scales; ++sc) {
+    const int rw = w / sc, rh = h / sc, x0 = (w - rw) / 2, y0 = (h - rh) / 2;
+    for (int mi = 0; mi < per; ++mi) {
+      const int m = kMembers[filter_set][mi];
+      float* bw = bin_weights + (size_t)9 * n;
+      for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
+          double f = 1.0;
+          if (m == HAAR2X) f = kF2[a];
+          if (m == HAAR2Y) f = kF2[b];
+          if (m == HAAR3X) f = kF3[a];
+          if (m == HAAR3Y) f = kF3[b];
+          bw[b * 3 + a] = (float)(f * g[b][a]);
+        }
+      vqnnf_filter_desc& d = out[n];
+      d.x0 = x0;
+      d.y0 = y0;
+      d.x1 = x0 + rw;
+      d.y1 = y0 + rh;
+      d.gx = d.gy = 3;
+      d.bin_weight = bw;
+      d.weight = (float)((m == GAUSS ? 1.0 : 0.25) / sc);
+      ++n;
+    }
+  }
+  *n_out = n;
   return ok();
 }
 

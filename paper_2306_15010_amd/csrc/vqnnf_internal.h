@@ -48,6 +48,21 @@ struct GridBank {
   int ye[9];   // row edges
 };
 
+// A bank with weighted filters, as the integral-image bank kernel reads it:
+// region groups of up to kBankMaxG x kBankMaxG bins (the taps of Alg. 2's
+// dilation filters sit on their edges) and filters that weigh a group's
+// bins.  A weighted desc is one group with one filter; an indicator desc is
+// one group whose every bin is a filter (coefficient 1), or, when its grid
+// is larger than kBankMaxG, one 1 x 1 group per bin.
+constexpr int kBankMaxG = 4;
+struct BankGroup {      // 16 int32 on the device
+  int32_t gx, gy;       // bins
+  int32_t f0, f1;       // filters [f0, f1) weigh this group's bins
+  int32_t xe[5], ye[5]; // tap offsets (bin edges) from the window's top-left
+  int32_t pad[2];
+};
+static_assert(sizeof(BankGroup) == 64, "device layout");
+
 // Assignment tables for FP8 maps of one channel-scale vector: the scale is
 // folded into the codebook (c' = s*c), so they are built per distinct scale.
 struct ScaledSet {
@@ -67,8 +82,13 @@ struct DeviceTemplate {
   std::vector<int32_t> counts;       // [n_filters][k]
   std::vector<float> weights;        // [n_filters]
   // expanded filter boxes (template coordinates), one per filter
-  std::vector<int32_t> boxes;        // [n_filters][4] x0,y0,x1,y1
+  std::vector<int32_t> boxes;        // [n_filters][4] x0,y0,x1,y1 (indicator banks)
   GridBank grid{};
+  // banks with weighted filters (scored by the bank kernel)
+  bool weighted = false;
+  std::vector<BankGroup> groups;
+  std::vector<float> coef;           // [n_filters][16]: bin (a, b) at b * 4 + a
+  std::vector<float> resp;           // [n_filters][k] R(tau), FP32 as the kernel computes it
   BoundCoef bound_bf16q{};           // BF16-stored query, codebook hi+lo
   BoundCoef bound_f32q{};            // FP32-stored query, both split hi+lo
   std::vector<float> cnorm32;        // [k] ||c||^2 rounded to FP32
@@ -82,6 +102,9 @@ struct DeviceTemplate {
   uint32_t* d_counts16 = nullptr;    // [n_filters][kpad/2] u16 pairs
   float* d_weights = nullptr;        // [n_filters]
   int32_t* d_boxes = nullptr;        // [n_filters][4]
+  BankGroup* d_groups = nullptr;     // weighted banks
+  float* d_coef = nullptr;           // [n_filters][16]
+  float* d_resp = nullptr;           // [n_filters][kpad] (pad channels 0)
   int magic = 0;
 };
 
@@ -99,6 +122,7 @@ struct HostTables {
   std::vector<float> cnorm;          // [kpad]
   std::vector<int32_t> counts;       // [nf][kpad]
   std::vector<uint32_t> counts16;    // [nf][kpad/2]
+  std::vector<float> resp;           // [nf][kpad] weighted banks
 };
 void build_tables(DeviceTemplate& t, HostTables& ht);
 void build_scaled_tables(const DeviceTemplate& t, const float* scale, std::vector<uint16_t>& frag_bf16,
@@ -184,6 +208,8 @@ struct ScoreArgs {
 };
 hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out);
 hipError_t launch_score_integral(const ScoreArgs& a, hipStream_t s);
+// Weighted banks: heatmap + best from the integral image a.P.
+hipError_t launch_score_bank(const ScoreArgs& a, hipStream_t s);
 // True when the on-chip score kernel can take this template's bank.
 bool fused_supported(const DeviceTemplate& t);
 // Scratch bytes of the on-chip path's per-channel-group partial sums.
@@ -195,7 +221,8 @@ hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
 // Kernel-name registry for timing.
 enum KernelId {
   K_FILL = 0, K_ASSIGN_PLAIN, K_ASSIGN_REFINED, K_RESCORE, K_INT_EDGE, K_INT_PREFIX,
-  K_INT_MAIN, K_SCORE_FUSED, K_SCORE_COMBINE, K_SCORE_INTEGRAL, K_ASSIGN_MULTI, K_COUNT
+  K_INT_MAIN, K_SCORE_FUSED, K_SCORE_COMBINE, K_SCORE_INTEGRAL, K_ASSIGN_MULTI, K_SCORE_BANK,
+  K_COUNT
 };
 const char* kernel_name(int id);
 

@@ -352,6 +352,35 @@ void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_st
   t.labels.resize(n);
   for (int64_t p = 0; p < n; ++p) t.labels[p] = (uint8_t)lab[p];
   // R(tau): per-filter counts over the template
+  t.counts.clear();
+  t.resp.clear();
+  if (t.weighted) {
+    // bin counts per group, then each filter's FP32 FMA chain over its
+    // non-zero bins in row-major order (the bank kernel's order)
+    t.resp.assign((size_t)t.n_filters * k, 0.0f);
+    std::vector<float> cnt((size_t)16 * k);
+    for (const BankGroup& g : t.groups) {
+      std::fill(cnt.begin(), cnt.end(), 0.0f);
+      for (int b = 0; b < g.gy; ++b)
+        for (int a = 0; a < g.gx; ++a) {
+          std::vector<int> hist(k, 0);
+          for (int y = g.ye[b]; y < g.ye[b + 1]; ++y)
+            for (int xx = g.xe[a]; xx < g.xe[a + 1]; ++xx) hist[t.labels[(size_t)y * t.w + xx]]++;
+          for (int j = 0; j < k; ++j) cnt[(size_t)(b * 4 + a) * k + j] = (float)hist[j];
+        }
+      for (int f = g.f0; f < g.f1; ++f)
+        for (int j = 0; j < k; ++j) {
+          float r = 0.0f;
+          for (int b = 0; b < g.gy; ++b)
+            for (int a = 0; a < g.gx; ++a) {
+              const float cv = t.coef[(size_t)f * 16 + b * 4 + a];
+              if (cv != 0.0f) r = std::fmaf(cv, cnt[(size_t)(b * 4 + a) * k + j], r);
+            }
+          t.resp[(size_t)f * k + j] = r;
+        }
+    }
+    return;
+  }
   t.counts.assign((size_t)t.n_filters * k, 0);
   for (int f = 0; f < t.n_filters; ++f) {
     const int32_t* b = &t.boxes[(size_t)f * 4];
@@ -378,10 +407,16 @@ void build_tables(DeviceTemplate& t, HostTables& ht) {
   }
   pack_frag_bf16(t, hi, lo, ht.frag_bf16);
   pack_frag_f32(t, t.codebook, ht.frag_f32);
-  // counts padded to kpad
-  ht.counts.assign((size_t)t.n_filters * g.kpad, 0);
-  ht.counts16.assign((size_t)t.n_filters * g.kpad / 2, 0);
-  for (int f = 0; f < t.n_filters; ++f)
+  // counts (indicator banks) or responses (weighted banks) padded to kpad
+  ht.resp.clear();
+  if (t.weighted) {
+    ht.resp.assign((size_t)t.n_filters * g.kpad, 0.0f);
+    for (int f = 0; f < t.n_filters; ++f)
+      for (int j = 0; j < k; ++j) ht.resp[(size_t)f * g.kpad + j] = t.resp[(size_t)f * k + j];
+  }
+  ht.counts.assign(t.weighted ? 0 : (size_t)t.n_filters * g.kpad, 0);
+  ht.counts16.assign(t.weighted ? 0 : (size_t)t.n_filters * g.kpad / 2, 0);
+  for (int f = 0; f < (t.weighted ? 0 : t.n_filters); ++f)
     for (int j = 0; j < k; ++j) {
       int32_t v = t.counts[(size_t)f * k + j];
       ht.counts[(size_t)f * g.kpad + j] = v;

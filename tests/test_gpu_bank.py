@@ -1,0 +1,207 @@
+"""GPU parity of weighted filter banks (the paper's Gaussian / Haar filters with
+sub-scale aggregation, and mixed banks) against the FP64 oracle, through the C
+ABI: vqnnf_match (assignment, integral image, bank kernel, localisation),
+vqnnf_filter + vqnnf_score_integral, and batched matching.
+
+Tolerance, derived from the kernel's arithmetic (u = 2^-24).  Bin counts are
+exact integers.  Per filter f and channel j the template and query responses
+are FMA chains over at most nb bins with FP32 coefficients: each is within
+(nb + 2) u sum_b |c_b| n_b of the oracle's FP64 value with the paper's FP64
+coefficients; summed over j that is at most (nb + 2) u M_f with
+M_f = max_b |c_b| * area(region).  The |difference|, the lane's channel sum
+(cpl terms), the FMA chain over all nf filters and the tree over at most 64
+lanes add (2 + cpl + nf + 6) u times the score's magnitude, which is at most
+S = sum_f w_f * 2 M_f.  The test allows twice the first-order sum:
+|gpu - oracle| <= 2 u (2 (nb + 2) + 8 + cpl + nf) S.  A wrong bin, tap or
+coefficient moves a score by about w_f * (one bin's share of M_f), orders of
+magnitude above this."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import vqnnf_oracle as O
+from paper_2306_15010_amd import binding as B
+from paper_2306_15010_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -24
+REFINED = B.VQNNF_PREC_BF16_REFINED
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    c = B.Context(stream=torch.cuda.current_stream())
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def to_dev(qm):
+    if qm.dtype == "f32":
+        return torch.from_numpy(np.ascontiguousarray(qm.data)).cuda()
+    return torch.from_numpy(qm.data.view(np.int16)).cuda()
+
+
+def to_oracle_bank(bank):
+    out = []
+    for e in bank:
+        x0, y0, x1, y1, gx, gy, wt = e[:7]
+        bw = None if len(e) < 8 or e[7] is None else np.asarray(e[7], np.float64)
+        out.append(O.FilterDesc(x0, y0, x1, y1, gx, gy, bw, float(wt)))
+    return out
+
+
+def tolerance(filters, k):
+    L = 1
+    while L < k and L < 64:
+        L *= 2
+    cpl = -(-k // L)
+    nf = len(filters)
+    nb = max(len(f.boxes) for f in filters)
+    S = 0.0
+    for f in filters:
+        mx = max(abs(c) for c, *_ in f.boxes)
+        area = sum((x1 - x0) * (y1 - y0) for _, x0, y0, x1, y1 in f.boxes)
+        S += f.weight * 2.0 * mx * area
+    return 2.0 * U * (2 * (nb + 2) + 8 + cpl + nf) * S
+
+
+def crop_case(seed, H, W, D, dtype, tw, th, noise=0.1, M=24):
+    qm = synth.random_map(H, W, D, dtype, seed=seed, M=M)
+    rng = np.random.default_rng(seed + 1000)
+    x0, y0 = int(rng.integers(0, W - tw + 1)), int(rng.integers(0, H - th + 1))
+    q = qm.decoded_f32().astype(np.float32)
+    t = q[y0:y0 + th, x0:x0 + tw].copy()
+    if noise:
+        t = t + np.float32(noise) * rng.standard_normal(t.shape).astype(np.float32)
+    return qm, np.ascontiguousarray(t, np.float32), (x0, y0)
+
+
+def oracle_sim(qm, tpl, tdata, bank_o):
+    cb = tpl.codebook().astype(np.float64)
+    tl = tpl.labels().astype(np.int64)
+    assert np.array_equal(tl, O.assign_map(tdata.astype(np.float64), cb))
+    ql = O.assign_map(O.decode(qm.dtype, qm.data, qm.scale), cb)
+    filters = O.expand_bank(bank_o)
+    rt = O.template_representation(tl, tpl.k, filters)
+    h, w = tdata.shape[:2]
+    return O.similarity_map_fast(ql, tpl.k, w, h, filters, rt), filters
+
+
+def check(gpu_heat, sim, filters, k, best, what):
+    gpu = gpu_heat.cpu().numpy().astype(np.float64).reshape(sim.shape)
+    tol = tolerance(filters, k)
+    err = np.abs(gpu - sim)
+    log(f"{what}: {sim.size} windows, max abs err {err.max():.3e}, tolerance {tol:.3e}")
+    assert np.isfinite(gpu).all()
+    assert (err <= tol).all(), f"{what}: {(err > tol).sum()} windows outside tolerance"
+    (bx, by), bs = best
+    ow = sim.shape[1]
+    assert int(np.argmax(gpu.reshape(-1))) == by * ow + bx      # first maximum, row-major
+    assert bs == np.float32(gpu[by, bx])
+    assert sim[by, bx] >= sim.max() - 2 * tol
+
+
+CASES = [
+    # seed, H, W, D, dtype, tw, th, k, bank (set, scales)
+    (1, 150, 170, 64, "bf16", 44, 40, 32, ("23rect", 3)),
+    (2, 70, 90, 27, "f32", 25, 21, 8, ("2rect", 2)),          # 8 windows per wave, ragged tail
+    (3, 128, 140, 64, "bf16", 60, 60, 128, ("23rect", 4)),    # two channels per lane
+    (4, 90, 100, 32, "f32", 30, 33, 200, ("3rect", 3)),       # four per lane, 56 masked lanes
+    (5, 64, 80, 16, "bf16", 27, 24, 48, ("gauss", 1)),        # one per lane, 16 masked lanes
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"k{c[7]}-{c[8][0]}S{c[8][1]}" for c in CASES])
+def test_paper_bank_match(ctx, case):
+    seed, H, W, D, dt, tw, th, k, (fs, S) = case
+    log(f"paper bank {fs} S={S}: map {H}x{W} D={D} {dt}, template {tw}x{th}, k={k}")
+    qm, tdata, _ = crop_case(seed, H, W, D, dt, tw, th)
+    bank = B.paper_bank(tw, th, fs, S)
+    tpl = B.vqnnf_codebook(ctx, tdata, k, 20, seed, bank)
+    dq = to_dev(qm)
+    heat = torch.full(((H - th + 1) * (W - tw + 1),), float("nan"), device="cuda")
+    best = B.vqnnf_match(ctx, tpl, B.device_fmap(dq, qm.dtype), REFINED, heat)
+    # the oracle builds the bank from the paper on its own (FP64 coefficients)
+    sim, filters = oracle_sim(qm, tpl, tdata, O.paper_bank(tw, th, fs, S))
+    check(heat, sim, filters, k, best, f"{fs} S={S} k={k}")
+
+
+def test_mixed_bank_and_single_window(ctx):
+    # indicator entries (one larger than a weighted group may be) beside a weighted one
+    qm, tdata, _ = crop_case(6, 60, 66, 24, "bf16", 27, 25, M=16)
+    rng = np.random.default_rng(7)
+    bank = [(0, 0, 27, 25, 1, 1, 1.0), (2, 3, 22, 21, 2, 2, 0.5), (0, 0, 27, 25, 5, 5, 1.0),
+            (4, 1, 20, 24, 4, 3, 0.3, rng.standard_normal((3, 4)))]
+    tpl = B.vqnnf_codebook(ctx, tdata, 16, 20, 1, bank)
+    dq = to_dev(qm)
+    heat = torch.full((36 * 40,), float("nan"), device="cuda")
+    best = B.vqnnf_match(ctx, tpl, B.device_fmap(dq, "bf16"), REFINED, heat)
+    sim, filters = oracle_sim(qm, tpl, tdata, to_oracle_bank(bank))
+    check(heat, sim, filters, 16, best, "mixed bank")
+    # template as large as the map: one window
+    qm1 = synth.random_map(30, 34, 24, "bf16", seed=8, M=12)
+    t1 = np.ascontiguousarray(qm1.decoded_f32().astype(np.float32) + np.float32(0.05))
+    bank1 = B.paper_bank(34, 30, "23rect", 2)
+    tpl1 = B.vqnnf_codebook(ctx, t1, 12, 20, 2, bank1)
+    h1 = torch.full((1,), float("nan"), device="cuda")
+    best1 = B.vqnnf_match(ctx, tpl1, B.device_fmap(to_dev(qm1), "bf16"), REFINED, h1)
+    sim1, f1 = oracle_sim(qm1, tpl1, t1, O.paper_bank(34, 30, "23rect", 2))
+    check(h1, sim1, f1, 12, best1, "single window")
+
+
+def test_noise_free_crop_scores_exactly_zero(ctx):
+    """The template's R(tau) and the kernel's response use one FMA chain, so the
+    window that holds the template's own labels scores 0 exactly."""
+    qm, tdata, (x0, y0) = crop_case(9, 120, 110, 48, "bf16", 36, 36, noise=0.0)
+    bank = B.paper_bank(36, 36, "23rect", 3)
+    tpl = B.vqnnf_codebook(ctx, tdata, 32, 20, 3, bank)
+    heat = torch.full((85 * 75,), float("nan"), device="cuda")
+    (bx, by), bs = B.vqnnf_match(ctx, tpl, B.device_fmap(to_dev(qm), "bf16"), REFINED, heat)
+    h = heat.cpu().numpy().reshape(85, 75)
+    assert h[y0, x0] == 0.0 and bs == 0.0
+    assert (bx, by) == (x0, y0) or h[by, bx] == 0.0
+    assert (h <= 0.0).all()
+
+
+def test_score_integral_and_batched_equal_match(ctx):
+    qm, tdata, _ = crop_case(10, 96, 104, 32, "bf16", 33, 30)
+    dq = to_dev(qm)
+    fm = B.device_fmap(dq, "bf16")
+    bank = B.paper_bank(33, 30, "23rect", 3)
+    tpl = B.vqnnf_codebook(ctx, tdata, 24, 20, 4, bank)
+    n = (96 - 30 + 1) * (104 - 33 + 1)
+    ref = torch.empty(n, device="cuda")
+    best = B.vqnnf_match(ctx, tpl, fm, REFINED, ref)
+    # stage by stage: labels, integral image, bank score from the integral image
+    lab = torch.empty(96 * 104, dtype=torch.uint8, device="cuda")
+    B.vqnnf_assign(ctx, tpl, fm, REFINED, lab)
+    P = torch.empty(97 * 105 * 24, dtype=torch.int32, device="cuda")
+    B.vqnnf_filter(ctx, tpl, lab, 96, 104, P)
+    h2 = torch.full((n,), float("nan"), device="cuda")
+    best2 = B.vqnnf_score_integral(ctx, tpl, P, 96, 104, h2)
+    assert torch.equal(h2, ref) and best2 == best
+    # batched, beside pairs with the benchmark bank
+    t2 = np.ascontiguousarray(tdata[:20, :24])
+    tpl_b = B.vqnnf_codebook(ctx, t2, 16, 20, 5, B.default_bank(24, 20, 3))
+    tpl_w = B.vqnnf_codebook(ctx, t2, 16, 20, 5, B.paper_bank(24, 20, "2rect", 2))
+    tpls = [tpl, tpl_b, tpl_w]
+    heats = [torch.full((n,), float("nan"), device="cuda"),
+             torch.full((77 * 81,), float("nan"), device="cuda"),
+             torch.full((77 * 81,), float("nan"), device="cuda")]
+    out = B.vqnnf_match_batched(ctx, tpls, [fm] * 3, REFINED, heats)
+    for i, tp in enumerate(tpls):
+        r = torch.empty_like(heats[i])
+        assert out[i] == B.vqnnf_match(ctx, tp, fm, REFINED, r), i
+        assert torch.equal(r, heats[i]), i
