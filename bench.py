@@ -130,6 +130,64 @@ def secondary(name, ctx, B, synth, steps):
     return out
 
 
+def bank_ops_per_window(bank, k):
+    """Algorithmic lane-ops of the bank kernel per window: per region group
+    (one per scale here) the tap differences and count conversions
+    (gx(gy+1) + 2 gx gy per channel), per filter one FMA per non-zero bin plus
+    |difference| and accumulation (3) per channel."""
+    ops = 0
+    prev = None
+    for e in bank:
+        gx, gy, bw = e[4], e[5], np.asarray(e[7])
+        if tuple(e[:6]) != prev:            # consecutive filters of one region share its counts
+            ops += k * (gx * (gy + 1) + 2 * gx * gy)
+        prev = tuple(e[:6])
+        ops += k * (int(np.count_nonzero(bw)) + 3)
+    return ops
+
+
+def paper_bank_leg(ctx, B, t, fm, qm, steps, torch):
+    """The paper's own filter bank (Gaussian + Haar 2x/2y/3x/3y at scales
+    1..3: 15 weighted filters, Sec. 5.2) on the same map and template:
+    assignment, integral image in HBM, bank kernel, localisation."""
+    h, w, _ = t.data.shape
+    bank = B.paper_bank(w, h, "23rect", 3)
+    tpl = B.vqnnf_codebook(ctx, t.data, t.k, 20, 0, bank)
+    oh, ow = qm.H - h + 1, qm.W - w + 1
+    heat = torch.empty(oh * ow, device="cuda")
+    P = B.VQNNF_PREC_BF16_REFINED
+    for _ in range(3):
+        B.vqnnf_match(ctx, tpl, fm, P, heat, want_best=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.vqnnf_match(ctx, tpl, fm, P, heat, want_best=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    ctx.reset_times()
+    ctx.set_timing(True)
+    for _ in range(steps):
+        B.vqnnf_match(ctx, tpl, fm, P, heat, want_best=False)
+    kt = ctx.kernel_times()
+    ctx.set_timing(False)
+    best, _ = B.vqnnf_match(ctx, tpl, fm, P, heat)
+    avg = {k: v[1] / max(1, v[0]) for k, v in kt.items()}
+    out = {"workload": f"same map and template, paper bank F_2,3-rect at S=3 ({len(bank)} weighted filters)",
+           "value": qm.H * qm.W / (ms / 1e3), "unit": "px/s", "ms_per_step": ms,
+           "kernels_avg_ms": {k: round(v, 4) for k, v in avg.items()},
+           "best": {"x": best[0], "y": best[1], "planted": [t.x0, t.y0]}}
+    if "score_bank" in avg:
+        ops = bank_ops_per_window(bank, t.k) * oh * ow
+        ach = ops / (avg["score_bank"] * 1e-3) / 1e12
+        out["score_bank_roofline"] = {"bound": "alu", "achieved": ach, "peak": ALU_PEAK_TOPS,
+                                      "unit": "Tops/s", "frac": ach / ALU_PEAK_TOPS,
+                                      "ops_per_window": bank_ops_per_window(bank, t.k)}
+    if "integral_main" in avg:
+        pbytes = (qm.H + 1) * (qm.W + 1) * t.k * 4 + qm.H * qm.W
+        out["integral_hbm_tbs"] = pbytes / (avg["integral_main"] * 1e-3) / 1e12
+    return out
+
+
 def batched_bench(args, ctx, B, synth, torch):
     """Batched workloads: every (template, map) pair in one vqnnf_match_batched
     call, replayed as one captured HIP graph, against the same pairs as
@@ -366,6 +424,8 @@ def main():
     if not args.no_secondary and args.workload == "c3":
         log("timing the 512x512 D=64 FP32 workload (both paths)")
         sec = secondary("c2", ctx, B, synth, max(5, args.steps))
+        log("timing the paper's filter bank on the same map")
+        sec = {"c2": sec, "paper_bank": paper_bank_leg(ctx, B, t, fm, qm, max(5, args.steps // 2), torch)}
 
     cpu = None
     if not args.no_cpu_baseline:

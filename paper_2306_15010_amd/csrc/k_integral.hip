@@ -138,13 +138,18 @@ __global__ __launch_bounds__(256) void integral_main_kernel(IntegralArgs a, int 
     vj[i] = f % k;
     V[i] = (f < tw * k) ? abv[f] : 0;
   }
-  int32_t* P = a.P;
+  // 32-bit P, or P mod 2^16 (differences of taps still give exact counts
+  // below 2^16 in wrapping 16-bit arithmetic)
+  auto put = [&](int64_t i, int v) {
+    if (a.P16) a.P16[i] = (uint16_t)v;
+    else a.P[i] = v;
+  };
   if (r == 0) {
 #pragma unroll
     for (int i = 0; i < VPT; ++i)
-      if (tid + 256 * i < tw * k) P[(int64_t)(x0 + vdx[i] + 1) * k + vj[i]] = 0;
+      if (tid + 256 * i < tw * k) put((int64_t)(x0 + vdx[i] + 1) * k + vj[i], 0);
     if (s == 0)
-      for (int j = tid; j < k; j += 256) P[j] = 0;
+      for (int j = tid; j < k; j += 256) put(j, 0);
   }
   // per-channel slice of the mask computation for this wave
   const int jw0 = (k * wave) / 4, jw1 = (k * (wave + 1)) / 4;
@@ -158,18 +163,18 @@ __global__ __launch_bounds__(256) void integral_main_kernel(IntegralArgs a, int 
     }
     for (int j = tid; j < k; j += 256) left[buf * k + j] = a.rsh[((int64_t)y * S + s) * k + j];
     __syncthreads();
-    int32_t* prow = P + (int64_t)(y + 1) * rowlen + (int64_t)(x0 + 1) * k;
+    const int64_t prow = (int64_t)(y + 1) * rowlen + (int64_t)(x0 + 1) * k;
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       if (tid + 256 * i < tw * k) {
         const unsigned long long below = (2ull << vdx[i]) - 1ull;
         const int cnt = __popcll(masks[buf * k + vj[i]] & below);
         V[i] += left[buf * k + vj[i]] + cnt;
-        prow[tid + 256 * i] = V[i];
+        put(prow + tid + 256 * i, V[i]);
       }
     }
     if (s == 0)
-      for (int j = tid; j < k; j += 256) P[(int64_t)(y + 1) * rowlen + j] = 0;
+      for (int j = tid; j < k; j += 256) put((int64_t)(y + 1) * rowlen + j, 0);
   }
 }
 

@@ -247,7 +247,8 @@ vqnnf_status check_map(const vqnnf_fmap* m, const char* what) {
 
 // Banks with weighted filters: region groups for the bank kernel (see
 // BankGroup); filters in desc order, a desc's bins row-major, as for
-// indicator banks.
+// indicator banks.  Consecutive weighted descs over the same region and grid
+// (the filters of one scale) share one group.
 void expand_weighted(const vqnnf_filter_desc* bank, int n_desc, DeviceTemplate& t) {
   t.groups.clear();
   t.coef.clear();
@@ -261,6 +262,20 @@ void expand_weighted(const vqnnf_filter_desc* bank, int n_desc, DeviceTemplate& 
   for (int i = 0; i < n_desc; ++i) {
     const vqnnf_filter_desc& d = bank[i];
     const bool small = d.gx <= kBankMaxG && d.gy <= kBankMaxG;
+    if (d.bin_weight && i > 0 && bank[i - 1].bin_weight && bank[i - 1].x0 == d.x0 &&
+        bank[i - 1].y0 == d.y0 && bank[i - 1].x1 == d.x1 && bank[i - 1].y1 == d.y1 &&
+        bank[i - 1].gx == d.gx && bank[i - 1].gy == d.gy) {
+      // same region and grid as the previous weighted desc: its group's
+      // bin counts serve this filter too
+      BankGroup& g = t.groups.back();
+      const double region = (double)(d.x1 - d.x0) * (double)(d.y1 - d.y0);
+      const int f = add_filter((double)d.weight);
+      for (int b = 0; b < d.gy; ++b)
+        for (int a = 0; a < d.gx; ++a)
+          t.coef[(size_t)f * 16 + b * 4 + a] = (float)((double)d.bin_weight[b * d.gx + a] / region);
+      g.f1 = f + 1;
+      continue;
+    }
     if (d.bin_weight || small) {
       BankGroup g{};
       g.gx = d.gx;
@@ -302,6 +317,14 @@ void expand_weighted(const vqnnf_filter_desc* bank, int n_desc, DeviceTemplate& 
     }
   }
   t.n_filters = (int)t.weights.size();
+  // edges past a group's grid repeat its last edge (zero-area bins the
+  // kernel's fixed tap pattern can read); largest side for the kernel shape
+  t.bank_g = 1;
+  for (BankGroup& g : t.groups) {
+    for (int a = g.gx + 1; a <= kBankMaxG; ++a) g.xe[a] = g.xe[g.gx];
+    for (int b = g.gy + 1; b <= kBankMaxG; ++b) g.ye[b] = g.ye[g.gy];
+    t.bank_g = std::max(t.bank_g, std::max(g.gx, g.gy));
+  }
 }
 
 vqnnf_status expand_bank(const vqnnf_filter_desc* bank, int n_desc, int w, int h,
@@ -333,6 +356,11 @@ vqnnf_status expand_bank(const vqnnf_filter_desc* bank, int n_desc, int w, int h
   t.weighted = weighted;
   if (weighted) {
     expand_weighted(bank, n_desc, t);
+    const size_t lds = (t.groups.size() * 16 + (size_t)t.n_filters * (make_assign_geom(t.k, 1).kpad + 17)) *
+                       sizeof(float);
+    if (lds > kBankMaxLds)
+      return fail(VQNNF_ENOTSUP, "weighted bank: %d filters x %d channels exceed the %zu KiB the bank "
+                  "kernel holds on chip", t.n_filters, t.k, kBankMaxLds / 1024);
     t.grid = GridBank{};
     t.grid.valid = false;
     return ok();
@@ -565,16 +593,26 @@ vqnnf_status check_score_dims(const vqnnf_template* tp, int H, int W) {
   if ((int64_t)H * W >= (1ll << 31)) return fail(VQNNF_EINVAL, "H*W must be < 2^31");
   if (t.w > W || t.h > H)
     return fail(VQNNF_EINVAL, "template %dx%d larger than the %dx%d map", t.w, t.h, W, H);
+  if (t.weighted) {
+    // the bank kernel addresses a band of h + 66 integral-image rows with
+    // 32-bit byte offsets
+    const int64_t row_bytes = (int64_t)(W + 1) * t.k * 4;
+    if ((int64_t)(t.h + 66) * row_bytes >= (1ll << 32))
+      return fail(VQNNF_ENOTSUP, "weighted bank: a %d-column map with k = %d is too wide for the bank kernel",
+                  W, t.k);
+  }
   return ok();
 }
 
 vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* labels,
                                   const int32_t* P, int32_t H, int32_t W, float* heatmap,
-                                  unsigned long long* best, bool zeroed) {
+                                  unsigned long long* best, bool zeroed,
+                                  const uint16_t* P16 = nullptr) {
   ScoreArgs a{};
   a.t = &t->t;
   a.labels = labels;
   a.P = P;
+  a.P16 = P16;
   a.H = H;
   a.W = W;
   a.heatmap = heatmap;
@@ -634,24 +672,30 @@ vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t*
   return ok();
 }
 
+// Channels of the matching path's integral image: weighted banks read it
+// mod 2^16 in channel pairs, so their channel count is rounded up to even.
+int int_channels(const DeviceTemplate& d) { return d.weighted ? d.k + (d.k & 1) : d.k; }
+
 // Score of one pair from a label map: the on-chip kernel, or the integral
 // image and the integral score for banks the on-chip kernel does not take.
 vqnnf_status enqueue_score_labels(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* lab, int H,
                                   int W, float* heatmap, unsigned long long* key) {
   if (fused_supported(t->t)) return enqueue_score(c, t, lab, nullptr, H, W, heatmap, key, true);
-  const int k = t->t.k;
+  const int k = int_channels(t->t);
   const int64_t R = (H + kIntTile - 1) / kIntTile, S = (W + kIntTile - 1) / kIntTile;
   IntegralArgs a{};
   a.labels = lab;
   a.H = H;
   a.W = W;
   a.k = k;
-  a.P = (int32_t*)c->int_p.p;
+  // weighted banks: P mod 2^16 with an even channel count (pad channel empty)
+  if (t->t.weighted) a.P16 = (uint16_t*)c->int_p.p;
+  else a.P = (int32_t*)c->int_p.p;
   a.rsh = (int32_t*)c->int_side.p;
   a.cbh = a.rsh + (size_t)H * S * k;
   a.th = a.cbh + (size_t)R * W * k;
   HIP_TRY(launch_integral(a, c->stream));
-  return enqueue_score(c, t, nullptr, a.P, H, W, heatmap, key, true);
+  return enqueue_score(c, t, nullptr, a.P, H, W, heatmap, key, true, a.P16);
 }
 
 // Scratch for matching the given pairs one after another (sized for the largest).
@@ -670,8 +714,9 @@ vqnnf_status pair_scratch(vqnnf_ctx* c, const vqnnf_template* const* t, const vq
       partb = std::max(partb, fused_partial_bytes(d, q[i]->H, q[i]->W));
     } else {
       const int64_t R = (q[i]->H + kIntTile - 1) / kIntTile, S = (q[i]->W + kIntTile - 1) / kIntTile;
-      side = std::max(side, (size_t)((int64_t)q[i]->H * S + R * q[i]->W + R * S) * d.k * 4);
-      pbytes = std::max(pbytes, (size_t)(q[i]->H + 1) * (q[i]->W + 1) * d.k * 4);
+      const int kc = int_channels(d);
+      side = std::max(side, (size_t)((int64_t)q[i]->H * S + R * q[i]->W + R * S) * kc * 4);
+      pbytes = std::max(pbytes, (size_t)(q[i]->H + 1) * (q[i]->W + 1) * kc * (d.weighted ? 2 : 4));
     }
   }
   vqnnf_status s = check_cap(c, {{&c->control, control}, {&c->labels, lab}, {&c->wl_pix, wp},

@@ -55,10 +55,15 @@ struct GridBank {
 // one group whose every bin is a filter (coefficient 1), or, when its grid
 // is larger than kBankMaxG, one 1 x 1 group per bin.
 constexpr int kBankMaxG = 4;
+// The bank kernel keeps the group table and every filter's R(tau), bin
+// coefficients and weight (16 words per group + n_filters x (kpad + 17)
+// floats) in LDS.
+constexpr size_t kBankMaxLds = 160 * 1024;
 struct BankGroup {      // 16 int32 on the device
   int32_t gx, gy;       // bins
   int32_t f0, f1;       // filters [f0, f1) weigh this group's bins
-  int32_t xe[5], ye[5]; // tap offsets (bin edges) from the window's top-left
+  int32_t xe[5], ye[5]; // tap offsets (bin edges) from the window's top-left;
+                        // entries past gx / gy repeat the last edge
   int32_t pad[2];
 };
 static_assert(sizeof(BankGroup) == 64, "device layout");
@@ -86,6 +91,7 @@ struct DeviceTemplate {
   GridBank grid{};
   // banks with weighted filters (scored by the bank kernel)
   bool weighted = false;
+  int bank_g = 0;                    // largest group side (1..kBankMaxG)
   std::vector<BankGroup> groups;
   std::vector<float> coef;           // [n_filters][16]: bin (a, b) at b * 4 + a
   std::vector<float> resp;           // [n_filters][k] R(tau), FP32 as the kernel computes it
@@ -188,6 +194,7 @@ struct IntegralArgs {
   const uint8_t* labels;
   int H, W, k;
   int32_t* P;            // [(H+1)(W+1)k]
+  uint16_t* P16;         // if set, P is written here instead, mod 2^16
   int32_t* rsh;          // [H][S][k]
   int32_t* cbh;          // [R][W][k]
   int32_t* th;           // [R][S][k]
@@ -199,6 +206,7 @@ struct ScoreArgs {
   const DeviceTemplate* t;
   const uint8_t* labels;       // on-chip path
   const int32_t* P;            // integral path
+  const uint16_t* P16;         // weighted banks: integral image mod 2^16, even channel count
   int H, W;
   float* heatmap;
   unsigned long long* best;    // packed (orderable score, ~index), must be 0
