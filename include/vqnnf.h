@@ -149,10 +149,25 @@ void vqnnf_ctx_destroy(vqnnf_ctx* ctx);
  *  tmpl: HOST map, dtype VQNNF_F32, H = h, W = w.
  *  k in [1, 256]; bank: host array of n_desc >= 1 entries, each region
  *  inside [0,w) x [0,h) with non-empty bins.
- * Runs on the host; uploads the handle's tables to the device. */
+ * On a device context the k-means and the template NNF run on the GPU
+ * (FP64, the same operations in the same order, so the result is bit-identical
+ * to the host definition); on a host context they run on the host.  The
+ * handle's tables are uploaded to the device. */
 vqnnf_status vqnnf_codebook(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, int32_t k, int32_t lloyd_iters,
                             uint64_t seed, const vqnnf_filter_desc* bank, int32_t n_desc,
                             vqnnf_template** out);
+
+/* vqnnf_codebook for n templates at once: template i has map tmpls[i],
+ * k = ks[i], seed seeds[i] and bank banks[i] (n_descs[i] entries); every
+ * template runs lloyd_iters iterations.  On a device context the k-means of
+ * all templates (and their NNFs) run on the GPU together, bit-identical to
+ * the host definition above; on a host context they run on the host.  out:
+ * n handles, all NULL on error (EINVAL names the template).  Temporary device
+ * memory is allocated and released inside the call (within the scratch cap). */
+vqnnf_status vqnnf_codebook_batched(vqnnf_ctx* ctx, int32_t n, const vqnnf_fmap* const* tmpls,
+                                    const int32_t* ks, int32_t lloyd_iters, const uint64_t* seeds,
+                                    const vqnnf_filter_desc* const* banks, const int32_t* n_descs,
+                                    vqnnf_template** out);
 
 /* Same as vqnnf_codebook but with a caller-supplied codebook (host float
  * [k][D], FP32) instead of k-means: used to restore an exported template and

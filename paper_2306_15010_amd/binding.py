@@ -22,6 +22,7 @@ VQNNF_PREC_FP32_PLAIN, VQNNF_PREC_BF16_REFINED = 0, 1
 
 EXPORTED = [
     "vqnnf_ctx_create", "vqnnf_ctx_create_host", "vqnnf_ctx_destroy", "vqnnf_codebook",
+    "vqnnf_codebook_batched",
     "vqnnf_template_from_codebook", "vqnnf_template_free", "vqnnf_template_info",
     "vqnnf_template_codebook", "vqnnf_template_labels", "vqnnf_template_counts",
     "vqnnf_template_weights", "vqnnf_template_responses", "vqnnf_paper_bank", "vqnnf_assign", "vqnnf_filter", "vqnnf_score",
@@ -68,6 +69,8 @@ def lib() -> C.CDLL:
         "vqnnf_ctx_destroy": (None, [vp]),
         "vqnnf_codebook": (st, [vp, P(FMap), i32, i32, u64, P(FilterDesc), i32, P(vp)]),
         "vqnnf_template_from_codebook": (st, [vp, P(FMap), vp, i32, P(FilterDesc), i32, P(vp)]),
+        "vqnnf_codebook_batched": (st, [vp, i32, P(P(FMap)), P(i32), i32, P(u64), P(P(FilterDesc)),
+                                        P(i32), P(vp)]),
         "vqnnf_template_free": (None, [vp]),
         "vqnnf_template_info": (st, [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]),
         "vqnnf_template_codebook": (st, [vp, vp]),
@@ -279,6 +282,22 @@ def vqnnf_codebook(ctx: Context, template: np.ndarray, k: int, lloyd_iters: int,
     _check(lib().vqnnf_codebook(ctx.h, C.byref(fm), k, lloyd_iters, seed, descs, len(bank),
                                 C.byref(h)))
     return Template(ctx, h)
+
+
+def vqnnf_codebook_batched(ctx: Context, templates: Sequence[np.ndarray], ks: Sequence[int],
+                           lloyd_iters: int, seeds: Sequence[int], banks) -> list:
+    """vqnnf_codebook_batched: one handle per template (host FP32 [h][w][D])."""
+    n = len(templates)
+    maps = [host_fmap(t) for t in templates]
+    fms = (C.POINTER(FMap) * n)(*[C.pointer(m[0]) for m in maps])
+    descs = [bank_descs(b) for b in banks]
+    dps = (C.POINTER(FilterDesc) * n)(*[C.cast(d, C.POINTER(FilterDesc)) for d in descs])
+    kk = (C.c_int32 * n)(*ks)
+    ss = (C.c_uint64 * n)(*seeds)
+    nd = (C.c_int32 * n)(*[len(b) for b in banks])
+    out = (C.c_void_p * n)()
+    _check(lib().vqnnf_codebook_batched(ctx.h, n, fms, kk, lloyd_iters, ss, dps, nd, out))
+    return [Template(ctx, C.c_void_p(out[i])) for i in range(n)]
 
 
 def vqnnf_template_from_codebook(ctx: Context, template: np.ndarray, codebook: np.ndarray,

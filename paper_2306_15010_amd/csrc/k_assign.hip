@@ -27,7 +27,8 @@ thread_local TimingHook g_hook{nullptr, nullptr, nullptr};
 const char* const kNames[K_COUNT] = {
     "fill",           "assign_fp32_plain", "assign_bf16_refined", "rescore_fp64",
     "integral_edges", "integral_prefix",   "integral_main",       "score_partial",
-    "score_combine",  "score_integral", "assign_multi", "score_bank"};
+    "score_combine",  "score_integral", "assign_multi", "score_bank",
+    "kmeans"};
 }  // namespace
 
 void set_timing_hook(const TimingHook* h) {

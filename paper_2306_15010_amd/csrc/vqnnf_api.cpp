@@ -457,11 +457,12 @@ vqnnf_status prepare_scaled(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_
   return ok();
 }
 
-vqnnf_status finish_template(vqnnf_ctx* ctx, vqnnf_template* tp, const vqnnf_fmap* tmpl) {
+vqnnf_status finish_template(vqnnf_ctx* ctx, vqnnf_template* tp, const vqnnf_fmap* tmpl,
+                             const uint8_t* labels = nullptr) {
   DeviceTemplate& t = tp->t;
   const float* td = (const float*)tmpl->data;
   int64_t st = tmpl->pixel_stride ? tmpl->pixel_stride : tmpl->D;
-  prepare_template_host(t, td, st);
+  prepare_template_host(t, td, st, labels);
   HostTables ht;
   build_tables(t, ht);
   if (!ctx->has_device) return ok();
@@ -802,14 +803,80 @@ void vqnnf_ctx_destroy(vqnnf_ctx* c) {
   delete c;
 }
 
-static vqnnf_status make_template(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, const float* codebook,
-                                  int32_t k, int32_t iters, uint64_t seed,
-                                  const vqnnf_filter_desc* bank, int32_t n_desc,
-                                  vqnnf_template** out) {
+// k-means of several templates on the device in one set of launches:
+// codebooks (FP32) and the templates' NNFs, bit-identical to kmeans_host +
+// assign_host.  Temporary device memory, released before returning.
+static vqnnf_status kmeans_device(vqnnf_ctx* c, const std::vector<vqnnf_template*>& tps,
+                                  const vqnnf_fmap* const* tmpls, int iters, const uint64_t* seeds,
+                                  std::vector<std::vector<uint8_t>>& labels) {
+  const size_t n = tps.size();
+  std::vector<size_t> off(n + 1, 0);
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  struct Sz { size_t x, c, c32, lab, idx, start, d2, csum, pdist, pidx; };
+  std::vector<Sz> sz(n);
+  for (size_t i = 0; i < n; ++i) {
+    const DeviceTemplate& t = tps[i]->t;
+    const size_t l = (size_t)t.w * t.h, kd = (size_t)t.k * t.D, nch = (t.k + 15) / 16;
+    sz[i] = {al(l * t.D * 4), al(kd * 8), al(kd * 4), al(l), al(l * 4), al((t.k + 1) * 4), al(l * 8),
+             al(l * 8), al(nch * l * 8), al(nch * l)};
+    const Sz& z = sz[i];
+    off[i + 1] = off[i] + z.x + z.c + z.c32 + z.lab + z.idx + z.start + z.d2 + z.csum + z.pdist + z.pidx;
+  }
+  const size_t jobs_off = al(off[n]);
+  const size_t total = jobs_off + al(n * sizeof(KmJob));
+  if (total > c->cap) return fail(VQNNF_ENOMEM, "k-means needs %zu bytes of device memory, cap %llu", total,
+                                  (unsigned long long)c->cap);
+  char* arena = nullptr;
+  HIP_TRY(hipMalloc((void**)&arena, total));
+  std::vector<KmJob> jobs(n);
+  std::vector<float> pts;
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+    const DeviceTemplate& t = tps[i]->t;
+    const Sz& z = sz[i];
+    char* b = arena + off[i];
+    KmJob& j = jobs[i];
+    j.x = (const float*)b; b += z.x;
+    j.c = (double*)b; b += z.c;
+    j.c32 = (float*)b; b += z.c32;
+    j.lab = (uint8_t*)b; b += z.lab;
+    j.idx = (int*)b; b += z.idx;
+    j.start = (int*)b; b += z.start;
+    j.d2 = (double*)b; b += z.d2;
+    j.csum = (double*)b; b += z.csum;
+    j.pdist = (double*)b; b += z.pdist;
+    j.pidx = (uint8_t*)b;
+    j.seed = seeds[i];
+    j.l = t.w * t.h;
+    j.D = t.D;
+    j.k = t.k;
+    const vqnnf_fmap* m = tmpls[i];
+    const int64_t st = m->pixel_stride ? m->pixel_stride : m->D;
+    e = hipMemcpy2DAsync((void*)j.x, (size_t)t.D * 4, m->data, (size_t)st * 4, (size_t)t.D * 4, (size_t)j.l,
+                         hipMemcpyHostToDevice, c->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(arena + jobs_off, jobs.data(), n * sizeof(KmJob), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_kmeans((const KmJob*)(arena + jobs_off), jobs, iters, c->stream);
+  labels.assign(n, {});
+  for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+    DeviceTemplate& t = tps[i]->t;
+    t.codebook.resize((size_t)t.k * t.D);
+    labels[i].resize((size_t)jobs[i].l);
+    e = hipMemcpyAsync(t.codebook.data(), jobs[i].c32, t.codebook.size() * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(labels[i].data(), jobs[i].lab, labels[i].size(), hipMemcpyDeviceToHost, c->stream);
+  }
+  const hipError_t e2 = hipStreamSynchronize(c->stream);
+  hipFree(arena);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) return fail(VQNNF_EHIP, "k-means on the device: %s", hipGetErrorString(e));
+  return ok();
+}
+
+static vqnnf_status new_template(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, int32_t k, int32_t iters,
+                                 const vqnnf_filter_desc* bank, int32_t n_desc, vqnnf_template** out) {
   vqnnf_status s;
-  if (!out) return fail(VQNNF_EINVAL, "null output pointer");
-  *out = nullptr;
-  if ((s = check_ctx(ctx))) return s;
   if ((s = check_template_map(tmpl))) return s;
   if (k < 1 || k > kMaxK) return fail(VQNNF_EINVAL, "k=%d outside [1, %d]", k, kMaxK);
   if (iters < 0) return fail(VQNNF_EINVAL, "lloyd_iters must be >= 0");
@@ -821,13 +888,32 @@ static vqnnf_status make_template(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, const 
   t.D = tmpl->D;
   t.k = k;
   if ((s = expand_bank(bank, n_desc, t.w, t.h, t))) { delete tp; return s; }
+  *out = tp;
+  return ok();
+}
+
+static vqnnf_status make_template(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, const float* codebook,
+                                  int32_t k, int32_t iters, uint64_t seed,
+                                  const vqnnf_filter_desc* bank, int32_t n_desc,
+                                  vqnnf_template** out) {
+  vqnnf_status s;
+  if (!out) return fail(VQNNF_EINVAL, "null output pointer");
+  *out = nullptr;
+  if ((s = check_ctx(ctx))) return s;
+  vqnnf_template* tp = nullptr;
+  if ((s = new_template(ctx, tmpl, k, iters, bank, n_desc, &tp))) return s;
+  DeviceTemplate& t = tp->t;
   int64_t n = (int64_t)t.w * t.h;
   int64_t st = tmpl->pixel_stride ? tmpl->pixel_stride : tmpl->D;
   const float* td = (const float*)tmpl->data;
+  std::vector<std::vector<uint8_t>> lab;
   if (codebook) {
     for (int64_t i = 0; i < (int64_t)k * t.D; ++i)
       if (!std::isfinite(codebook[i])) { delete tp; return fail(VQNNF_EINVAL, "codebook: non-finite value"); }
     t.codebook.assign(codebook, codebook + (size_t)k * t.D);
+  } else if (ctx->has_device) {
+    std::vector<vqnnf_template*> one{tp};
+    if ((s = kmeans_device(ctx, one, &tmpl, iters, &seed, lab))) { delete tp; return s; }
   } else {
     std::vector<double> x((size_t)n * t.D);
     for (int64_t p = 0; p < n; ++p)
@@ -836,7 +922,11 @@ static vqnnf_status make_template(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, const 
     t.codebook.resize(c.size());
     for (size_t i = 0; i < c.size(); ++i) t.codebook[i] = (float)c[i];
   }
-  if ((s = finish_template(ctx, tp, tmpl))) { free_device(t); delete tp; return s; }
+  if ((s = finish_template(ctx, tp, tmpl, lab.empty() ? nullptr : lab[0].data()))) {
+    free_device(t);
+    delete tp;
+    return s;
+  }
   *out = tp;
   return ok();
 }
@@ -845,6 +935,57 @@ vqnnf_status vqnnf_codebook(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, int32_t k, i
                             uint64_t seed, const vqnnf_filter_desc* bank, int32_t n_desc,
                             vqnnf_template** out) {
   return make_template(ctx, tmpl, nullptr, k, lloyd_iters, seed, bank, n_desc, out);
+}
+
+vqnnf_status vqnnf_codebook_batched(vqnnf_ctx* ctx, int32_t n, const vqnnf_fmap* const* tmpls,
+                                    const int32_t* ks, int32_t lloyd_iters, const uint64_t* seeds,
+                                    const vqnnf_filter_desc* const* banks, const int32_t* n_descs,
+                                    vqnnf_template** out) {
+  vqnnf_status s;
+  if ((s = check_ctx(ctx))) return s;
+  if (n < 1 || !tmpls || !ks || !seeds || !banks || !n_descs || !out)
+    return fail(VQNNF_EINVAL, "batched codebooks: need n >= 1 and non-null arrays");
+  for (int i = 0; i < n; ++i) out[i] = nullptr;
+  std::vector<vqnnf_template*> tps;
+  auto drop = [&]() {
+    for (vqnnf_template* tp : tps) {
+      free_device(tp->t);
+      delete tp;
+    }
+  };
+  for (int i = 0; i < n; ++i) {
+    vqnnf_template* tp = nullptr;
+    if ((s = new_template(ctx, tmpls[i], ks[i], lloyd_iters, banks[i], n_descs[i], &tp))) {
+      const std::string msg = vqnnf_last_error();
+      drop();
+      return fail(s, "template %d: %s", i, msg.c_str());
+    }
+    tps.push_back(tp);
+  }
+  std::vector<std::vector<uint8_t>> lab;
+  if (ctx->has_device) {
+    if ((s = kmeans_device(ctx, tps, tmpls, lloyd_iters, seeds, lab))) { drop(); return s; }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      DeviceTemplate& t = tps[i]->t;
+      const int64_t np = (int64_t)t.w * t.h;
+      const int64_t st = tmpls[i]->pixel_stride ? tmpls[i]->pixel_stride : tmpls[i]->D;
+      const float* td = (const float*)tmpls[i]->data;
+      std::vector<double> x((size_t)np * t.D);
+      for (int64_t p = 0; p < np; ++p)
+        for (int d = 0; d < t.D; ++d) x[(size_t)p * t.D + d] = (double)td[p * st + d];
+      std::vector<double> c = kmeans_host(x, np, t.D, t.k, lloyd_iters, seeds[i]);
+      t.codebook.resize(c.size());
+      for (size_t q = 0; q < c.size(); ++q) t.codebook[q] = (float)c[q];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    if ((s = finish_template(ctx, tps[i], tmpls[i], lab.empty() ? nullptr : lab[i].data()))) {
+      drop();
+      return s;
+    }
+  for (int i = 0; i < n; ++i) out[i] = tps[i];
+  return ok();
 }
 
 vqnnf_status vqnnf_template_from_codebook(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl,

@@ -119,7 +119,10 @@ std::vector<double> kmeans_host(const std::vector<double>& x, int64_t n, int D, 
                                 uint64_t seed);
 std::vector<int> assign_host(const std::vector<double>& x, int64_t n, int D,
                              const std::vector<double>& c, int k);
-void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_stride);
+// Template NNF and R(tau) on the host; `labels` (h*w, optional) is the NNF
+// already computed on the device.
+void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_stride,
+                           const uint8_t* labels = nullptr);
 
 // Device-ready tables of a template, built on the host.
 struct HostTables {
@@ -226,11 +229,28 @@ size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W);
 int fused_default_tyw(const DeviceTemplate& t, int H, int W, int n_cu);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
 
+// k-means of one template's points on the device (all buffers device).
+struct KmJob {
+  const float* x;        // [l][D] points, FP32
+  double* c;             // [k][D] centres
+  float* c32;            // [k][D] final codebook
+  uint8_t* lab;          // [l] labels (after the call: NNF against c32)
+  int* idx;              // [l] points grouped by cluster, in point order
+  int* start;            // [k + 1] cluster offsets into idx
+  double* d2;            // [l] k-means++ D^2
+  double* csum;          // [l] its running sum
+  double* pdist;         // [ceil(k/16)][l] nearest distance per centre chunk
+  uint8_t* pidx;         // [ceil(k/16)][l] its centre
+  uint64_t seed;
+  int l, D, k, pad;
+};
+hipError_t launch_kmeans(const KmJob* d_jobs, const std::vector<KmJob>& jobs, int iters, hipStream_t s);
+
 // Kernel-name registry for timing.
 enum KernelId {
   K_FILL = 0, K_ASSIGN_PLAIN, K_ASSIGN_REFINED, K_RESCORE, K_INT_EDGE, K_INT_PREFIX,
   K_INT_MAIN, K_SCORE_FUSED, K_SCORE_COMBINE, K_SCORE_INTEGRAL, K_ASSIGN_MULTI, K_SCORE_BANK,
-  K_COUNT
+  K_KMEANS, K_COUNT
 };
 const char* kernel_name(int id);
 

@@ -339,18 +339,23 @@ void pack_frag_f32(const DeviceTemplate& t, const std::vector<float>& x, std::ve
 }  // namespace
 
 // Builds every host table of a template from its FP32 codebook.
-void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_stride) {
+void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_stride,
+                           const uint8_t* labels) {
   const int D = t.D, k = t.k;
   t.geom = make_assign_geom(k, D);
-  // template NNF with the exact FP64 rule
   int64_t n = (int64_t)t.w * t.h;
-  std::vector<double> x((size_t)n * D), c((size_t)k * D);
-  for (int64_t p = 0; p < n; ++p)
-    for (int d = 0; d < D; ++d) x[(size_t)p * D + d] = (double)tmpl[p * tmpl_stride + d];
-  for (size_t i = 0; i < c.size(); ++i) c[i] = (double)t.codebook[i];
-  std::vector<int> lab = assign_host(x, n, D, c, k);
-  t.labels.resize(n);
-  for (int64_t p = 0; p < n; ++p) t.labels[p] = (uint8_t)lab[p];
+  if (labels) {
+    t.labels.assign(labels, labels + n);
+  } else {
+    // template NNF with the exact FP64 rule
+    std::vector<double> x((size_t)n * D), c((size_t)k * D);
+    for (int64_t p = 0; p < n; ++p)
+      for (int d = 0; d < D; ++d) x[(size_t)p * D + d] = (double)tmpl[p * tmpl_stride + d];
+    for (size_t i = 0; i < c.size(); ++i) c[i] = (double)t.codebook[i];
+    std::vector<int> lab = assign_host(x, n, D, c, k);
+    t.labels.resize(n);
+    for (int64_t p = 0; p < n; ++p) t.labels[p] = (uint8_t)lab[p];
+  }
   // R(tau): per-filter counts over the template
   t.counts.clear();
   t.resp.clear();

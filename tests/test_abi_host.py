@@ -167,3 +167,19 @@ def test_scratch_cap_reports_enomem_before_any_device_call():
     with pytest.raises(B.VqnnfError) as ei:
         B.vqnnf_filter(ctx, tpl, FakeTensor(), 1024, 1024, FakeTensor())
     assert ei.value.status == B.VQNNF_ENOMEM
+
+
+def test_batched_codebooks_on_host_context():
+    ctx = B.Context(host=True)
+    ts = [synth.random_map(h, w, 12, "f32", seed=60 + h, M=8).data for h, w in [(10, 12), (14, 9), (8, 8)]]
+    ks, seeds = [4, 8, 5], [1, 2, 3]
+    banks = [B.default_bank(12, 10, 2), B.paper_bank(9, 14, "3rect", 1), B.default_bank(8, 8, 1)]
+    out = B.vqnnf_codebook_batched(ctx, ts, ks, 20, seeds, banks)
+    for i, tp in enumerate(out):
+        one = B.vqnnf_codebook(ctx, ts[i], ks[i], 20, seeds[i], banks[i])
+        assert np.array_equal(tp.codebook().view(np.uint32), one.codebook().view(np.uint32))
+        assert np.array_equal(tp.labels(), one.labels())
+        assert np.array_equal(tp.responses(), one.responses())
+    with pytest.raises(B.VqnnfError) as ei:
+        B.vqnnf_codebook_batched(ctx, ts, [4, 0, 5], 20, seeds, banks)
+    assert ei.value.status == B.VQNNF_EINVAL and "template 1" in str(ei.value)
