@@ -16,8 +16,8 @@
 //   * Lloyd: each point goes to its nearest centre (lowest index on ties);
 //     each centre becomes the sequential sum of its points in point order
 //     divided by their count; an empty cluster keeps its centre.
-// The running sum of D^2 is inherently serial and runs on one lane; the rest
-// is parallel over points, centres and dimensions.
+// The running sum of D^2 is inherently serial and runs on one wave per
+// template; the rest is parallel over points, centres and dimensions.
 #include "vqnnf_internal.h"
 
 #pragma clang fp contract(off)
@@ -28,7 +28,6 @@ namespace {
 
 constexpr int kKmCK = 16;     // centres per LDS chunk in the assignment
 constexpr int kKmTD = 256;    // dimensions per LDS chunk
-constexpr int kKmInitThreads = 1024;
 
 __device__ __forceinline__ uint64_t splitmix_next(uint64_t& s) {
   s += 0x9E3779B97F4A7C15ull;
@@ -47,120 +46,141 @@ __device__ __forceinline__ int uniform_index(double u, int n) {
   return f >= (double)(n - 1) ? n - 1 : (int)f;
 }
 
-// d(x_p, c) for one point against a centre staged in LDS in chunks of kKmTD.
-__device__ double sqdist_lds(const float* xp, const double* cs, int t0, int tn, double acc) {
-  for (int t = 0; t < tn; ++t) {
-    const double diff = (double)xp[t0 + t] - cs[t];
-    const double sq = diff * diff;
-    acc = acc + sq;
-  }
-  return acc;
-}
-
-// D^2 of every point to centre `ci` (already in c), folded into d2 by minimum
-// (first centre: written).  Whole block.
-__device__ void km_update_d2(const KmJob& j, int ci, bool first, double* cs) {
-  double acc[8];
-  const int n = j.l, D = j.D;
-  // points handled by this thread: p = tid + i * blockDim, up to 8 per pass
-  for (int p0 = 0; p0 < n; p0 += 8 * kKmInitThreads) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = 0.0;
-    for (int t0 = 0; t0 < D; t0 += kKmTD) {
-      const int tn = min(kKmTD, D - t0);
-      __syncthreads();
-      for (int t = threadIdx.x; t < tn; t += blockDim.x) cs[t] = j.c[(size_t)ci * D + t0 + t];
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int p = p0 + threadIdx.x + i * kKmInitThreads;
-        if (p < n) acc[i] = sqdist_lds(j.x + (size_t)p * D, cs, t0, tn, acc[i]);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int p = p0 + threadIdx.x + i * kKmInitThreads;
-      if (p < n) j.d2[p] = first ? acc[i] : (acc[i] < j.d2[p] ? acc[i] : j.d2[p]);
-    }
-  }
-  __syncthreads();
-}
-
-__device__ void copy_point_to_centre(const KmJob& j, int p, int ci) {
-  for (int t = threadIdx.x; t < j.D; t += blockDim.x)
-    j.c[(size_t)ci * j.D + t] = (double)j.x[(size_t)p * j.D + t];
-  __syncthreads();
-}
-
 }  // namespace
 
-// k-means++ seeding, one block per job.
-__global__ __launch_bounds__(kKmInitThreads) void km_init_kernel(const KmJob* jobs) {
-  const KmJob& j = jobs[blockIdx.x];
-  __shared__ double cs[kKmTD];
-  __shared__ double sh_total, sh_u;
-  __shared__ int sh_idx;
-  __shared__ int red[kKmInitThreads / 64];
-  uint64_t rng = j.seed;                 // every thread steps the same stream
-  const int n = j.l;
-  const int first = uniform_index(u01(rng), n);
-  copy_point_to_centre(j, first, 0);
-  km_update_d2(j, 0, true, cs);
-  for (int ci = 1; ci < j.k; ++ci) {
-    if (threadIdx.x == 0) {
-      double run = 0.0;
-      for (int p = 0; p < n; ++p) {
-        run = run + j.d2[p];
-        j.csum[p] = run;
+// k-means++, one draw per launch pair.  km_draw_kernel (one wave per job)
+// picks centre ci from the running sum of D^2 (ci = 0: a uniform draw) and
+// copies it; km_d2_kernel folds every point's distance to that centre into
+// D^2.  The generator state lives in state[0] between launches.
+__global__ __launch_bounds__(64) void km_draw_kernel(const KmJob* __restrict__ jobs, int ci) {
+  const KmJob j = jobs[blockIdx.x];
+  if (ci >= j.k) return;
+  __shared__ double chunk_s[64];
+  const int lane = threadIdx.x, n = j.l;
+  uint64_t rng = ci == 0 ? j.seed : j.state[0];
+  const double u = u01(rng);
+  int idx = -1;
+  if (ci == 0) {
+    idx = uniform_index(u, n);
+  } else {
+    // Strictly in point order.  Pass 1: S = the running sum over all points.
+    // Pass 2: the same running sum again, a chunk of 64 at a time (the sum
+    // never decreases, D^2 >= 0) until a chunk ends above u * S; that chunk is
+    // added once more point by point to find the first point above it.  Both
+    // passes perform exactly the additions of one serial running sum.
+    // Buffer loads bounded at n points: lanes past the end read 0; four chunks
+    // are in flight while one is added.
+    const __amdgpu_buffer_rsrc_t d2r = __builtin_amdgcn_make_buffer_rsrc(j.d2, (short)0, n * 8, 0x00020000);
+    auto ld = [&](int p) -> double {
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(d2r, (uint32_t)p * 8u, 0, 0));
+    };
+    // a chunk's values go through LDS so that every addend is read
+    // (broadcast) ahead of the dependent chain of additions
+    auto add_chunk = [&](double v, int cnt, double r) -> double {
+      chunk_s[lane] = v;
+      if (cnt >= 64) {
+#pragma unroll
+        for (int i = 0; i < 64; ++i) r = r + chunk_s[i];
+      } else {
+        for (int i = 0; i < cnt; ++i) r = r + chunk_s[i];
       }
-      sh_total = run;
+      return r;
+    };
+    double run = 0.0;
+    {
+      double q0 = ld(lane), q1 = ld(64 + lane), q2 = ld(128 + lane), q3 = ld(192 + lane);
+      for (int base = 0; base < n; base += 256) {
+        run = add_chunk(q0, n - base, run);
+        q0 = ld(base + 256 + lane);
+        run = add_chunk(q1, n - base - 64, run);
+        q1 = ld(base + 320 + lane);
+        run = add_chunk(q2, n - base - 128, run);
+        q2 = ld(base + 384 + lane);
+        run = add_chunk(q3, n - base - 192, run);
+        q3 = ld(base + 448 + lane);
+      }
     }
-    const double u = u01(rng);
-    __syncthreads();
-    const double total = sh_total;
-    int idx;
+    const double total = run;
     if (total == 0.0) {
       idx = uniform_index(u, n);
     } else {
       const double target = u * total;
-      // first p with csum[p] > target; else the last p with d2[p] > 0
-      int best = 0x7FFFFFFF, last = -1;
-      for (int p = threadIdx.x; p < n; p += blockDim.x) {
-        if (j.csum[p] > target && p < best) best = p;
-        if (j.d2[p] > 0.0) last = p;
+      run = 0.0;
+      double q0 = ld(lane), q1 = ld(64 + lane), q2 = ld(128 + lane), q3 = ld(192 + lane);
+      int hit = -1;                      // first chunk whose end exceeds the target
+      double before = 0.0;               // running sum before that chunk
+      double hv = 0.0;                   // its values
+      for (int base = 0; base < n && hit < 0; base += 256) {
+        double r = add_chunk(q0, n - base, run);
+        if (r > target) { hit = base; before = run; hv = q0; break; }
+        run = r;
+        q0 = ld(base + 256 + lane);
+        r = add_chunk(q1, n - base - 64, run);
+        if (r > target) { hit = base + 64; before = run; hv = q1; break; }
+        run = r;
+        q1 = ld(base + 320 + lane);
+        r = add_chunk(q2, n - base - 128, run);
+        if (r > target) { hit = base + 128; before = run; hv = q2; break; }
+        run = r;
+        q2 = ld(base + 384 + lane);
+        r = add_chunk(q3, n - base - 192, run);
+        if (r > target) { hit = base + 192; before = run; hv = q3; break; }
+        run = r;
+        q3 = ld(base + 448 + lane);
       }
+      if (hit >= 0) {
+        double r = before;
+        const int nb = min(64, n - hit);
+        chunk_s[lane] = hv;
+        for (int i = 0; i < nb; ++i) {
+          r = r + chunk_s[i];
+          if (r > target) { idx = hit + i; break; }
+        }
+      }
+      if (idx < 0) {
+        // no running sum exceeded u * S: the last point with D^2 > 0
+        int last = -1;
+        for (int p = lane; p < n; p += 64)
+          if (j.d2[p] > 0.0) last = p;
 #pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) {
-        best = min(best, __shfl_xor(best, m));
-        last = max(last, __shfl_xor(last, m));
+        for (int m = 32; m >= 1; m >>= 1) last = max(last, __shfl_xor(last, m));
+        idx = last;
       }
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int b = red[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = min(b, red[w]);
-        sh_idx = b;
-      }
-      __syncthreads();
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = last;
-      __syncthreads();
-      if (threadIdx.x == 0 && sh_idx == 0x7FFFFFFF) {
-        int l2 = red[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) l2 = max(l2, red[w]);
-        sh_idx = l2;
-      }
-      __syncthreads();
-      idx = sh_idx;
     }
-    copy_point_to_centre(j, idx, ci);
-    km_update_d2(j, ci, false, cs);
   }
+  for (int t = lane; t < j.D; t += 64) j.c[(size_t)ci * j.D + t] = (double)j.x[(size_t)idx * j.D + t];
+  if (lane == 0) j.state[0] = rng;
+}
+
+// D^2 of every point to centre ci, folded in by minimum (ci = 0: written).
+// Thread per point; the centre is staged in LDS in chunks of kKmTD.
+__global__ __launch_bounds__(256) void km_d2_kernel(const KmJob* __restrict__ jobs, int ci) {
+  const KmJob j = jobs[blockIdx.y];
+  if (ci >= j.k - 1 || (int64_t)blockIdx.x * 256 >= j.l) return;   // uniform per block
+  __shared__ double cs[kKmTD];
+  const int n = j.l, D = j.D;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const float* xtp = j.xt + min(p, n - 1);       // dimension-major: coalesced across the wave
+  double acc = 0.0;
+  for (int t0 = 0; t0 < D; t0 += kKmTD) {
+    const int tn = min(kKmTD, D - t0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < tn; t += 256) cs[t] = j.c[(size_t)ci * D + t0 + t];
+    __syncthreads();
+#pragma unroll 8
+    for (int t = 0; t < tn; ++t) {
+      const double diff = (double)xtp[(int64_t)(t0 + t) * n] - cs[t];
+      const double sq = diff * diff;
+      acc = acc + sq;
+    }
+  }
+  if (p < n) j.d2[p] = ci == 0 ? acc : (acc < j.d2[p] ? acc : j.d2[p]);
 }
 
 // Distances of a block of 256 points to one chunk of kKmCK centres (FP64
-// centres, or the FP32 codebook when c32in is set); writes the chunk's
+// centres, or the FP32 codebook when from_f32 is set); writes the chunk's
 // nearest centre (lowest index on ties) and its distance.
-__global__ __launch_bounds__(256) void km_assign_kernel(const KmJob* jobs, int from_f32) {
+__global__ __launch_bounds__(256) void km_assign_kernel(const KmJob* __restrict__ jobs, int from_f32) {
   const KmJob& j = jobs[blockIdx.z];
   const int n = j.l, D = j.D, k = j.k;
   const int c0 = blockIdx.y * kKmCK;
@@ -168,7 +188,7 @@ __global__ __launch_bounds__(256) void km_assign_kernel(const KmJob* jobs, int f
   const int nc = min(kKmCK, k - c0);
   __shared__ double cs[kKmCK][kKmTD];
   const int p = blockIdx.x * 256 + threadIdx.x;
-  const float* xp = j.x + (size_t)min(p, n - 1) * D;
+  const float* xtp = j.xt + min(p, n - 1);       // dimension-major: coalesced across the wave
   double acc[kKmCK];
 #pragma unroll
   for (int i = 0; i < kKmCK; ++i) acc[i] = 0.0;
@@ -183,8 +203,9 @@ __global__ __launch_bounds__(256) void km_assign_kernel(const KmJob* jobs, int f
       cs[ci][t] = v;
     }
     __syncthreads();
+#pragma unroll 4
     for (int t = 0; t < tn; ++t) {
-      const double xv = (double)xp[t0 + t];
+      const double xv = (double)xtp[(int64_t)(t0 + t) * n];
 #pragma unroll
       for (int i = 0; i < kKmCK; ++i) {
         const double diff = xv - cs[i][t];
@@ -207,7 +228,7 @@ __global__ __launch_bounds__(256) void km_assign_kernel(const KmJob* jobs, int f
 // Labels from the per-chunk nearest centres (chunks in index order, strict <
 // keeps the lowest index), then a stable counting sort of the points by
 // label: idx lists every cluster's points in increasing point order.
-__global__ __launch_bounds__(1024) void km_sort_kernel(const KmJob* jobs) {
+__global__ __launch_bounds__(1024) void km_sort_kernel(const KmJob* __restrict__ jobs) {
   const KmJob& j = jobs[blockIdx.x];
   const int n = j.l, k = j.k;
   const int nch = (k + kKmCK - 1) / kKmCK;
@@ -269,7 +290,7 @@ __global__ __launch_bounds__(1024) void km_sort_kernel(const KmJob* jobs) {
 
 // New centres: thread per (cluster, dimension), sequential sum of the
 // cluster's points in point order, divided by the count.
-__global__ __launch_bounds__(256) void km_update_kernel(const KmJob* jobs) {
+__global__ __launch_bounds__(256) void km_update_kernel(const KmJob* __restrict__ jobs) {
   const KmJob& j = jobs[blockIdx.y];
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)j.k * j.D) return;
@@ -277,11 +298,28 @@ __global__ __launch_bounds__(256) void km_update_kernel(const KmJob* jobs) {
   const int b = j.start[c], nb = j.start[c + 1] - b;
   if (nb == 0) return;                     // empty cluster keeps its centre
   double s = 0.0;
-  for (int m = 0; m < nb; ++m) s = s + (double)j.x[(size_t)j.idx[b + m] * j.D + t];
+  int m = 0;
+  for (; m + 8 <= nb; m += 8) {           // loads of 8 points ahead of their adds
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = j.x[(size_t)j.idx[b + m + q] * j.D + t];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s = s + (double)v[q];
+  }
+  for (; m < nb; ++m) s = s + (double)j.x[(size_t)j.idx[b + m] * j.D + t];
   j.c[e] = s / (double)nb;
 }
 
-__global__ __launch_bounds__(256) void km_round_kernel(const KmJob* jobs) {
+// Dimension-major copy of the points for the distance kernels.
+__global__ __launch_bounds__(256) void km_transpose_kernel(const KmJob* __restrict__ jobs) {
+  const KmJob& j = jobs[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)j.l * j.D) return;
+  const int t = (int)(e / j.l), p = (int)(e % j.l);
+  j.xt[e] = j.x[(size_t)p * j.D + t];
+}
+
+__global__ __launch_bounds__(256) void km_round_kernel(const KmJob* __restrict__ jobs) {
   const KmJob& j = jobs[blockIdx.y];
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e < (int64_t)j.k * j.D) j.c32[e] = (float)j.c[e];
@@ -290,16 +328,23 @@ __global__ __launch_bounds__(256) void km_round_kernel(const KmJob* jobs) {
 hipError_t launch_kmeans(const KmJob* d_jobs, const std::vector<KmJob>& jobs, int iters, hipStream_t s) {
   const int nj = (int)jobs.size();
   int max_l = 1, max_k = 1;
-  int64_t max_kd = 1;
+  int64_t max_kd = 1, max_ld = 1;
   for (const KmJob& j : jobs) {
     max_l = std::max(max_l, j.l);
     max_k = std::max(max_k, j.k);
     max_kd = std::max(max_kd, (int64_t)j.k * j.D);
+    max_ld = std::max(max_ld, (int64_t)j.l * j.D);
   }
   const dim3 ga((unsigned)((max_l + 255) / 256), (unsigned)((max_k + kKmCK - 1) / kKmCK), (unsigned)nj);
   const dim3 gu((unsigned)((max_kd + 255) / 256), (unsigned)nj);
   timing_begin(K_KMEANS);
-  hipLaunchKernelGGL(km_init_kernel, dim3(nj), dim3(kKmInitThreads), 0, s, d_jobs);
+  hipLaunchKernelGGL(km_transpose_kernel, dim3((unsigned)((max_ld + 255) / 256), (unsigned)nj), dim3(256), 0, s,
+                     d_jobs);
+  const dim3 gd((unsigned)((max_l + 255) / 256), (unsigned)nj);
+  for (int ci = 0; ci < max_k; ++ci) {
+    hipLaunchKernelGGL(km_draw_kernel, dim3(nj), dim3(64), 0, s, d_jobs, ci);
+    if (ci + 1 < max_k) hipLaunchKernelGGL(km_d2_kernel, gd, dim3(256), 0, s, d_jobs, ci);
+  }
   for (int it = 0; it < iters; ++it) {
     hipLaunchKernelGGL(km_assign_kernel, ga, dim3(256), 0, s, d_jobs, 0);
     hipLaunchKernelGGL(km_sort_kernel, dim3(nj), dim3(1024), 0, s, d_jobs);

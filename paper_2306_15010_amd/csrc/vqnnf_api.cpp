@@ -812,15 +812,15 @@ static vqnnf_status kmeans_device(vqnnf_ctx* c, const std::vector<vqnnf_template
   const size_t n = tps.size();
   std::vector<size_t> off(n + 1, 0);
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  struct Sz { size_t x, c, c32, lab, idx, start, d2, csum, pdist, pidx; };
+  struct Sz { size_t x, xt, c, c32, lab, idx, start, d2, state, pdist, pidx; };
   std::vector<Sz> sz(n);
   for (size_t i = 0; i < n; ++i) {
     const DeviceTemplate& t = tps[i]->t;
     const size_t l = (size_t)t.w * t.h, kd = (size_t)t.k * t.D, nch = (t.k + 15) / 16;
-    sz[i] = {al(l * t.D * 4), al(kd * 8), al(kd * 4), al(l), al(l * 4), al((t.k + 1) * 4), al(l * 8),
-             al(l * 8), al(nch * l * 8), al(nch * l)};
+    sz[i] = {al(l * t.D * 4), al(l * t.D * 4), al(kd * 8), al(kd * 4), al(l), al(l * 4), al((t.k + 1) * 4), al(l * 8), al(8),
+             al(nch * l * 8), al(nch * l)};
     const Sz& z = sz[i];
-    off[i + 1] = off[i] + z.x + z.c + z.c32 + z.lab + z.idx + z.start + z.d2 + z.csum + z.pdist + z.pidx;
+    off[i + 1] = off[i] + z.x + z.xt + z.c + z.c32 + z.lab + z.idx + z.start + z.d2 + z.state + z.pdist + z.pidx;
   }
   const size_t jobs_off = al(off[n]);
   const size_t total = jobs_off + al(n * sizeof(KmJob));
@@ -829,7 +829,7 @@ static vqnnf_status kmeans_device(vqnnf_ctx* c, const std::vector<vqnnf_template
   char* arena = nullptr;
   HIP_TRY(hipMalloc((void**)&arena, total));
   std::vector<KmJob> jobs(n);
-  std::vector<float> pts;
+  std::vector<std::vector<float>> packed(n);    // strided maps, packed (alive until the sync)
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < n && e == hipSuccess; ++i) {
     const DeviceTemplate& t = tps[i]->t;
@@ -837,13 +837,14 @@ static vqnnf_status kmeans_device(vqnnf_ctx* c, const std::vector<vqnnf_template
     char* b = arena + off[i];
     KmJob& j = jobs[i];
     j.x = (const float*)b; b += z.x;
+    j.xt = (float*)b; b += z.xt;
     j.c = (double*)b; b += z.c;
     j.c32 = (float*)b; b += z.c32;
     j.lab = (uint8_t*)b; b += z.lab;
     j.idx = (int*)b; b += z.idx;
     j.start = (int*)b; b += z.start;
     j.d2 = (double*)b; b += z.d2;
-    j.csum = (double*)b; b += z.csum;
+    j.state = (uint64_t*)b; b += z.state;
     j.pdist = (double*)b; b += z.pdist;
     j.pidx = (uint8_t*)b;
     j.seed = seeds[i];
@@ -852,8 +853,14 @@ static vqnnf_status kmeans_device(vqnnf_ctx* c, const std::vector<vqnnf_template
     j.k = t.k;
     const vqnnf_fmap* m = tmpls[i];
     const int64_t st = m->pixel_stride ? m->pixel_stride : m->D;
-    e = hipMemcpy2DAsync((void*)j.x, (size_t)t.D * 4, m->data, (size_t)st * 4, (size_t)t.D * 4, (size_t)j.l,
-                         hipMemcpyHostToDevice, c->stream);
+    const float* src = (const float*)m->data;
+    if (st != t.D) {   // one contiguous copy instead of one per pixel
+      packed[i].resize((size_t)j.l * t.D);
+      for (int64_t q = 0; q < j.l; ++q)
+        std::memcpy(&packed[i][(size_t)q * t.D], src + q * st, (size_t)t.D * 4);
+      src = packed[i].data();
+    }
+    e = hipMemcpyAsync((void*)j.x, src, (size_t)j.l * t.D * 4, hipMemcpyHostToDevice, c->stream);
   }
   if (e == hipSuccess)
     e = hipMemcpyAsync(arena + jobs_off, jobs.data(), n * sizeof(KmJob), hipMemcpyHostToDevice, c->stream);

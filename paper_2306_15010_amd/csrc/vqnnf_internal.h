@@ -232,13 +232,14 @@ hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
 // k-means of one template's points on the device (all buffers device).
 struct KmJob {
   const float* x;        // [l][D] points, FP32
+  float* xt;             // [D][l] the same, dimension-major
   double* c;             // [k][D] centres
   float* c32;            // [k][D] final codebook
   uint8_t* lab;          // [l] labels (after the call: NNF against c32)
   int* idx;              // [l] points grouped by cluster, in point order
   int* start;            // [k + 1] cluster offsets into idx
   double* d2;            // [l] k-means++ D^2
-  double* csum;          // [l] its running sum
+  uint64_t* state;       // [1] generator state between draws
   double* pdist;         // [ceil(k/16)][l] nearest distance per centre chunk
   uint8_t* pidx;         // [ceil(k/16)][l] its centre
   uint64_t seed;
