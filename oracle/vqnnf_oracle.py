@@ -12,7 +12,8 @@ the order of a floating-point sum matters.  numpy reductions such as `sum` are
 never used on floats, since they sum pairwise.
 
 Contents and the passages they follow:
-  O1  decode of stored values (FP32 / BF16 / FP8 E4M3FN x per-channel scale)
+  O1  decode of stored values (FP32 / BF16 / FP8 E4M3FN x per-channel scale;
+      RGB images as 3x3 colour patches, Sec. 5.2 "Feature Extraction")
   O2  k-means codebook: seeded k-means++ then Lloyd (Sec. 3.1, Sec. 4 "K-means
       computation", Sec. 5.2 "Codebook and NNF Generation")
   O3  nearest-codeword assignment (Alg. 1, Sec. 3.1; exact L2 NN, Sec. 5.2)
@@ -89,6 +90,27 @@ def decode_e4m3fn(codes: np.ndarray, scale: np.ndarray) -> np.ndarray:
     return v * np.asarray(scale, dtype=np.float32).astype(np.float64)
 
 
+def rgb_patch_features(img: np.ndarray) -> np.ndarray:
+    """Colour features (Sec. 5.2 "Feature Extraction"): every pixel's 3x3
+    neighbourhood of RGB values, 27 per pixel.  img: uint8 [H, W, 3].
+    Readings: feature t = (3*dy + dx)*3 + c holds channel c of the pixel at
+    offset (dx - 1, dy - 1), dx, dy in {0, 1, 2}; neighbours outside the image
+    take the nearest pixel inside (edge replication); values are the raw
+    0..255 integers (exact).  Returns float64 [H, W, 27]."""
+    im = np.asarray(img, dtype=np.uint8)
+    H, W, C = im.shape
+    if C != 3:
+        raise ValueError("RGB image expected")
+    out = np.zeros((H, W, 27), dtype=np.float64)
+    for dy in range(3):
+        ys = np.clip(np.arange(H) + dy - 1, 0, H - 1)
+        for dx in range(3):
+            xs = np.clip(np.arange(W) + dx - 1, 0, W - 1)
+            for c in range(3):
+                out[:, :, (3 * dy + dx) * 3 + c] = im[ys][:, xs, c].astype(np.float64)
+    return out
+
+
 def decode(dtype: str, data: np.ndarray, scale: Optional[np.ndarray] = None) -> np.ndarray:
     if dtype == "f32":
         return decode_f32(data)
@@ -96,6 +118,8 @@ def decode(dtype: str, data: np.ndarray, scale: Optional[np.ndarray] = None) -> 
         return decode_bf16(data)
     if dtype == "fp8":
         return decode_e4m3fn(data, scale)
+    if dtype == "rgb8":
+        return rgb_patch_features(data)
     raise ValueError(dtype)
 
 

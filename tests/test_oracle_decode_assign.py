@@ -134,3 +134,42 @@ def test_assign_follows_sequential_fp64_order():
     assert O.assign(q, c)[0] == 0
     # reversed order of the same terms would be caught: pairwise gives more
     assert (2 ** -54 + 2 ** -54) + (2 ** -54 + 2 ** -54) + 1.0 == 1.0 + 2 ** -52
+
+
+# ------------------------------------------------------------------ colour patches (Sec. 5.2)
+
+def test_rgb_patch_features_by_hand():
+    """2 x 3 image with distinct channel values; every feature of two pixels
+    written out from the definition (3x3 neighbourhood, edge replication)."""
+    img = np.arange(2 * 3 * 3, dtype=np.uint8).reshape(2, 3, 3) * 7
+    f = O.rgb_patch_features(img)
+    assert f.shape == (2, 3, 27)
+    # pixel (x=1, y=0): rows y-1 -> 0 (replicated), 0, 1; columns 0, 1, 2
+    expect = []
+    for yy in (0, 0, 1):
+        for xx in (0, 1, 2):
+            expect += [int(v) for v in img[yy, xx]]
+    assert f[0, 1].tolist() == expect
+    # corner pixel (x=2, y=1): rows 0, 1, 1; columns 1, 2, 2
+    expect = []
+    for yy in (0, 1, 1):
+        for xx in (1, 2, 2):
+            expect += [int(v) for v in img[yy, xx]]
+    assert f[1, 2].tolist() == expect
+    # the centre of each patch is the pixel itself
+    assert np.array_equal(f[:, :, 12:15], img.astype(np.float64))
+
+
+def test_rgb_patch_features_invariants():
+    rng = np.random.default_rng(3)
+    img = rng.integers(0, 256, size=(9, 11, 3)).astype(np.uint8)
+    f = O.rgb_patch_features(img)
+    # interior pixel: feature block (dy, dx) is the pixel at (x+dx-1, y+dy-1)
+    for dy in range(3):
+        for dx in range(3):
+            assert np.array_equal(f[1:-1, 1:-1, (3 * dy + dx) * 3:(3 * dy + dx) * 3 + 3],
+                                  img[dy:dy + 7, dx:dx + 9].astype(np.float64))
+    # a constant image gives identical features everywhere
+    c = np.full((4, 5, 3), 17, np.uint8)
+    assert np.all(O.rgb_patch_features(c) == 17)
+    assert np.array_equal(O.decode("rgb8", img), f)
