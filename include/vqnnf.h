@@ -50,7 +50,13 @@ typedef enum {
 typedef enum {
   VQNNF_F32 = 0,      /* IEEE binary32                                      */
   VQNNF_BF16 = 1,     /* bfloat16 bit patterns (uint16)                     */
-  VQNNF_FP8_E4M3 = 2  /* OCP E4M3FN codes (uint8) times a per-channel scale */
+  VQNNF_FP8_E4M3 = 2, /* OCP E4M3FN codes (uint8) times a per-channel scale */
+  /* uint8 RGB image whose features are its colour patches (Sec. 5.2
+   * "Feature Extraction"): D = 27, feature (3*dy + dx)*3 + c of pixel (x, y)
+   * is channel c of the pixel at (x + dx - 1, y + dy - 1), dx, dy in 0..2,
+   * neighbours outside the image replaced by the nearest pixel inside, values
+   * 0..255.  pixel_stride counts bytes (>= 3; 0 means 3). */
+  VQNNF_RGB8 = 3
 } vqnnf_dtype;
 
 /* Arithmetic used for the nearest-codeword search. */

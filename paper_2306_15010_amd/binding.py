@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvqnnf.so")
 
 VQNNF_OK, VQNNF_EINVAL, VQNNF_ENOMEM, VQNNF_EHIP, VQNNF_ENOTSUP, VQNNF_EHANDLE = range(6)
-VQNNF_F32, VQNNF_BF16, VQNNF_FP8_E4M3 = 0, 1, 2
+VQNNF_F32, VQNNF_BF16, VQNNF_FP8_E4M3, VQNNF_RGB8 = 0, 1, 2, 3
 VQNNF_PREC_FP32_PLAIN, VQNNF_PREC_BF16_REFINED = 0, 1
 
 EXPORTED = [
@@ -112,11 +112,16 @@ def last_error() -> str:
 
 # ------------------------------------------------------------------ maps
 
-_DT = {"f32": VQNNF_F32, "bf16": VQNNF_BF16, "fp8": VQNNF_FP8_E4M3}
+_DT = {"f32": VQNNF_F32, "bf16": VQNNF_BF16, "fp8": VQNNF_FP8_E4M3, "rgb8": VQNNF_RGB8}
 
 
 def host_fmap(arr: np.ndarray) -> Tuple[FMap, np.ndarray]:
-    """FP32 host map [H][W][D] (the array is kept alive by the caller)."""
+    """Host map [H][W][D] as FP32, or a uint8 RGB image [H][W][3] (its 27
+    colour features); the array is kept alive by the caller."""
+    if arr.dtype == np.uint8 and arr.ndim == 3 and arr.shape[2] == 3:
+        a = np.ascontiguousarray(arr)
+        H, W, _ = a.shape
+        return FMap(a.ctypes.data, VQNNF_RGB8, H, W, 27, 3, None), a
     a = np.ascontiguousarray(arr, dtype=np.float32)
     H, W, D = a.shape
     return FMap(a.ctypes.data, VQNNF_F32, H, W, D, D, None), a
@@ -124,9 +129,12 @@ def host_fmap(arr: np.ndarray) -> Tuple[FMap, np.ndarray]:
 
 def device_fmap(t, dtype: str, channel_scale: Optional[np.ndarray] = None) -> FMap:
     """Device map from a torch tensor [H][W][D] (float32 / uint16 bits /
-    bfloat16 / uint8 E4M3FN codes with host FP32 channel_scale[D])."""
+    bfloat16 / uint8 E4M3FN codes with host FP32 channel_scale[D] / uint8 RGB
+    pixels of S >= 3 bytes, "rgb8")."""
     H, W, S = t.shape[0], t.shape[1], t.shape[2]
     assert t.is_contiguous()
+    if dtype == "rgb8":          # uint8 [H][W][S >= 3]: colour features, D = 27
+        return FMap(t.data_ptr(), VQNNF_RGB8, H, W, 27, S, None)
     scale = None
     if channel_scale is not None:
         channel_scale = np.ascontiguousarray(channel_scale, dtype=np.float32)

@@ -18,7 +18,7 @@ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
 
 
 // Query storage of a kernel instance.
-constexpr int kQBF16 = 0, kQF32 = 1, kQFP8 = 2;
+constexpr int kQBF16 = 0, kQF32 = 1, kQFP8 = 2, kQRGB8 = 3;
 
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 

@@ -28,7 +28,7 @@ const char* const kNames[K_COUNT] = {
     "fill",           "assign_fp32_plain", "assign_bf16_refined", "rescore_fp64",
     "integral_edges", "integral_prefix",   "integral_main",       "score_partial",
     "score_combine",  "score_integral", "assign_multi", "score_bank",
-    "kmeans"};
+    "kmeans",         "assign_lowd"};
 }  // namespace
 
 void set_timing_hook(const TimingHook* h) {
@@ -619,6 +619,7 @@ struct RParams {
   const uint32_t* wl_pix;
   const uint32_t* wl_mask;
   uint8_t* labels;
+  int img_w, img_h;          // RGB images: colour features are built from pixels
 };
 
 constexpr int kRPix = 32;    // worklist pixels per wave
@@ -745,6 +746,24 @@ __device__ double seq_dist(const void* q, int64_t qoff, const float* c, int D, c
   return acc;
 }
 
+// The same sequential FP64 distance for a colour feature of an RGB image:
+// element t = (3*dy + dx)*3 + c is channel c of the pixel at (x + dx - 1,
+// y + dy - 1), edges replicated (D = 27).
+__device__ double seq_dist_rgb(const RParams& p, uint32_t pix, const float* c) {
+#pragma clang fp contract(off)
+  const uint8_t* img = (const uint8_t*)p.q;
+  const int y = (int)(pix / (uint32_t)p.img_w), x = (int)(pix - (uint32_t)y * (uint32_t)p.img_w);
+  double acc = 0.0;
+  for (int t = 0; t < 27; ++t) {
+    const int dy = t / 9, dx = (t / 3) % 3, ch = t % 3;
+    const int yy = min(max(y + dy - 1, 0), p.img_h - 1), xx = min(max(x + dx - 1, 0), p.img_w - 1);
+    const double dq = (double)img[((int64_t)yy * p.img_w + xx) * p.stride + ch] - (double)c[t];
+    const double sq = dq * dq;
+    acc = acc + sq;
+  }
+  return acc;
+}
+
 template <int QT, bool VEC>
 __global__ __launch_bounds__(64) void rescore_kernel(RParams p) {
   __shared__ uint32_t pfx[kRPix + 1];   // exclusive prefix of candidate counts
@@ -777,8 +796,12 @@ __global__ __launch_bounds__(64) void rescore_kernel(RParams p) {
         for (int step = kRPix / 2; step >= 1; step >>= 1)
           if (pfx[s + step] <= P) s += step;
         j = nth_candidate(p.wl_mask + (int64_t)(g0 + s) * mw, mw, p.k, P - pfx[s]);
-        const int64_t qoff = (int64_t)p.wl_pix[g0 + s] * p.stride;
-        d = seq_dist<QT, VEC>(p.q, qoff, p.codebook + (int64_t)j * p.D, p.D, p.scale);
+        if constexpr (QT == kQRGB8) {
+          d = seq_dist_rgb(p, p.wl_pix[g0 + s], p.codebook + (int64_t)j * p.D);
+        } else {
+          const int64_t qoff = (int64_t)p.wl_pix[g0 + s] * p.stride;
+          d = seq_dist<QT, VEC>(p.q, qoff, p.codebook + (int64_t)j * p.D, p.D, p.scale);
+        }
       }
       rd[lane] = d;
       rj[lane] = j;
@@ -960,6 +983,8 @@ hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu) {
   rp.wl_pix = a.wl_pix;
   rp.wl_mask = a.wl_mask;
   rp.labels = a.labels;
+  rp.img_w = a.img_w;
+  rp.img_h = a.img_h;
   const int qt = qtype(a.dtype);
   // whole steps of 8 elements: query rows aligned to the step width (16 bytes;
   // 8 for FP8 codes) and codeword rows 16-byte aligned
@@ -967,7 +992,8 @@ hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu) {
   const int grid = n_cu * 4;   // one wave per block; waves stride over the worklist
   timing_begin(K_RESCORE);
   hipError_t e;
-  if (qt == kQF32) e = go_rescore<kQF32>(rp, grid, vec, s);
+  if (a.dtype == VQNNF_RGB8) e = go_rescore<kQRGB8>(rp, grid, false, s);
+  else if (qt == kQF32) e = go_rescore<kQF32>(rp, grid, vec, s);
   else if (qt == kQFP8) e = go_rescore<kQFP8>(rp, grid, vec, s);
   else e = go_rescore<kQBF16>(rp, grid, vec, s);
   timing_end(K_RESCORE);

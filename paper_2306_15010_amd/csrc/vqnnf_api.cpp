@@ -221,8 +221,15 @@ size_t dtype_size(int dt) {
     case VQNNF_F32: return 4;
     case VQNNF_BF16: return 2;
     case VQNNF_FP8_E4M3: return 1;
+    case VQNNF_RGB8: return 1;
   }
   return 0;
+}
+
+// Elements between pixels (bytes for an RGB image, whose pixel is 3 bytes).
+int64_t map_stride(const vqnnf_fmap* m) {
+  if (m->pixel_stride) return m->pixel_stride;
+  return m->dtype == VQNNF_RGB8 ? 3 : m->D;
 }
 
 vqnnf_status check_map(const vqnnf_fmap* m, const char* what) {
@@ -231,8 +238,13 @@ vqnnf_status check_map(const vqnnf_fmap* m, const char* what) {
   if (dtype_size(m->dtype) == 0) return fail(VQNNF_EINVAL, "%s: unknown dtype %d", what, m->dtype);
   if (m->H < 1 || m->W < 1) return fail(VQNNF_EINVAL, "%s: H and W must be >= 1 (got %d x %d)", what, m->H, m->W);
   if (m->D < 1) return fail(VQNNF_EINVAL, "%s: D must be >= 1 (got %d)", what, m->D);
-  int64_t st = m->pixel_stride ? m->pixel_stride : m->D;
-  if (st < m->D) return fail(VQNNF_EINVAL, "%s: pixel_stride %lld < D %d", what, (long long)st, m->D);
+  const int64_t st = map_stride(m);
+  if (m->dtype == VQNNF_RGB8) {
+    if (m->D != 27) return fail(VQNNF_EINVAL, "%s: an RGB map has D = 27 colour features (got %d)", what, m->D);
+    if (st < 3) return fail(VQNNF_EINVAL, "%s: RGB pixel_stride %lld < 3 bytes", what, (long long)st);
+  } else if (st < m->D) {
+    return fail(VQNNF_EINVAL, "%s: pixel_stride %lld < D %d", what, (long long)st, m->D);
+  }
   if ((int64_t)m->H * m->W >= (1ll << 31)) return fail(VQNNF_EINVAL, "%s: H*W must be < 2^31", what);
   if (st * (int64_t)dtype_size(m->dtype) > (1ll << 22))
     return fail(VQNNF_EINVAL, "%s: a pixel row (pixel_stride * element size) must be <= 4 MiB", what);
@@ -486,9 +498,11 @@ vqnnf_status finish_template(vqnnf_ctx* ctx, vqnnf_template* tp, const vqnnf_fma
 vqnnf_status check_template_map(const vqnnf_fmap* tmpl) {
   vqnnf_status s = check_map(tmpl, "template");
   if (s) return s;
-  if (tmpl->dtype != VQNNF_F32) return fail(VQNNF_EINVAL, "template: dtype must be VQNNF_F32");
+  if (tmpl->dtype != VQNNF_F32 && tmpl->dtype != VQNNF_RGB8)
+    return fail(VQNNF_EINVAL, "template: dtype must be VQNNF_F32 or VQNNF_RGB8");
   if (tmpl->H > 255 || tmpl->W > 255)
     return fail(VQNNF_EINVAL, "template: sides must be <= 255 (window histograms are 16-bit)");
+  if (tmpl->dtype == VQNNF_RGB8) return ok();
   for (int64_t p = 0; p < (int64_t)tmpl->H * tmpl->W; ++p) {
     const float* v = (const float*)tmpl->data + p * (tmpl->pixel_stride ? tmpl->pixel_stride : tmpl->D);
     for (int d = 0; d < tmpl->D; ++d)
@@ -543,7 +557,9 @@ vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap
   const DeviceTemplate& t = tp->t;
   AssignArgs a{};
   a.q = q->data;
-  a.stride = q->pixel_stride ? q->pixel_stride : q->D;
+  a.stride = map_stride(q);
+  a.img_w = q->W;
+  a.img_h = q->H;
   a.n_pix = (int64_t)q->H * q->W;
   a.D = q->D;
   a.dtype = q->dtype;
@@ -558,8 +574,10 @@ vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap
   a.frag_bf16 = ss ? ss->d_frag_bf16 : t.d_frag_bf16;
   a.frag_f32 = ss ? ss->d_frag_f32 : t.d_frag_f32;
   a.scale = ss ? ss->d_scale : nullptr;
+  const bool lowd = lowd_supported(q->dtype, q->D);
   if (prec == VQNNF_PREC_FP32_PLAIN) {
-    HIP_TRY(launch_assign_plain(a, c->stream, c->n_cu));
+    if (lowd) HIP_TRY(launch_assign_lowd(a, false, c->stream));
+    else HIP_TRY(launch_assign_plain(a, c->stream, c->n_cu));
     return ok();
   }
   a.wl_count = (uint32_t*)((char*)c->control.p + 8);
@@ -567,7 +585,8 @@ vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap
   a.wl_mask = (uint32_t*)c->wl_mask.p;
   a.bound = ss ? ss->bound : (q->dtype == VQNNF_F32) ? t.bound_f32q : t.bound_bf16q;
   if (!counter_zeroed) HIP_TRY(launch_fill_u32(a.wl_count, 0u, 1, c->stream));
-  HIP_TRY(launch_assign_refined(a, c->stream, c->n_cu));
+  if (lowd) HIP_TRY(launch_assign_lowd(a, true, c->stream));
+  else HIP_TRY(launch_assign_refined(a, c->stream, c->n_cu));
   HIP_TRY(launch_rescore(a, c->stream, c->n_cu));
   return ok();
 }
@@ -899,6 +918,21 @@ static vqnnf_status new_template(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, int32_t
   return ok();
 }
 
+// An RGB template as its FP32 colour features (the map `f` points at `buf`).
+static vqnnf_status rgb_template_features(const vqnnf_fmap* m, std::vector<float>& buf, vqnnf_fmap& f) {
+  vqnnf_status s = check_template_map(m);
+  if (s) return s;
+  buf.resize((size_t)m->H * m->W * 27);
+  rgb_patch_features_host((const uint8_t*)m->data, m->H, m->W, map_stride(m), buf.data());
+  f = *m;
+  f.data = buf.data();
+  f.dtype = VQNNF_F32;
+  f.D = 27;
+  f.pixel_stride = 27;
+  f.channel_scale = nullptr;
+  return ok();
+}
+
 static vqnnf_status make_template(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, const float* codebook,
                                   int32_t k, int32_t iters, uint64_t seed,
                                   const vqnnf_filter_desc* bank, int32_t n_desc,
@@ -907,6 +941,12 @@ static vqnnf_status make_template(vqnnf_ctx* ctx, const vqnnf_fmap* tmpl, const 
   if (!out) return fail(VQNNF_EINVAL, "null output pointer");
   *out = nullptr;
   if ((s = check_ctx(ctx))) return s;
+  std::vector<float> rgb_buf;
+  vqnnf_fmap rgb_f{};
+  if (tmpl && tmpl->dtype == VQNNF_RGB8) {
+    if ((s = rgb_template_features(tmpl, rgb_buf, rgb_f))) return s;
+    tmpl = &rgb_f;
+  }
   vqnnf_template* tp = nullptr;
   if ((s = new_template(ctx, tmpl, k, iters, bank, n_desc, &tp))) return s;
   DeviceTemplate& t = tp->t;
@@ -953,6 +993,19 @@ vqnnf_status vqnnf_codebook_batched(vqnnf_ctx* ctx, int32_t n, const vqnnf_fmap*
   if (n < 1 || !tmpls || !ks || !seeds || !banks || !n_descs || !out)
     return fail(VQNNF_EINVAL, "batched codebooks: need n >= 1 and non-null arrays");
   for (int i = 0; i < n; ++i) out[i] = nullptr;
+  // RGB templates as their FP32 colour features
+  std::vector<std::vector<float>> rgb_buf(n);
+  std::vector<vqnnf_fmap> rgb_f(n);
+  std::vector<const vqnnf_fmap*> maps(tmpls, tmpls + n);
+  for (int i = 0; i < n; ++i)
+    if (tmpls[i] && tmpls[i]->dtype == VQNNF_RGB8) {
+      if ((s = rgb_template_features(tmpls[i], rgb_buf[i], rgb_f[i]))) {
+        const std::string msg = vqnnf_last_error();
+        return fail(s, "template %d: %s", i, msg.c_str());
+      }
+      maps[i] = &rgb_f[i];
+    }
+  tmpls = maps.data();
   std::vector<vqnnf_template*> tps;
   auto drop = [&]() {
     for (vqnnf_template* tp : tps) {
@@ -1237,8 +1290,8 @@ namespace {
 std::vector<std::vector<int>> group_by_map(int n, const vqnnf_fmap* const* q) {
   std::vector<std::vector<int>> groups;
   auto same = [](const vqnnf_fmap* a, const vqnnf_fmap* b) {
-    const int64_t sa = a->pixel_stride ? a->pixel_stride : a->D;
-    const int64_t sb = b->pixel_stride ? b->pixel_stride : b->D;
+    const int64_t sa = map_stride(a);
+    const int64_t sb = map_stride(b);
     return a->data == b->data && a->dtype == b->dtype && a->H == b->H && a->W == b->W &&
            a->D == b->D && sa == sb && a->channel_scale == b->channel_scale;
   };

@@ -121,6 +121,7 @@ std::vector<int> assign_host(const std::vector<double>& x, int64_t n, int D,
                              const std::vector<double>& c, int k);
 // Template NNF and R(tau) on the host; `labels` (h*w, optional) is the NNF
 // already computed on the device.
+void rgb_patch_features_host(const uint8_t* img, int H, int W, int64_t stride, float* out);
 void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_stride,
                            const uint8_t* labels = nullptr);
 
@@ -150,6 +151,7 @@ struct AssignArgs {
   const uint4* frag_bf16;  // codebook fragments (the template's, or its FP8 ScaledSet's)
   const float* frag_f32;
   const float* scale;      // FP8 maps: [D] device channel scales; else null
+  int img_w, img_h;        // RGB maps: image size (colour features built per pixel)
   uint8_t* labels;
   // refined path only
   uint32_t* wl_count;    // worklist counter (must be 0 on entry)
@@ -191,6 +193,11 @@ hipError_t launch_assign_multi(const MultiArgs& a, hipStream_t s, int n_cu);
 hipError_t launch_assign_plain(const AssignArgs& a, hipStream_t s, int n_cu);
 hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu);
 hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu);
+// Low-dimensional features (F32 / BF16, D <= 32) and RGB colour features:
+// direct FP32 distances with a relative error bound; `refined` appends
+// near ties to the re-score worklist.
+bool lowd_supported(int dtype, int D);
+hipError_t launch_assign_lowd(const AssignArgs& a, bool refined, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
 struct IntegralArgs {
@@ -251,7 +258,7 @@ hipError_t launch_kmeans(const KmJob* d_jobs, const std::vector<KmJob>& jobs, in
 enum KernelId {
   K_FILL = 0, K_ASSIGN_PLAIN, K_ASSIGN_REFINED, K_RESCORE, K_INT_EDGE, K_INT_PREFIX,
   K_INT_MAIN, K_SCORE_FUSED, K_SCORE_COMBINE, K_SCORE_INTEGRAL, K_ASSIGN_MULTI, K_SCORE_BANK,
-  K_KMEANS, K_COUNT
+  K_KMEANS, K_ASSIGN_LOWD, K_COUNT
 };
 const char* kernel_name(int id);
 

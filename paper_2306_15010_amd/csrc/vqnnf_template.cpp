@@ -338,6 +338,23 @@ void pack_frag_f32(const DeviceTemplate& t, const std::vector<float>& x, std::ve
 
 }  // namespace
 
+// Colour features of an RGB image: feature (3*dy + dx)*3 + c of pixel (x, y)
+// is channel c of the pixel at (x + dx - 1, y + dy - 1), edges replicated.
+void rgb_patch_features_host(const uint8_t* img, int H, int W, int64_t stride, float* out) {
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      float* f = out + ((size_t)y * W + x) * 27;
+      for (int dy = 0; dy < 3; ++dy) {
+        const int yy = std::min(std::max(y + dy - 1, 0), H - 1);
+        for (int dx = 0; dx < 3; ++dx) {
+          const int xx = std::min(std::max(x + dx - 1, 0), W - 1);
+          const uint8_t* p = img + ((int64_t)yy * W + xx) * stride;
+          for (int c = 0; c < 3; ++c) f[(3 * dy + dx) * 3 + c] = (float)p[c];
+        }
+      }
+    }
+}
+
 // Builds every host table of a template from its FP32 codebook.
 void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_stride,
                            const uint8_t* labels) {

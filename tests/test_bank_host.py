@@ -145,3 +145,21 @@ def test_weighted_bank_errors():
     with pytest.raises(B.VqnnfError) as ei:
         B.vqnnf_score(ctx, tpl, FakeTensor(0x2000), 32, 32, FakeTensor(0x3000))
     assert ei.value.status == B.VQNNF_ENOTSUP and "vqnnf_score_integral" in str(ei.value)
+
+
+def test_rgb_template_on_host_context_matches_oracle():
+    """An RGB template: its colour features (3x3 patches), k-means codebook and
+    NNF equal the oracle's bit for bit."""
+    ctx = B.Context(host=True)
+    img = synth.rgb_image(30, 34, seed=5)
+    tpl = B.vqnnf_codebook(ctx, img, 12, 20, 2, B.default_bank(34, 30, 2))
+    feats = O.rgb_patch_features(img)
+    ref = O.kmeans_codebook(feats.astype(np.float32), 12, 20, 2)
+    assert np.array_equal(tpl.codebook().view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(tpl.labels(), O.assign_map(feats, ref.astype(np.float64)).astype(np.uint8))
+    # an RGB map must declare its 27 colour features
+    bad = B.FMap(img.ctypes.data, B.VQNNF_RGB8, 30, 34, 26, 3, None)
+    h = C.c_void_p()
+    st = B.lib().vqnnf_codebook(ctx.h, C.byref(bad), 4, 5, 0, B.bank_descs(B.default_bank(34, 30, 2)), 2,
+                                C.byref(h))
+    assert st == B.VQNNF_EINVAL
