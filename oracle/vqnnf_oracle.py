@@ -13,7 +13,8 @@ never used on floats, since they sum pairwise.
 
 Contents and the passages they follow:
   O1  decode of stored values (FP32 / BF16 / FP8 E4M3FN x per-channel scale;
-      RGB images as 3x3 colour patches, Sec. 5.2 "Feature Extraction")
+      RGB images as 3x3 colour patches, Sec. 5.2 "Feature Extraction");
+      O1b PCA reduction of the features (Sec. 5.5)
   O2  k-means codebook: seeded k-means++ then Lloyd (Sec. 3.1, Sec. 4 "K-means
       computation", Sec. 5.2 "Codebook and NNF Generation")
   O3  nearest-codeword assignment (Alg. 1, Sec. 3.1; exact L2 NN, Sec. 5.2)
@@ -121,6 +122,41 @@ def decode(dtype: str, data: np.ndarray, scale: Optional[np.ndarray] = None) -> 
     if dtype == "rgb8":
         return rgb_patch_features(data)
     raise ValueError(dtype)
+
+
+# --------------------------------------------------------------------------
+# O1b: dimensionality reduction (Sec. 5.5): PCA of the template's features.
+#
+# Readings (the paper names only "PCA" and the target sizes 9 and 18): the
+# principal axes are fitted on the template's pixels (mean-centred, covariance
+# normalised by the pixel count), the d axes of largest variance in
+# decreasing order, each with its largest-magnitude component positive (the
+# first such component on ties); template and query are both projected onto
+# them after subtracting the template mean.
+
+def pca_fit(x: np.ndarray, d: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """x: float64 [n, D] -> (mean [D], basis [d, D], variances [d])."""
+    x = np.asarray(x, dtype=np.float64)
+    n, D = x.shape
+    mean = np.zeros(D)
+    for i in range(n):                      # sequential sum in point order
+        mean = mean + x[i]
+    mean = mean / float(n)
+    xc = x - mean
+    cov = (xc.T @ xc) / float(n)            # library matmul: a step, not the method
+    w, v = np.linalg.eigh(cov)              # ascending eigenvalues
+    order = np.argsort(-w, kind="stable")[:d]
+    basis = v[:, order].T.copy()
+    for r in range(d):
+        j = int(np.argmax(np.abs(basis[r])))
+        if basis[r, j] < 0:
+            basis[r] = -basis[r]
+    return mean, basis, w[order]
+
+
+def pca_project(x: np.ndarray, mean: np.ndarray, basis: np.ndarray) -> np.ndarray:
+    """(x - mean) . basis^T for every row of x [..., D] -> [..., d]."""
+    return (np.asarray(x, dtype=np.float64) - mean) @ np.asarray(basis, dtype=np.float64).T
 
 
 # --------------------------------------------------------------------------
