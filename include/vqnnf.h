@@ -175,6 +175,27 @@ vqnnf_status vqnnf_codebook_batched(vqnnf_ctx* ctx, int32_t n, const vqnnf_fmap*
                                     const vqnnf_filter_desc* const* banks, const int32_t* n_descs,
                                     vqnnf_template** out);
 
+/* Dimensionality reduction (Sec. 5.5): PCA of the template's features, the
+ * pixels mean-centred, covariance normalised by the pixel count (FP64), the d
+ * axes of largest variance in decreasing order, each with its
+ * largest-magnitude component positive.
+ *  tmpl: HOST map (F32, or RGB8 for colour features), as for vqnnf_codebook.
+ *  d in [1, min(D, 64)].  mean: HOST float[D]; basis: HOST float[d][D] (row i
+ *  is axis i); variances: HOST float[d] or NULL.  Host only; EINVAL on bad
+ *  arguments. */
+vqnnf_status vqnnf_pca_fit(const vqnnf_fmap* tmpl, int32_t d, float* mean, float* basis, float* variances);
+
+/* Projects a DEVICE map onto d axes: out[(y*W + x)*d + i] =
+ * sum_t (q_t - mean_t) * basis[i][t] for every pixel, in FP32 (the
+ * subtraction rounded, products accumulated by FMA in increasing t), where
+ * q_t is the map's element value (FP8: code x scale rounded to FP32; RGB8:
+ * colour feature t).  mean/basis: HOST, as from vqnnf_pca_fit; out: DEVICE
+ * float[H*W*d].  The result is an F32 map of D = d for vqnnf_codebook (after
+ * copying a projected template back) and every matching call.  Asynchronous
+ * on the context stream. */
+vqnnf_status vqnnf_pca_project(vqnnf_ctx* ctx, const vqnnf_fmap* map, const float* mean,
+                               const float* basis, int32_t d, float* out);
+
 /* Same as vqnnf_codebook but with a caller-supplied codebook (host float
  * [k][D], FP32) instead of k-means: used to restore an exported template and
  * to run every stage against an independently computed codebook. */

@@ -22,7 +22,7 @@ VQNNF_PREC_FP32_PLAIN, VQNNF_PREC_BF16_REFINED = 0, 1
 
 EXPORTED = [
     "vqnnf_ctx_create", "vqnnf_ctx_create_host", "vqnnf_ctx_destroy", "vqnnf_codebook",
-    "vqnnf_codebook_batched",
+    "vqnnf_codebook_batched", "vqnnf_pca_fit", "vqnnf_pca_project",
     "vqnnf_template_from_codebook", "vqnnf_template_free", "vqnnf_template_info",
     "vqnnf_template_codebook", "vqnnf_template_labels", "vqnnf_template_counts",
     "vqnnf_template_weights", "vqnnf_template_responses", "vqnnf_paper_bank", "vqnnf_assign", "vqnnf_filter", "vqnnf_score",
@@ -69,6 +69,8 @@ def lib() -> C.CDLL:
         "vqnnf_ctx_destroy": (None, [vp]),
         "vqnnf_codebook": (st, [vp, P(FMap), i32, i32, u64, P(FilterDesc), i32, P(vp)]),
         "vqnnf_template_from_codebook": (st, [vp, P(FMap), vp, i32, P(FilterDesc), i32, P(vp)]),
+        "vqnnf_pca_fit": (st, [P(FMap), i32, vp, vp, vp]),
+        "vqnnf_pca_project": (st, [vp, P(FMap), vp, vp, i32, vp]),
         "vqnnf_codebook_batched": (st, [vp, i32, P(P(FMap)), P(i32), i32, P(u64), P(P(FilterDesc)),
                                         P(i32), P(vp)]),
         "vqnnf_template_free": (None, [vp]),
@@ -290,6 +292,24 @@ def vqnnf_codebook(ctx: Context, template: np.ndarray, k: int, lloyd_iters: int,
     _check(lib().vqnnf_codebook(ctx.h, C.byref(fm), k, lloyd_iters, seed, descs, len(bank),
                                 C.byref(h)))
     return Template(ctx, h)
+
+
+def vqnnf_pca_fit(template: np.ndarray, d: int):
+    """vqnnf_pca_fit: (mean [D], basis [d][D], variances [d]) of a host template."""
+    fm, keep = host_fmap(template)
+    mean = np.empty(fm.D, np.float32)
+    basis = np.empty((d, fm.D), np.float32)
+    var = np.empty(d, np.float32)
+    _check(lib().vqnnf_pca_fit(C.byref(fm), d, mean.ctypes.data, basis.ctypes.data, var.ctypes.data))
+    return mean, basis, var
+
+
+def vqnnf_pca_project(ctx: Context, query: FMap, mean: np.ndarray, basis: np.ndarray, out) -> None:
+    """vqnnf_pca_project into the device tensor `out` ([H][W][d] float32)."""
+    m = np.ascontiguousarray(mean, np.float32)
+    b = np.ascontiguousarray(basis, np.float32)
+    _check(lib().vqnnf_pca_project(ctx.h, C.byref(query), m.ctypes.data, b.ctypes.data, b.shape[0],
+                                   out.data_ptr()))
 
 
 def vqnnf_codebook_batched(ctx: Context, templates: Sequence[np.ndarray], ks: Sequence[int],

@@ -28,7 +28,7 @@ const char* const kNames[K_COUNT] = {
     "fill",           "assign_fp32_plain", "assign_bf16_refined", "rescore_fp64",
     "integral_edges", "integral_prefix",   "integral_main",       "score_partial",
     "score_combine",  "score_integral", "assign_multi", "score_bank",
-    "kmeans",         "assign_lowd"};
+    "kmeans",         "assign_lowd",       "pca_project"};
 }  // namespace
 
 void set_timing_hook(const TimingHook* h) {

@@ -72,6 +72,7 @@ struct vqnnf_ctx {
   Buffer int_p;        // integral image for the integral score path
   Buffer partials;     // per channel group partial sums of the on-chip score
   Buffer keys;         // u64 [n_pairs] best keys of a batched call
+  Buffer pca;          // projection tables: basis, mean, channel scales
   // fused multi-template assignment of a batch (per map group)
   Buffer m_labels;     // uint8 [n_templates][n_pix]
   Buffer m_count;      // u32 [n_templates] worklist counters
@@ -809,7 +810,7 @@ void vqnnf_ctx_destroy(vqnnf_ctx* c) {
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     Buffer* bs[] = {&c->control, &c->labels, &c->wl_pix, &c->wl_mask, &c->int_side, &c->int_p,
-                    &c->partials, &c->keys, &c->m_labels, &c->m_count, &c->m_wl_pix, &c->m_wl_mask};
+                    &c->partials, &c->keys, &c->pca, &c->m_labels, &c->m_count, &c->m_wl_pix, &c->m_wl_mask};
     for (Buffer* b : bs)
       if (b->p) hipFree(b->p);
     for (auto& mp : c->mplans)
@@ -1045,6 +1046,59 @@ vqnnf_status vqnnf_codebook_batched(vqnnf_ctx* ctx, int32_t n, const vqnnf_fmap*
       return s;
     }
   for (int i = 0; i < n; ++i) out[i] = tps[i];
+  return ok();
+}
+
+vqnnf_status vqnnf_pca_fit(const vqnnf_fmap* tmpl, int32_t d, float* mean, float* basis, float* variances) {
+  vqnnf_status s;
+  if (!tmpl || !mean || !basis) return fail(VQNNF_EINVAL, "null template or output pointer");
+  std::vector<float> rgb_buf;
+  vqnnf_fmap rgb_f{};
+  if (tmpl->dtype == VQNNF_RGB8) {
+    if ((s = rgb_template_features(tmpl, rgb_buf, rgb_f))) return s;
+    tmpl = &rgb_f;
+  } else if ((s = check_template_map(tmpl))) {
+    return s;
+  }
+  if (d < 1 || d > std::min(tmpl->D, 64))
+    return fail(VQNNF_EINVAL, "d=%d outside [1, min(D, 64)] (D = %d)", d, tmpl->D);
+  std::vector<double> m, b, v;
+  pca_fit_host((const float*)tmpl->data, (int64_t)tmpl->H * tmpl->W, map_stride(tmpl), tmpl->D, d, m, b, v);
+  for (int t = 0; t < tmpl->D; ++t) mean[t] = (float)m[t];
+  for (size_t i = 0; i < b.size(); ++i) basis[i] = (float)b[i];
+  if (variances)
+    for (int i = 0; i < d; ++i) variances[i] = (float)v[i];
+  return ok();
+}
+
+vqnnf_status vqnnf_pca_project(vqnnf_ctx* c, const vqnnf_fmap* map, const float* mean, const float* basis,
+                               int32_t d, float* out) {
+  vqnnf_status s;
+  if ((s = check_ctx(c))) return s;
+  if ((s = check_map(map, "map"))) return s;
+  if (!mean || !basis || !out) return fail(VQNNF_EINVAL, "null mean, basis or output");
+  const int D = map->D;
+  if (d < 1 || d > std::min(D, 64)) return fail(VQNNF_EINVAL, "d=%d outside [1, min(D, 64)] (D = %d)", d, D);
+  if (pca_project_lds(D, d) > 160 * 1024)
+    return fail(VQNNF_ENOTSUP, "projection tables of %d x %d do not fit on chip", d, D);
+  for (int i = 0; i < d * D; ++i)
+    if (!std::isfinite(basis[i])) return fail(VQNNF_EINVAL, "basis: non-finite value");
+  for (int i = 0; i < D; ++i)
+    if (!std::isfinite(mean[i])) return fail(VQNNF_EINVAL, "mean: non-finite value");
+  const size_t tb = ((size_t)d * D + 2 * (size_t)D) * sizeof(float);
+  if ((s = check_cap(c, {{&c->pca, tb}}))) return s;
+  if ((s = need_device(c))) return s;
+  if ((s = ensure(c, c->pca, tb, "projection tables"))) return s;
+  float* db = (float*)c->pca.p;
+  float* dm = db + (size_t)d * D;
+  float* ds = dm + D;
+  HIP_TRY(hipMemcpyAsync(db, basis, (size_t)d * D * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(dm, mean, (size_t)D * 4, hipMemcpyHostToDevice, c->stream));
+  if (map->dtype == VQNNF_FP8_E4M3)
+    HIP_TRY(hipMemcpyAsync(ds, map->channel_scale, (size_t)D * 4, hipMemcpyHostToDevice, c->stream));
+  HookScope hs(c);
+  HIP_TRY(launch_pca_project(map->data, map->dtype, map_stride(map), map->H, map->W, D,
+                             map->dtype == VQNNF_FP8_E4M3 ? ds : nullptr, dm, db, d, out, c->stream));
   return ok();
 }
 

@@ -122,6 +122,10 @@ std::vector<int> assign_host(const std::vector<double>& x, int64_t n, int D,
 // Template NNF and R(tau) on the host; `labels` (h*w, optional) is the NNF
 // already computed on the device.
 void rgb_patch_features_host(const uint8_t* img, int H, int W, int64_t stride, float* out);
+// PCA of n points (row stride `stride` floats): mean, the d principal axes
+// (rows, largest-magnitude component positive) and their variances, FP64.
+void pca_fit_host(const float* x, int64_t n, int64_t stride, int D, int d, std::vector<double>& mean,
+                  std::vector<double>& basis, std::vector<double>& var);
 void prepare_template_host(DeviceTemplate& t, const float* tmpl, int64_t tmpl_stride,
                            const uint8_t* labels = nullptr);
 
@@ -197,6 +201,10 @@ hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu);
 // direct FP32 distances with a relative error bound; `refined` appends
 // near ties to the re-score worklist.
 bool lowd_supported(int dtype, int D);
+// Projection onto d <= 64 principal axes (mean, basis on the device).
+size_t pca_project_lds(int D, int d);
+hipError_t launch_pca_project(const void* q, int dtype, int64_t stride, int H, int W, int D, const float* scale,
+                              const float* mean, const float* basis, int d, float* out, hipStream_t s);
 hipError_t launch_assign_lowd(const AssignArgs& a, bool refined, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
@@ -258,7 +266,7 @@ hipError_t launch_kmeans(const KmJob* d_jobs, const std::vector<KmJob>& jobs, in
 enum KernelId {
   K_FILL = 0, K_ASSIGN_PLAIN, K_ASSIGN_REFINED, K_RESCORE, K_INT_EDGE, K_INT_PREFIX,
   K_INT_MAIN, K_SCORE_FUSED, K_SCORE_COMBINE, K_SCORE_INTEGRAL, K_ASSIGN_MULTI, K_SCORE_BANK,
-  K_KMEANS, K_ASSIGN_LOWD, K_COUNT
+  K_KMEANS, K_ASSIGN_LOWD, K_PCA_PROJECT, K_COUNT
 };
 const char* kernel_name(int id);
 

@@ -19,10 +19,10 @@ namespace vqnnf {
 namespace {
 
 template <typename F>
-void parallel_for(int64_t n, F&& f) {
+void parallel_for(int64_t n, F&& f, int64_t min_n = 4096) {
   unsigned hw = std::thread::hardware_concurrency();
   int nt = (int)std::max(1u, std::min(hw ? hw : 1u, 32u));
-  if (n < 4096 || nt == 1) {
+  if (n < min_n || nt == 1) {
     f((int64_t)0, n);
     return;
   }
@@ -337,6 +337,162 @@ void pack_frag_f32(const DeviceTemplate& t, const std::vector<float>& x, std::ve
 }
 
 }  // namespace
+
+// Eigen-decomposition of a small symmetric matrix a [m][m] (row-major, FP64)
+// by cyclic Jacobi rotations: on return the eigenvalues are on a's diagonal
+// and v [m][m] holds the eigenvectors as columns.
+static void jacobi_eigen(std::vector<double>& a, std::vector<double>& v, int m) {
+  v.assign((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) v[(size_t)i * m + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < m; ++i) {
+      diag += a[(size_t)i * m + i] * a[(size_t)i * m + i];
+      for (int j = i + 1; j < m; ++j) off += a[(size_t)i * m + j] * a[(size_t)i * m + j];
+    }
+    if (off <= 1e-30 * diag || off == 0.0) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = a[(size_t)p * m + q];
+        if (apq == 0.0) continue;
+        const double app = a[(size_t)p * m + p], aqq = a[(size_t)q * m + q];
+        // rotation angle that zeroes a[p][q]: t = tan(theta), the smaller root
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < m; ++k) {           // columns p, q of a
+          const double akp = a[(size_t)k * m + p], akq = a[(size_t)k * m + q];
+          a[(size_t)k * m + p] = c * akp - sn * akq;
+          a[(size_t)k * m + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < m; ++k) {           // rows p, q of a
+          const double apk = a[(size_t)p * m + k], aqk = a[(size_t)q * m + k];
+          a[(size_t)p * m + k] = c * apk - sn * aqk;
+          a[(size_t)q * m + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < m; ++k) {           // eigenvector columns
+          const double vkp = v[(size_t)k * m + p], vkq = v[(size_t)k * m + q];
+          v[(size_t)k * m + p] = c * vkp - sn * vkq;
+          v[(size_t)k * m + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+}
+
+// Orthonormalises the m columns of q [D][m] (modified Gram-Schmidt, twice).
+static void orthonormalise(std::vector<double>& q, int D, int m) {
+  for (int pass = 0; pass < 2; ++pass)
+    for (int j = 0; j < m; ++j) {
+      for (int i = 0; i < j; ++i) {
+        double dot = 0.0;
+        for (int r = 0; r < D; ++r) dot += q[(size_t)r * m + i] * q[(size_t)r * m + j];
+        for (int r = 0; r < D; ++r) q[(size_t)r * m + j] -= dot * q[(size_t)r * m + i];
+      }
+      double nrm = 0.0;
+      for (int r = 0; r < D; ++r) nrm += q[(size_t)r * m + j] * q[(size_t)r * m + j];
+      nrm = std::sqrt(nrm);
+      for (int r = 0; r < D; ++r) q[(size_t)r * m + j] = nrm > 0 ? q[(size_t)r * m + j] / nrm : 0.0;
+    }
+}
+
+void pca_fit_host(const float* x, int64_t n, int64_t stride, int D, int d, std::vector<double>& mean,
+                  std::vector<double>& basis, std::vector<double>& var) {
+  mean.assign(D, 0.0);
+  for (int64_t p = 0; p < n; ++p)
+    for (int t = 0; t < D; ++t) mean[t] = mean[t] + (double)x[p * stride + t];
+  for (int t = 0; t < D; ++t) mean[t] = mean[t] / (double)n;
+  std::vector<double> xc((size_t)n * D);
+  for (int64_t p = 0; p < n; ++p)
+    for (int t = 0; t < D; ++t) xc[(size_t)p * D + t] = (double)x[p * stride + t] - mean[t];
+  // covariance, normalised by n; rows in parallel
+  std::vector<double> cov((size_t)D * D, 0.0);
+  parallel_for(D, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) {
+      double* ci = &cov[(size_t)i * D];
+      for (int64_t p = 0; p < n; ++p) {
+        const double xi = xc[(size_t)p * D + i];
+        const double* xp = &xc[(size_t)p * D];
+        for (int j = 0; j < D; ++j) ci[j] += xi * xp[j];
+      }
+      for (int j = 0; j < D; ++j) ci[j] /= (double)n;
+    }
+  }, 8);
+  // subspace iteration with Rayleigh-Ritz on m >= d columns
+  const int m = std::min(D, d + 8);
+  std::vector<double> q((size_t)D * m), z((size_t)D * m), t((size_t)m * m), v, theta(m);
+  uint64_t st = 0x243F6A8885A308D3ull;   // fixed start
+  for (auto& e : q) {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t r = st;
+    r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
+    r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
+    e = (double)((r ^ (r >> 31)) >> 11) * 0x1.0p-53 - 0.5;
+  }
+  orthonormalise(q, D, m);
+  auto mul_cov = [&](const std::vector<double>& in, std::vector<double>& out) {
+    parallel_for(D, [&](int64_t b, int64_t e) {
+      for (int64_t r = b; r < e; ++r)
+        for (int j = 0; j < m; ++j) {
+          double s2 = 0.0;
+          for (int k = 0; k < D; ++k) s2 += cov[(size_t)r * D + k] * in[(size_t)k * m + j];
+          out[(size_t)r * m + j] = s2;
+        }
+    }, 8);
+  };
+  for (int it = 0; it < 2000; ++it) {
+    mul_cov(q, z);
+    orthonormalise(z, D, m);
+    // Rayleigh-Ritz: t = z^T C z, rotate z onto t's eigenvectors
+    mul_cov(z, q);                                   // q <- C z
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        double s2 = 0.0;
+        for (int r = 0; r < D; ++r) s2 += z[(size_t)r * m + i] * q[(size_t)r * m + j];
+        t[(size_t)i * m + j] = s2;
+      }
+    for (int i = 0; i < m; ++i)
+      for (int j = i + 1; j < m; ++j) {
+        const double a2 = 0.5 * (t[(size_t)i * m + j] + t[(size_t)j * m + i]);
+        t[(size_t)i * m + j] = t[(size_t)j * m + i] = a2;
+      }
+    jacobi_eigen(t, v, m);
+    std::vector<int> order(m);
+    for (int i = 0; i < m; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a2, int b2) { return t[(size_t)a2 * m + a2] > t[(size_t)b2 * m + b2]; });
+    for (int r = 0; r < D; ++r)
+      for (int j = 0; j < m; ++j) {
+        double s2 = 0.0;
+        for (int i = 0; i < m; ++i) s2 += z[(size_t)r * m + i] * v[(size_t)i * m + order[j]];
+        q[(size_t)r * m + j] = s2;
+      }
+    for (int j = 0; j < m; ++j) theta[j] = t[(size_t)order[j] * m + order[j]];
+    // converged when every wanted Ritz pair has a small residual
+    if (it % 4 == 3 || it == 1999) {
+      mul_cov(q, z);
+      double worst = 0.0;
+      for (int j = 0; j < d; ++j) {
+        double r2 = 0.0;
+        for (int r = 0; r < D; ++r) {
+          const double e = z[(size_t)r * m + j] - theta[j] * q[(size_t)r * m + j];
+          r2 += e * e;
+        }
+        worst = std::max(worst, std::sqrt(r2));
+      }
+      if (worst <= 1e-12 * std::max(theta[0], 1e-300)) break;
+    }
+  }
+  basis.assign((size_t)d * D, 0.0);
+  var.assign(d, 0.0);
+  for (int j = 0; j < d; ++j) {
+    int arg = 0;
+    for (int r = 1; r < D; ++r)
+      if (std::fabs(q[(size_t)r * m + j]) > std::fabs(q[(size_t)arg * m + j])) arg = r;
+    const double sg = q[(size_t)arg * m + j] < 0 ? -1.0 : 1.0;
+    for (int r = 0; r < D; ++r) basis[(size_t)j * D + r] = sg * q[(size_t)r * m + j];
+    var[j] = theta[j];
+  }
+}
 
 // Colour features of an RGB image: feature (3*dy + dx)*3 + c of pixel (x, y)
 // is channel c of the pixel at (x + dx - 1, y + dy - 1), edges replicated.
