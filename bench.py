@@ -188,6 +188,86 @@ def paper_bank_leg(ctx, B, t, fm, qm, steps, torch):
     return out
 
 
+def _timed(fn, steps, torch):
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def _kernel_avgs(ctx, fn, steps):
+    ctx.reset_times()
+    ctx.set_timing(True)
+    for _ in range(steps):
+        fn()
+    kt = ctx.kernel_times()
+    ctx.set_timing(False)
+    return {k: round(v[1] / max(1, v[0]), 4) for k, v in kt.items()}
+
+
+def low_d_leg(ctx, B, t, qd, qm, steps, torch):
+    """The same map and template reduced to d = 18 and 9 principal axes of the
+    template (Sec. 5.5): the timed step is the query projection plus the
+    whole matching path at D = d; the template's PCA and k-means are
+    preparation."""
+    h, w, D = t.data.shape
+    out = {}
+    for d in (18, 9):
+        mean, basis, _ = B.vqnnf_pca_fit(t.data, d)
+        tp = torch.empty((h, w, d), dtype=torch.float32, device="cuda")
+        B.vqnnf_pca_project(ctx, B.device_fmap(torch.from_numpy(np.ascontiguousarray(t.data)).cuda(), "f32"),
+                            mean, basis, tp)
+        tpl = B.vqnnf_codebook(ctx, tp.cpu().numpy(), t.k, 20, 0, B.default_bank(w, h, t.grid))
+        qp = torch.empty((qm.H, qm.W, d), dtype=torch.float32, device="cuda")
+        heat = torch.empty((qm.H - h + 1) * (qm.W - w + 1), device="cuda")
+        fm_in = B.device_fmap(qd, qm.dtype)
+        fm = B.device_fmap(qp, "f32")
+
+        def step():
+            B.vqnnf_pca_project(ctx, fm_in, mean, basis, qp)
+            B.vqnnf_match(ctx, tpl, fm, B.VQNNF_PREC_BF16_REFINED, heat, want_best=False)
+
+        ms = _timed(step, steps, torch)
+        best, _ = B.vqnnf_match(ctx, tpl, fm, B.VQNNF_PREC_BF16_REFINED, heat)
+        out[f"d{d}"] = {"value": qm.H * qm.W / (ms / 1e3), "unit": "px/s", "ms_per_step": ms,
+                        "kernels_avg_ms": _kernel_avgs(ctx, step, steps),
+                        "best": {"x": best[0], "y": best[1], "planted": [t.x0, t.y0]}}
+    out["workload"] = "same map and template, PCA of the template to d = 18 / 9, projection timed"
+    return out
+
+
+def colour_leg(ctx, B, synth, steps, torch):
+    """Colour features (Sec. 5.2): a 1280x720 RGB image (the long-video frame
+    size), a 100x100 crop as template, k = 128; features are 3x3 RGB patches
+    built inside the assignment; the full-window + 3x3 grid bank and the
+    paper's best colour bank (F_2,3-rect at S = 4, 20 filters)."""
+    H, W, side, k = 720, 1280, 100, 128
+    img = synth.rgb_image(H, W, seed=230615014)
+    rng = np.random.default_rng(230615014)
+    x0, y0 = int(rng.integers(0, W - side + 1)), int(rng.integers(0, H - side + 1))
+    crop = np.ascontiguousarray(img[y0:y0 + side, x0:x0 + side])
+    fm = B.device_fmap(torch.from_numpy(img).cuda(), "rgb8")
+    heat = torch.empty((H - side + 1) * (W - side + 1), device="cuda")
+    out = {"workload": f"{W}x{H} RGB, colour features D=27, {side}x{side} template, k={k}"}
+    for name, bank in (("full_3x3", B.default_bank(side, side, 3)),
+                       ("paper_23rect_S4", B.paper_bank(side, side, "23rect", 4))):
+        tpl = B.vqnnf_codebook(ctx, crop, k, 20, 0, bank)
+
+        def step():
+            B.vqnnf_match(ctx, tpl, fm, B.VQNNF_PREC_BF16_REFINED, heat, want_best=False)
+
+        ms = _timed(step, steps, torch)
+        best, _ = B.vqnnf_match(ctx, tpl, fm, B.VQNNF_PREC_BF16_REFINED, heat)
+        out[name] = {"value": H * W / (ms / 1e3), "unit": "px/s", "ms_per_step": ms,
+                     "kernels_avg_ms": _kernel_avgs(ctx, step, steps),
+                     "best": {"x": best[0], "y": best[1], "planted": [x0, y0]}}
+    return out
+
+
 def batched_bench(args, ctx, B, synth, torch):
     """Batched workloads: every (template, map) pair in one vqnnf_match_batched
     call, replayed as one captured HIP graph, against the same pairs as
@@ -430,6 +510,9 @@ def main():
         sec = secondary("c2", ctx, B, synth, max(5, args.steps))
         log("timing the paper's filter bank on the same map")
         sec = {"c2": sec, "paper_bank": paper_bank_leg(ctx, B, t, fm, qm, max(5, args.steps // 2), torch)}
+        log("timing the low-dimensional (PCA) and colour-feature workloads")
+        sec["low_d"] = low_d_leg(ctx, B, t, qd, qm, max(5, args.steps // 2), torch)
+        sec["colour"] = colour_leg(ctx, B, synth, max(5, args.steps // 2), torch)
 
     cpu = None
     if not args.no_cpu_baseline:

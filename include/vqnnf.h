@@ -186,10 +186,13 @@ vqnnf_status vqnnf_codebook_batched(vqnnf_ctx* ctx, int32_t n, const vqnnf_fmap*
 vqnnf_status vqnnf_pca_fit(const vqnnf_fmap* tmpl, int32_t d, float* mean, float* basis, float* variances);
 
 /* Projects a DEVICE map onto d axes: out[(y*W + x)*d + i] =
- * sum_t (q_t - mean_t) * basis[i][t] for every pixel, in FP32 (the
- * subtraction rounded, products accumulated by FMA in increasing t), where
- * q_t is the map's element value (FP8: code x scale rounded to FP32; RGB8:
- * colour feature t).  mean/basis: HOST, as from vqnnf_pca_fit; out: DEVICE
+ * sum_t (q_t - mean_t) * basis[i][t] for every pixel, where q_t is the map's
+ * element value (FP8: code x scale rounded to FP32; RGB8: colour feature t).
+ * Arithmetic: FP32, the subtraction rounded and the products accumulated by
+ * FMA in increasing t; BF16 maps with D a multiple of 32 and 16-byte aligned
+ * rows use the matrix cores instead: exact products of the elements with an
+ * exact three-term BF16 split of the basis, FP32 accumulation, then minus
+ * mean . basis (computed in FP64, rounded once).  mean/basis: HOST, as from vqnnf_pca_fit; out: DEVICE
  * float[H*W*d].  The result is an F32 map of D = d for vqnnf_codebook (after
  * copying a projected template back) and every matching call.  Asynchronous
  * on the context stream. */

@@ -136,13 +136,16 @@ def device_fmap(t, dtype: str, channel_scale: Optional[np.ndarray] = None) -> FM
     H, W, S = t.shape[0], t.shape[1], t.shape[2]
     assert t.is_contiguous()
     if dtype == "rgb8":          # uint8 [H][W][S >= 3]: colour features, D = 27
-        return FMap(t.data_ptr(), VQNNF_RGB8, H, W, 27, S, None)
+        fm = FMap(t.data_ptr(), VQNNF_RGB8, H, W, 27, S, None)
+        fm._tensor = t           # the device memory stays allocated while the map exists
+        return fm
     scale = None
     if channel_scale is not None:
         channel_scale = np.ascontiguousarray(channel_scale, dtype=np.float32)
         scale = channel_scale.ctypes.data
     fm = FMap(t.data_ptr(), _DT[dtype], H, W, S, S, scale)
     fm._scale = channel_scale   # the host scales stay alive with the map
+    fm._tensor = t              # and so does the device memory
     return fm
 
 

@@ -3,7 +3,8 @@
 // built on the fly from an RGB image (Sec. 5.2 "Feature Extraction": the 3x3
 // neighbourhood of RGB values, D = 27, edges replicated).
 //
-// One thread per pixel: its features in registers, the codebook in LDS, the
+// One thread per pixel: its features in registers, the codebook read through
+// scalar loads (the same value for every lane: an SGPR operand of the FMA), the
 // direct distances d~_j = sum_t (q_t - c_jt)^2 in FP32 (subtract, then FMA).
 // Their error is relative: |d~_j - d_j| <= e32 * d_j with
 // e32 = (1 + u)^2 (1 + gamma_D) - 1, u = 2^-24, and the FP64 distances of the
@@ -30,7 +31,6 @@ struct LowParams {
   int64_t stride;          // elements (bytes for RGB) between pixels
   int64_t n_pix;
   int W, H, D, k, mask_words, refined;
-  const float* codebook;   // [k][D]
   uint8_t* labels;
   uint32_t* wl_count;
   uint32_t* wl_pix;
@@ -69,7 +69,7 @@ __device__ __forceinline__ void load_features(const LowParams& p, int64_t px, fl
   }
 }
 
-__device__ __forceinline__ float dist(const float (&qv)[kLowMaxD], const float* c, int D) {
+__device__ __forceinline__ float dist(const float (&qv)[kLowMaxD], const float* __restrict__ c, int D) {
   float d = 0.f;
 #pragma unroll
   for (int t = 0; t < kLowMaxD; ++t) {
@@ -82,10 +82,7 @@ __device__ __forceinline__ float dist(const float (&qv)[kLowMaxD], const float* 
 }
 
 template <int QT>
-__global__ __launch_bounds__(256) void assign_lowd_kernel(LowParams p) {
-  __shared__ float cb[kMaxK * kLowMaxD];
-  for (int i = threadIdx.x; i < p.k * p.D; i += 256) cb[i] = p.codebook[i];
-  __syncthreads();
+__global__ __launch_bounds__(256) void assign_lowd_kernel(LowParams p, const float* __restrict__ cb) {
   const int64_t px = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool valid = px < p.n_pix;
   float qv[kLowMaxD];
@@ -145,7 +142,6 @@ hipError_t launch_assign_lowd(const AssignArgs& a, bool refined, hipStream_t s) 
   p.k = t.k;
   p.mask_words = (t.geom.kpad + 31) / 32;
   p.refined = refined ? 1 : 0;
-  p.codebook = t.d_codebook;
   p.labels = a.labels;
   p.wl_count = a.wl_count;
   p.wl_pix = a.wl_pix;
@@ -159,9 +155,10 @@ hipError_t launch_assign_lowd(const AssignArgs& a, bool refined, hipStream_t s) 
   p.floor = (float)(4.0 * (D + 2) * 0x1.0p-126);
   const dim3 grid((unsigned)((a.n_pix + 255) / 256));
   timing_begin(K_ASSIGN_LOWD);
-  if (a.dtype == VQNNF_RGB8) hipLaunchKernelGGL(assign_lowd_kernel<kQRGB8>, grid, dim3(256), 0, s, p);
-  else if (a.dtype == VQNNF_F32) hipLaunchKernelGGL(assign_lowd_kernel<kQF32>, grid, dim3(256), 0, s, p);
-  else hipLaunchKernelGGL(assign_lowd_kernel<kQBF16>, grid, dim3(256), 0, s, p);
+  const float* cb = t.d_codebook;
+  if (a.dtype == VQNNF_RGB8) hipLaunchKernelGGL(assign_lowd_kernel<kQRGB8>, grid, dim3(256), 0, s, p, cb);
+  else if (a.dtype == VQNNF_F32) hipLaunchKernelGGL(assign_lowd_kernel<kQF32>, grid, dim3(256), 0, s, p, cb);
+  else hipLaunchKernelGGL(assign_lowd_kernel<kQBF16>, grid, dim3(256), 0, s, p, cb);
   timing_end(K_ASSIGN_LOWD);
   return hipGetLastError();
 }

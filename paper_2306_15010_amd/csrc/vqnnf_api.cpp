@@ -227,6 +227,20 @@ size_t dtype_size(int dt) {
   return 0;
 }
 
+// BF16 rounding (nearest, ties to even) of a finite FP32 value, and its bits.
+uint16_t bf16_bits(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_round(float x) {
+  const uint32_t u = (uint32_t)bf16_bits(x) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 // Elements between pixels (bytes for an RGB image, whose pixel is 3 bytes).
 int64_t map_stride(const vqnnf_fmap* m) {
   if (m->pixel_stride) return m->pixel_stride;
@@ -1079,20 +1093,61 @@ vqnnf_status vqnnf_pca_project(vqnnf_ctx* c, const vqnnf_fmap* map, const float*
   if (!mean || !basis || !out) return fail(VQNNF_EINVAL, "null mean, basis or output");
   const int D = map->D;
   if (d < 1 || d > std::min(D, 64)) return fail(VQNNF_EINVAL, "d=%d outside [1, min(D, 64)] (D = %d)", d, D);
-  if (pca_project_lds(D, d) > 160 * 1024)
-    return fail(VQNNF_ENOTSUP, "projection tables of %d x %d do not fit on chip", d, D);
   for (int i = 0; i < d * D; ++i)
     if (!std::isfinite(basis[i])) return fail(VQNNF_EINVAL, "basis: non-finite value");
   for (int i = 0; i < D; ++i)
     if (!std::isfinite(mean[i])) return fail(VQNNF_EINVAL, "mean: non-finite value");
-  const size_t tb = ((size_t)d * D + 2 * (size_t)D) * sizeof(float);
+  // BF16 maps with aligned rows of whole 32-element groups: matrix cores, the
+  // basis split into three BF16 terms (exact for every finite FP32 value it
+  // is checked for), the centring applied as mean . basis
+  const int64_t st = map_stride(map);
+  bool mfma = map->dtype == VQNNF_BF16 && D % 32 == 0 && (uintptr_t)map->data % 16 == 0 && (st * 2) % 16 == 0 &&
+              pca_mfma_lds(D, d) <= 160 * 1024;
+  const int rbn = (d + 15) / 16, steps = D / 32;
+  std::vector<uint16_t> frag;
+  std::vector<float> mb;
+  if (mfma) {
+    frag.assign((size_t)steps * 3 * rbn * 64 * 8, 0);
+    for (int i = 0; i < d && mfma; ++i)
+      for (int t = 0; t < D; ++t) {
+        const float b = basis[(size_t)i * D + t];
+        const float h = bf16_round(b), r1 = b - h, l = bf16_round(r1), r2 = r1 - l, l2 = bf16_round(r2);
+        if ((double)h + (double)l + (double)l2 != (double)b) { mfma = false; break; }
+        const float terms[3] = {h, l, l2};
+        const int s2 = t / 32, lg = (t % 32) / 8, e = t % 8, rb = i / 16, lane = (i % 16) + 16 * lg;
+        for (int term = 0; term < 3; ++term)
+          frag[((((size_t)s2 * 3 + term) * rbn + rb) * 64 + lane) * 8 + e] = bf16_bits(terms[term]);
+      }
+    mb.resize(d);
+    for (int i = 0; i < d; ++i) {
+      double acc = 0.0;
+      for (int t = 0; t < D; ++t) acc += (double)mean[t] * (double)basis[(size_t)i * D + t];
+      mb[i] = (float)acc;
+    }
+  }
+  const size_t tb = mfma ? frag.size() * 2 + (size_t)d * 4 + 256 : ((size_t)d * D + 2 * (size_t)D) * sizeof(float);
   if ((s = check_cap(c, {{&c->pca, tb}}))) return s;
   if ((s = need_device(c))) return s;
   if ((s = ensure(c, c->pca, tb, "projection tables"))) return s;
+  if (mfma) {
+    uint4* dfrag = (uint4*)c->pca.p;
+    float* dmb = (float*)((char*)c->pca.p + frag.size() * 2);
+    HIP_TRY(hipMemcpyAsync(dfrag, frag.data(), frag.size() * 2, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(dmb, mb.data(), (size_t)d * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));   // host tables are released on return
+    HookScope hs(c);
+    HIP_TRY(launch_pca_mfma((const uint16_t*)map->data, st, map->H, map->W, D, dfrag, dmb, d, out, c->n_cu,
+                            c->stream));
+    return ok();
+  }
   float* db = (float*)c->pca.p;
   float* dm = db + (size_t)d * D;
   float* ds = dm + D;
-  HIP_TRY(hipMemcpyAsync(db, basis, (size_t)d * D * 4, hipMemcpyHostToDevice, c->stream));
+  std::vector<float> bt((size_t)d * D);      // t-major: the d values of element t together
+  for (int i = 0; i < d; ++i)
+    for (int t = 0; t < D; ++t) bt[(size_t)t * d + i] = basis[(size_t)i * D + t];
+  HIP_TRY(hipMemcpyAsync(db, bt.data(), (size_t)d * D * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));   // the host copy of the table is released on return
   HIP_TRY(hipMemcpyAsync(dm, mean, (size_t)D * 4, hipMemcpyHostToDevice, c->stream));
   if (map->dtype == VQNNF_FP8_E4M3)
     HIP_TRY(hipMemcpyAsync(ds, map->channel_scale, (size_t)D * 4, hipMemcpyHostToDevice, c->stream));

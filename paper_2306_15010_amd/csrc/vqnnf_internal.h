@@ -201,10 +201,16 @@ hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu);
 // direct FP32 distances with a relative error bound; `refined` appends
 // near ties to the re-score worklist.
 bool lowd_supported(int dtype, int D);
-// Projection onto d <= 64 principal axes (mean, basis on the device).
-size_t pca_project_lds(int D, int d);
+// Projection onto d <= 64 principal axes (device tables: basis t-major
+// [D][d], mean [D], FP8 channel scales [D]).
 hipError_t launch_pca_project(const void* q, int dtype, int64_t stride, int H, int W, int D, const float* scale,
-                              const float* mean, const float* basis, int d, float* out, hipStream_t s);
+                              const float* mean, const float* basis_t, int d, float* out, hipStream_t s);
+// BF16 maps, D a multiple of 32, 16-byte aligned rows: matrix cores with the
+// basis split into three exact BF16 terms (fragments [D/32][3][ceil(d/16)][64]
+// uint4) and the centring mean . basis subtracted at the end.
+size_t pca_mfma_lds(int D, int d);
+hipError_t launch_pca_mfma(const uint16_t* q, int64_t stride, int H, int W, int D, const uint4* frag,
+                           const float* mb, int d, float* out, int n_cu, hipStream_t s);
 hipError_t launch_assign_lowd(const AssignArgs& a, bool refined, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 

@@ -376,13 +376,15 @@ def random_map(H: int, W: int, D: int, dtype: str, seed: int, M: int = 16,
     return encode(mixture_features(z, means, sigma, r_feat), dtype)
 
 
-def rgb_image(H: int, W: int, seed: int, M: int = 12, noise: float = 8.0) -> np.ndarray:
-    """A seeded uint8 RGB image [H, W, 3] of smooth colour regions: the
-    component field of the feature maps, one palette colour per component,
-    plus Gaussian noise, clipped to 0..255 (stand-in for the colour images
-    of the colour-feature workloads)."""
+def rgb_image(H: int, W: int, seed: int, M: int = 12, noise: float = 8.0, cell: int = 8) -> np.ndarray:
+    """A seeded uint8 RGB image [H, W, 3] of colour regions: the component
+    field of the feature maps drawn at 1/cell resolution and enlarged to
+    cell x cell blocks, one palette colour per component, plus Gaussian
+    noise, clipped to 0..255 (stand-in for the colour images of the
+    colour-feature workloads)."""
     r_pal, r_lab, r_noise = _streams(seed, 3)
     palette = r_pal.uniform(20.0, 235.0, size=(M, 3))
-    z = smooth_label_field(H, W, M, r_lab)
+    zc = smooth_label_field(-(-H // cell), -(-W // cell), M, r_lab)
+    z = np.repeat(np.repeat(zc, cell, axis=0), cell, axis=1)[:H, :W]
     img = palette[z] + noise * r_noise.standard_normal(size=(H, W, 3))
     return np.clip(np.rint(img), 0, 255).astype(np.uint8)

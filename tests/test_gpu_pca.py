@@ -1,10 +1,15 @@
 """PCA reduction on the GPU (vqnnf_pca_project) and the low-dimensional
 matching path it feeds (Sec. 5.5).
 
-Projection tolerance, derived: each output is an FMA chain over the D terms
-(q_t - m_t) * b_t with the subtraction rounded (FP8 values also rounded once
-when decoded to FP32), so |gpu - exact| <= (D + 3) u sum_t |q_t - m_t| |b_t|
-(first order, u = 2^-24); the test allows twice that."""
+Projection tolerance, derived (u = 2^-24, first order, the test allows twice
+the bound):
+  * FP32 / FP8 / RGB maps: an FMA chain over the D terms (q_t - m_t) * b_t with
+    the subtraction rounded (FP8 values also rounded once when decoded), so
+    |gpu - exact| <= (D + 3) u sum_t |q_t - m_t| |b_t|;
+  * BF16 maps on the matrix cores: exact products of the BF16 elements with the
+    three exact BF16 terms of each basis value, about 3D FP32 additions, then
+    minus mean . basis (rounded once), so
+    |gpu - exact| <= (3D + 4) u sum_t (|q_t| + |m_t|) |b_t|."""
 import sys
 
 import numpy as np
@@ -64,7 +69,11 @@ def test_projection_parity(ctx, H, W, D, dt, d):
     B.vqnnf_pca_project(ctx, fm, mean, basis, out)
     xc = x.reshape(-1, D) - mean.astype(np.float64)
     ref = xc @ basis.astype(np.float64).T
-    bound = 2 * (D + 3) * U * (np.abs(xc) @ np.abs(basis.astype(np.float64)).T)
+    ab = np.abs(basis.astype(np.float64)).T
+    if dt == "bf16":
+        bound = 2 * (3 * D + 4) * U * ((np.abs(x.reshape(-1, D)) + np.abs(mean.astype(np.float64))) @ ab)
+    else:
+        bound = 2 * (D + 3) * U * (np.abs(xc) @ ab)
     got = out.cpu().numpy().reshape(-1, d).astype(np.float64)
     err = np.abs(got - ref)
     log(f"projection {H}x{W} D={D} {dt} -> {d}: max err {err.max():.3e}, max err/bound {(err / bound).max():.3f}")
