@@ -16,6 +16,8 @@
 //    still candidates.  The FP64 re-score kernel settles those pixels with the
 //    exact sequential FP64 distance, lowest index on ties.
 #include "vqnnf_internal.h"
+
+#include <cstring>
 #include "dev_common.h"
 #include "assign_common.h"
 
@@ -764,15 +766,16 @@ __device__ double seq_dist_rgb(const RParams& p, uint32_t pix, const float* c) {
   return acc;
 }
 
+// Block `blk` of `nblk` walks the worklist of one (template, map) pair.
 template <int QT, bool VEC>
-__global__ __launch_bounds__(64) void rescore_kernel(RParams p) {
+__device__ __forceinline__ void rescore_body(const RParams& p, uint32_t blk, uint32_t nblk) {
   __shared__ uint32_t pfx[kRPix + 1];   // exclusive prefix of candidate counts
   __shared__ double rd[64];
   __shared__ int rj[64];
   const int lane = threadIdx.x;
   const int mw = p.mask_words;
   const uint32_t count = *p.wl_count;
-  for (uint32_t g0 = blockIdx.x * kRPix; g0 < count; g0 += gridDim.x * kRPix) {
+  for (uint32_t g0 = blk * kRPix; g0 < count; g0 += nblk * kRPix) {
     const uint32_t npx = min((uint32_t)kRPix, count - g0);
     uint32_t nc = 0;
     if (lane < (int)npx) {
@@ -821,6 +824,17 @@ __global__ __launch_bounds__(64) void rescore_kernel(RParams p) {
     if (lane < (int)npx && bj >= 0) p.labels[p.wl_pix[g0 + lane]] = (uint8_t)bj;
     __syncthreads();
   }
+}
+
+template <int QT, bool VEC>
+__global__ __launch_bounds__(64) void rescore_kernel(RParams p) {
+  rescore_body<QT, VEC>(p, blockIdx.x, gridDim.x);
+}
+
+// Batched: blockIdx.y selects the pair.
+template <int QT, bool VEC>
+__global__ __launch_bounds__(64) void rescore_batch_kernel(const RParams* __restrict__ tab) {
+  rescore_body<QT, VEC>(tab[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // ============================================================ launchers
@@ -884,6 +898,39 @@ hipError_t go_rescore(const RParams& rp, int grid, bool vec, hipStream_t s) {
   if (vec) hipLaunchKernelGGL((rescore_kernel<QT, true>), dim3(grid), dim3(64), 0, s, rp);
   else hipLaunchKernelGGL((rescore_kernel<QT, false>), dim3(grid), dim3(64), 0, s, rp);
   return hipGetLastError();
+}
+
+template <int QT>
+hipError_t go_rescore_b(const RParams* tab, int grid, int n, bool vec, hipStream_t s) {
+  if (vec) hipLaunchKernelGGL((rescore_batch_kernel<QT, true>), dim3(grid, n), dim3(64), 0, s, tab);
+  else hipLaunchKernelGGL((rescore_batch_kernel<QT, false>), dim3(grid, n), dim3(64), 0, s, tab);
+  return hipGetLastError();
+}
+
+RParams make_rparams(const AssignArgs& a) {
+  const DeviceTemplate& t = *a.t;
+  RParams rp{};
+  rp.q = a.q;
+  rp.stride = a.stride;
+  rp.D = a.D;
+  rp.k = t.k;
+  rp.mask_words = a.mask_words > 0 ? a.mask_words : (t.geom.kpad + 31) / 32;
+  rp.codebook = t.d_codebook;
+  rp.scale = a.scale;
+  rp.wl_count = a.wl_count;
+  rp.wl_pix = a.wl_pix;
+  rp.wl_mask = a.wl_mask;
+  rp.labels = a.labels;
+  rp.img_w = a.img_w;
+  rp.img_h = a.img_h;
+  return rp;
+}
+
+// whole steps of 8 elements: query rows aligned to the step width (16 bytes;
+// 8 for FP8 codes) and codeword rows 16-byte aligned
+bool rescore_vec(const AssignArgs& a) {
+  const int qt = qtype(a.dtype);
+  return a.dtype != VQNNF_RGB8 && rows_aligned(a, qbytes(qt), qt == kQFP8 ? 8 : 16) && (a.D % 4 == 0);
 }
 
 }  // namespace
@@ -970,25 +1017,9 @@ hipError_t launch_assign_plain(const AssignArgs& a, hipStream_t s, int n_cu) {
 }
 
 hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu) {
-  const DeviceTemplate& t = *a.t;
-  RParams rp{};
-  rp.q = a.q;
-  rp.stride = a.stride;
-  rp.D = a.D;
-  rp.k = t.k;
-  rp.mask_words = (t.geom.kpad + 31) / 32;
-  rp.codebook = t.d_codebook;
-  rp.scale = a.scale;
-  rp.wl_count = a.wl_count;
-  rp.wl_pix = a.wl_pix;
-  rp.wl_mask = a.wl_mask;
-  rp.labels = a.labels;
-  rp.img_w = a.img_w;
-  rp.img_h = a.img_h;
+  const RParams rp = make_rparams(a);
   const int qt = qtype(a.dtype);
-  // whole steps of 8 elements: query rows aligned to the step width (16 bytes;
-  // 8 for FP8 codes) and codeword rows 16-byte aligned
-  const bool vec = rows_aligned(a, qbytes(qt), qt == kQFP8 ? 8 : 16) && (a.D % 4 == 0);
+  const bool vec = rescore_vec(a);
   const int grid = n_cu * 4;   // one wave per block; waves stride over the worklist
   timing_begin(K_RESCORE);
   hipError_t e;
@@ -998,5 +1029,38 @@ hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu) {
   else e = go_rescore<kQBF16>(rp, grid, vec, s);
   timing_end(K_RESCORE);
   return e;
+}
+
+void plan_rescore_batch(const std::vector<AssignArgs>& pairs, RescoreBatchPlan* out) {
+  out->blob.clear();
+  out->launches.clear();
+  for (int cls = 0; cls < 8; ++cls) {   // (query type, vector path)
+    std::vector<RParams> tab;
+    for (const AssignArgs& a : pairs) {
+      const int qt = a.dtype == VQNNF_RGB8 ? kQRGB8 : qtype(a.dtype);
+      if (qt * 2 + (rescore_vec(a) ? 1 : 0) == cls) tab.push_back(make_rparams(a));
+    }
+    if (tab.empty()) continue;
+    const size_t off = (out->blob.size() + 63) / 64 * 64;
+    out->blob.resize(off + tab.size() * sizeof(RParams));
+    std::memcpy(out->blob.data() + off, tab.data(), tab.size() * sizeof(RParams));
+    out->launches.push_back({cls / 2, cls % 2, off, (int)tab.size()});
+  }
+}
+
+hipError_t launch_rescore_batch(const RescoreBatchPlan& pl, const uint8_t* d_blob, int n_cu, hipStream_t s) {
+  for (const RescoreBatchPlan::Launch& l : pl.launches) {
+    const RParams* tab = (const RParams*)(d_blob + l.tab_off);
+    const int grid = n_cu;   // per pair; waves stride over its worklist
+    timing_begin(K_RESCORE);
+    hipError_t e;
+    if (l.qt == kQRGB8) e = go_rescore_b<kQRGB8>(tab, grid, l.n, false, s);
+    else if (l.qt == kQF32) e = go_rescore_b<kQF32>(tab, grid, l.n, l.vec != 0, s);
+    else if (l.qt == kQFP8) e = go_rescore_b<kQFP8>(tab, grid, l.n, l.vec != 0, s);
+    else e = go_rescore_b<kQBF16>(tab, grid, l.n, l.vec != 0, s);
+    timing_end(K_RESCORE);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 }  // namespace vqnnf

@@ -25,6 +25,10 @@
 // score_integral: any indicator bank, reading the taps from a precomputed
 // integral image (vqnnf_filter's output).
 #include "vqnnf_internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
 #include "dev_common.h"
 
 namespace vqnnf {
@@ -85,7 +89,10 @@ __device__ __forceinline__ void block_max_to(unsigned long long key, unsigned lo
 //      accumulating sum_j min(T_j, C_j) with v_dot2_u32_u16, while the
 //      column threads move Q down to the next row (two labels per band and
 //      column change).
-// The integer sums of the group are written per window; a second kernel adds
+// Bins of equal weight share one sum.  With one channel group the tile
+// kernel forms eq. 2 and the argmax itself; otherwise the integer sums of
+// the group are written per window as 16-bit words (a sum is at most the
+// window area, and template sides are at most 255) and a second kernel adds
 // the groups, forms eq. 2 and the argmax.
 constexpr int kSL = 7;                 // columns per prefix segment (odd: a wave's lanes hit distinct banks)
 constexpr int kNSeg = 53;              // segments per row (<= 64 lanes)
@@ -95,6 +102,8 @@ constexpr int kKG = 16;                // channels per block
 constexpr int kPQ = kKG / 8;           // 16-byte entries (four pairs) per column per band
 constexpr int kTXW = 256;              // windows per tile row
 constexpr int kST = 512;               // threads per block: kTXW windows x kPQ pair groups
+constexpr int kMaxAcc = 17;            // sums per window: full window + up to 4 x 4 bins
+constexpr int kMaxCls = 4;             // merged bin classes (distinct bin weights)
 
 struct TileParams {
   const uint8_t* labels;
@@ -105,8 +114,17 @@ struct TileParams {
   int kpad;
   int xe[5], ye[5];
   const uint32_t* t16;  // [nf][kpad/2] template counts, u16 pairs
-  uint32_t* part;       // [n_groups][nacc][pstride] sums of min(T_j, C_j)
+  uint16_t* part;       // [ng][nacc][pstride] sums of min(T_j, C_j)
   int64_t pstride;      // windows per partial row, oh*ow rounded up to 4
+  int nacc;             // sums per window: 2 (one bin weight), 1 + classes, or 1 + g*g
+  uint32_t cmask[kMaxCls];  // merged classes: bit f of cmask[c - 1] = bin filter f in sum c
+  int nx, ng;           // tiles per heatmap row, channel groups
+  uint32_t b0;          // batched launches: first block of the pair
+  // one channel group: eq. 2 per sum a, the heatmap and the best key
+  float wt[kMaxAcc];
+  int area2[kMaxAcc];   // twice the summed areas of the filters in sum a
+  float* heatmap;
+  unsigned long long* best;
 };
 
 typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
@@ -124,10 +142,33 @@ __device__ __forceinline__ uint32_t min_dot(uint32_t c, uint32_t t, uint32_t acc
   return __builtin_amdgcn_udot2(m, (u16x2_t){1, 1}, acc, false);
 }
 
+// Block-wide maximum of the keys for blocks of NW waves, then one atomicMax.
+template <int NW>
+__device__ __forceinline__ void block_max_n(unsigned long long key, unsigned long long* best) {
+  __shared__ unsigned long long wmax[NW];
+  key = wave_max_u64(key);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long k = wmax[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) k = wmax[i] > k ? wmax[i] : k;
+    if (k > __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(best, k);
+  }
+}
+
+// Pointers read from an argument table are generic; the kernels only touch
+// global memory through them, which lets them use global (not flat) accesses.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // UNI: every bin has the same weight, so the bins share one accumulator
-// (accumulator 0: full window, 1: bins); otherwise one per filter.
+// (accumulator 0: full window, 1: bins); otherwise one per filter while
+// scoring, merged into the stored sums at the end of each row.
 template <int G, bool UNI>
-__global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
+__device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int by, int grp) {
   constexpr int NF = 1 + G * G;
   constexpr int NACC = UNI ? 2 : NF;
   constexpr int NR = G * kPQ;                        // (band, pair group) rows
@@ -135,10 +176,12 @@ __global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
   __shared__ uint4 Qs[NR][kHS];
   __shared__ uint4 Hs[NR][kHS];
   __shared__ uint32_t red[NACC][kTXW];
+  const auto labs = gbl(p.labels);
+  const auto t16 = gbl(p.t16);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int x0 = blockIdx.x * p.txw, y0 = blockIdx.y * p.tyw;
-  const int grp = blockIdx.z, j0 = grp * kKG;
+  const int x0 = bx * p.txw, y0 = by * p.tyw;
+  const int j0 = grp * kKG;
   const int txv = min(p.txw, p.ow - x0), tyv = min(p.tyw, p.oh - y0);
   const int cols = txv + p.w - 1;
   const int nseg = cols / kSL + 1;                   // segments cover [0, cols]
@@ -158,7 +201,7 @@ __global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
     int l8[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r)
-      l8[r] = (r0 + r < p.h) ? (int)p.labels[(int64_t)(y0 + r0 + r) * p.W + x0 + c] - j0 : -1;
+      l8[r] = (r0 + r < p.h) ? (int)labs[(int64_t)(y0 + r0 + r) * p.W + x0 + c] - j0 : -1;
     int b = 0;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -175,23 +218,51 @@ __global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
 #pragma unroll
   for (int f = 0; f < NF; ++f)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) T[f][s] = p.t16[f * (p.kpad / 2) + j0 / 2 + pq * 4 + s];
+    for (int s = 0; s < 4; ++s) T[f][s] = t16[f * (p.kpad / 2) + j0 / 2 + pq * 4 + s];
   // labels leaving / entering each band at the next row step, prefetched
   int lo[G], li[G];
   auto fetch = [&](int ynext, int c) {
 #pragma unroll
     for (int b = 0; b < G; ++b) {
-      lo[b] = (int)p.labels[(int64_t)(ynext - 1 + p.ye[b]) * p.W + x0 + c] - j0;
-      li[b] = (int)p.labels[(int64_t)(ynext - 1 + p.ye[b + 1]) * p.W + x0 + c] - j0;
+      lo[b] = (int)labs[(int64_t)(ynext - 1 + p.ye[b]) * p.W + x0 + c] - j0;
+      li[b] = (int)labs[(int64_t)(ynext - 1 + p.ye[b + 1]) * p.W + x0 + c] - j0;
     }
   };
   if (tyv > 1 && tid < cols) fetch(y0 + 1, tid);
 
   uint32_t acc[NACC];
-  auto store_row = [&](int yy) {  // pair group 0 adds group 1's sums
-    const int64_t win = (int64_t)yy * p.ow + x0 + xl;
+  unsigned long long key = 0ull;
+  // pair group 0 adds group 1's sums, merges bins of equal weight and stores
+  // the sums, or with one channel group forms the score itself
+  const bool merged = !UNI && p.nacc < NF;
+  auto store_row = [&](int yy) {
+    uint32_t v[NACC];
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) p.part[((int64_t)grp * NACC + a) * p.pstride + win] = acc[a] + red[a][xl];
+    for (int a = 0; a < NACC; ++a) v[a] = acc[a] + red[a][xl];
+    const int64_t win = (int64_t)yy * p.ow + x0 + xl;
+    float s = 0.f;
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) {
+      if (a >= p.nacc) break;
+      uint32_t o = v[a];
+      if (!UNI && merged && a >= 1 && a <= kMaxCls) {
+        const uint32_t cm = p.cmask[a >= 1 && a <= kMaxCls ? a - 1 : 0];
+        o = 0u;
+#pragma unroll
+        for (int f = 1; f < NF; ++f) o += ((cm >> f) & 1u) ? v[f] : 0u;
+      }
+      if (p.ng == 1) {
+        s = fmaf(p.wt[a], (float)(p.area2[a] - 2 * (int)o), s);
+      } else {
+        gbl(p.part)[((int64_t)grp * p.nacc + a) * p.pstride + win] = (uint16_t)o;
+      }
+    }
+    if (p.ng == 1) {
+      const float sc = -s;
+      gbl(p.heatmap)[win] = sc;
+      const unsigned long long k2 = best_key(sc, (uint32_t)win);
+      key = k2 > key ? k2 : key;
+    }
   };
   for (int dy = 0; dy < tyv; ++dy) {
     const int y = y0 + dy;
@@ -261,25 +332,47 @@ __global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
   }
   __syncthreads();
   if (pq == 0 && xl < txv) store_row(y0 + tyv - 1);
+  if (p.ng == 1) block_max_n<kST / 64>(key, p.best);
 }
+
+template <int G, bool UNI>
+__global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
+  score_tile_body<G, UNI>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Batched: block -> pair from a table, then (group, tile column, tile row)
+// with the channel group fastest.
+template <int G, bool UNI>
+__global__ __launch_bounds__(kST) void score_tile_batch_kernel(const TileParams* __restrict__ tab,
+                                                               const uint32_t* __restrict__ blk) {
+  const TileParams& p = tab[blk[blockIdx.x]];
+  const int b = (int)(blockIdx.x - p.b0);
+  const int grp = b % p.ng, t = b / p.ng;
+  score_tile_body<G, UNI>(p, t % p.nx, t / p.nx, grp);
+}
+
+typedef unsigned int u32x2_v __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_v __attribute__((ext_vector_type(4)));
+typedef float f32x4_v __attribute__((ext_vector_type(4)));
 
 // Adds the groups' integer sums, forms eq. 2 and the argmax.
 struct CombineParams {
-  const uint32_t* part;
+  const uint16_t* part;
   int64_t nwin, pstride;
-  bool vec_out;       // heatmap 16-byte aligned
+  int vec_out;        // heatmap 16-byte aligned
   int ngroups;
-  float wt[17];       // per accumulator weight
-  int area2[17];      // per accumulator: twice the summed bin areas
+  uint32_t b0;        // batched launches: first block of the pair
+  float wt[kMaxAcc];  // per stored sum
+  int area2[kMaxAcc]; // per stored sum: twice the summed filter areas
   float* heatmap;
   unsigned long long* best;
 };
 
-// Four consecutive windows per thread: 16-byte loads of every partial row
+// Four consecutive windows per thread: 8-byte loads of every partial row
 // (rows are padded to a multiple of four windows).
 template <int NACC>
-__global__ __launch_bounds__(256) void score_combine_kernel(CombineParams p) {
-  const int64_t w0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+__device__ __forceinline__ void combine_body(const CombineParams& p, int64_t blk) {
+  const int64_t w0 = (blk * 256 + threadIdx.x) * 4;
   unsigned long long key = 0ull;
   if (w0 < p.nwin) {
     uint4 m[NACC];
@@ -288,7 +381,11 @@ __global__ __launch_bounds__(256) void score_combine_kernel(CombineParams p) {
     for (int g = 0; g < p.ngroups; ++g) {
       uint4 v[NACC];
 #pragma unroll
-      for (int a = 0; a < NACC; ++a) v[a] = *(const uint4*)(p.part + ((int64_t)g * NACC + a) * p.pstride + w0);
+      for (int a = 0; a < NACC; ++a) {
+        const int64_t o = ((int64_t)g * NACC + a) * p.pstride + w0;
+        const u32x2_v h = *(const __attribute__((address_space(1))) u32x2_v*)gbl(p.part + o);
+        v[a] = make_uint4(h[0] & 0xFFFFu, h[0] >> 16, h[1] & 0xFFFFu, h[1] >> 16);
+      }
 #pragma unroll
       for (int a = 0; a < NACC; ++a)
         m[a] = make_uint4(m[a].x + v[a].x, m[a].y + v[a].y, m[a].z + v[a].z, m[a].w + v[a].w);
@@ -307,9 +404,9 @@ __global__ __launch_bounds__(256) void score_combine_kernel(CombineParams p) {
     }
     const int nv = (int)min((int64_t)4, p.nwin - w0);
     if (nv == 4 && p.vec_out) {
-      *(float4*)(p.heatmap + w0) = make_float4(sc[0], sc[1], sc[2], sc[3]);
+      *(__attribute__((address_space(1))) f32x4_v*)gbl(p.heatmap + w0) = f32x4_v{sc[0], sc[1], sc[2], sc[3]};
     } else {
-      for (int i = 0; i < nv; ++i) p.heatmap[w0 + i] = sc[i];
+      for (int i = 0; i < nv; ++i) gbl(p.heatmap)[w0 + i] = sc[i];
     }
     for (int i = 0; i < nv; ++i) {
       const unsigned long long k2 = best_key(sc[i], (uint32_t)(w0 + i));
@@ -317,6 +414,18 @@ __global__ __launch_bounds__(256) void score_combine_kernel(CombineParams p) {
     }
   }
   block_max_to(key, p.best);
+}
+
+template <int NACC>
+__global__ __launch_bounds__(256) void score_combine_kernel(CombineParams p) {
+  combine_body<NACC>(p, blockIdx.x);
+}
+
+template <int NACC>
+__global__ __launch_bounds__(256) void score_combine_batch_kernel(const CombineParams* __restrict__ tab,
+                                                                  const uint32_t* __restrict__ blk) {
+  const CombineParams& p = tab[blk[blockIdx.x]];
+  combine_body<NACC>(p, (int64_t)(blockIdx.x - p.b0));
 }
 
 // ================================================================ integral
@@ -368,11 +477,16 @@ __global__ __launch_bounds__(256) void score_integral_kernel(IntParams p) {
 // ================================================================ launchers
 namespace {
 
+// Geometry of the on-chip score for one template: tile width, the stored
+// sums (full window, then bins merged by weight) and their weights / areas.
 struct TilePlan {
   bool ok;
-  bool uni;
-  int txw, tyw;
+  bool uni;           // every bin has one weight: two sums
+  int txw;
   int nacc;
+  uint32_t cmask[kMaxCls];
+  float wt[kMaxAcc];
+  int area2[kMaxAcc];
 };
 
 // Tiles are as wide as the LDS rows allow (at most kTXW windows, at least 32).
@@ -380,74 +494,63 @@ TilePlan plan_tile(const DeviceTemplate& t) {
   TilePlan pl{};
   if (!t.grid.valid) return pl;
   const int G = t.grid.g;
-  if (G < 1 || G > 4 || t.geom.kpad % kKG) return pl;
+  const int NF = 1 + G * G;
+  if (G < 1 || G > 4 || t.geom.kpad % kKG || t.n_filters != NF) return pl;
   int maxband = 0;
   for (int b = 0; b < G; ++b) maxband = std::max(maxband, t.grid.ye[b + 1] - t.grid.ye[b]);
   pl.txw = std::min(kTXW, kColsMax + 1 - t.w);
   if (pl.txw < 32) return pl;
   if ((int64_t)maxband * (kColsMax + 1) >= 65536) return pl;   // u16 prefix counts
-  pl.uni = true;
-  for (int f = 2; f < t.n_filters; ++f)
-    if (t.weights[f] != t.weights[1]) pl.uni = false;
-  pl.nacc = pl.uni ? 2 : t.n_filters;
-  pl.tyw = 32;
+  // bins of equal weight share a sum: classes in order of first appearance
+  std::vector<float> wd;
+  int cls[kMaxAcc] = {};
+  for (int f = 1; f < NF; ++f) {
+    const auto it = std::find(wd.begin(), wd.end(), t.weights[f]);
+    cls[f] = (int)(it - wd.begin());
+    if (it == wd.end()) wd.push_back(t.weights[f]);
+  }
+  pl.uni = wd.size() == 1;
+  const bool merged = !pl.uni && (int)wd.size() <= kMaxCls;
+  pl.nacc = pl.uni ? 2 : merged ? 1 + (int)wd.size() : NF;
+  for (int f = 0; f < NF; ++f) {
+    const int32_t* b = &t.boxes[(size_t)f * 4];
+    const int area = (b[2] - b[0]) * (b[3] - b[1]);
+    const int a = f == 0 ? 0 : pl.uni ? 1 : merged ? 1 + cls[f] : f;
+    pl.wt[a] = t.weights[f];
+    pl.area2[a] += 2 * area;
+    if (merged && f > 0) pl.cmask[cls[f]] |= 1u << f;
+  }
+  if ((int64_t)t.w * t.h > 65535) return pl;   // 16-bit partial sums
   pl.ok = true;
   return pl;
 }
 
-template <int G, bool UNI>
-hipError_t go_tile(const TileParams& tp, hipStream_t s) {
-  dim3 grid((tp.ow + tp.txw - 1) / tp.txw, (tp.oh + tp.tyw - 1) / tp.tyw, tp.kpad / kKG);
-  hipLaunchKernelGGL((score_tile_kernel<G, UNI>), grid, dim3(kST), 0, s, tp);
-  return hipGetLastError();
-}
+// Kernel arguments of one pair's tile and combine kernels.
+struct PairTables {
+  TileParams tp;
+  CombineParams cp;
+  int G;
+  bool uni;
+  int ny;
+  int64_t ncblk;   // combine blocks (0: the tile kernel forms the scores)
+};
 
-template <int G>
-hipError_t go_tile_u(const TileParams& tp, bool uni, hipStream_t s) {
-  return uni ? go_tile<G, true>(tp, s) : go_tile<G, false>(tp, s);
-}
-
-hipError_t go_combine(const CombineParams& cp, int nacc, hipStream_t s) {
-  const dim3 grid((unsigned)((cp.nwin + 1023) / 1024)), blk(256);
-  switch (nacc) {
-    case 2: hipLaunchKernelGGL((score_combine_kernel<2>), grid, blk, 0, s, cp); break;
-    case 5: hipLaunchKernelGGL((score_combine_kernel<5>), grid, blk, 0, s, cp); break;
-    case 10: hipLaunchKernelGGL((score_combine_kernel<10>), grid, blk, 0, s, cp); break;
-    case 17: hipLaunchKernelGGL((score_combine_kernel<17>), grid, blk, 0, s, cp); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-}  // namespace
-
-size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W) {
-  TilePlan pl = plan_tile(t);
-  if (!pl.ok) return 0;
-  const int64_t nwin = (int64_t)(H - t.h + 1) * (W - t.w + 1);
-  return (size_t)(t.geom.kpad / kKG) * pl.nacc * ((nwin + 3) / 4 * 4) * 4;
-}
-
-hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out) {
-  const DeviceTemplate& t = *a.t;
-  const int ow = a.W - t.w + 1, oh = a.H - t.h + 1;
-  if (!t.grid.valid || !a.partials) return hipErrorInvalidValue;
-  TilePlan pl = plan_tile(t);
-  if (!pl.ok) return hipErrorInvalidConfiguration;
-  // equal tile widths; tile height from the caller (autotuned) or the default
+void make_pair(const DeviceTemplate& t, const TilePlan& pl, const uint8_t* labels, int H, int W, int tyw,
+               uint16_t* part, float* heatmap, unsigned long long* best, PairTables* o) {
+  const int ow = W - t.w + 1, oh = H - t.h + 1;
+  // equal tile widths
   const int nx = (ow + pl.txw - 1) / pl.txw;
-  pl.txw = (ow + nx - 1) / nx;
-  pl.tyw = a.tyw > 0 ? std::min(a.tyw, oh) : fused_default_tyw(t, a.H, a.W, a.n_cu);
-  TileParams tp{};
-  tp.labels = a.labels;
-  tp.H = a.H;
-  tp.W = a.W;
+  TileParams& tp = o->tp;
+  tp = TileParams{};
+  tp.labels = labels;
+  tp.H = H;
+  tp.W = W;
   tp.w = t.w;
   tp.h = t.h;
   tp.ow = ow;
   tp.oh = oh;
-  tp.txw = pl.txw;
-  tp.tyw = pl.tyw;
+  tp.txw = (ow + nx - 1) / nx;
+  tp.tyw = std::max(1, std::min(tyw, oh));
   tp.kpad = t.geom.kpad;
   const int G = t.grid.g;
   for (int i = 0; i <= G; ++i) {
@@ -455,43 +558,224 @@ hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_byt
     tp.ye[i] = t.grid.ye[i];
   }
   tp.t16 = t.d_counts16;
-  tp.part = (uint32_t*)a.partials;
   tp.pstride = ((int64_t)ow * oh + 3) / 4 * 4;
-  if (lds_bytes_out) {
-    const int NR = G * kPQ;
-    *lds_bytes_out = (size_t)2 * NR * kHS * 16 + (size_t)pl.nacc * kTXW * 4;
+  tp.nacc = pl.nacc;
+  for (int c = 0; c < kMaxCls; ++c) tp.cmask[c] = pl.cmask[c];
+  tp.nx = nx;
+  tp.ng = t.geom.kpad / kKG;
+  for (int a = 0; a < kMaxAcc; ++a) {
+    tp.wt[a] = pl.wt[a];
+    tp.area2[a] = pl.area2[a];
   }
-  timing_begin(K_SCORE_FUSED);
-  hipError_t e;
-  switch (G) {
-    case 1: e = go_tile_u<1>(tp, pl.uni, s); break;
-    case 2: e = go_tile_u<2>(tp, pl.uni, s); break;
-    case 3: e = go_tile_u<3>(tp, pl.uni, s); break;
-    case 4: e = go_tile_u<4>(tp, pl.uni, s); break;
-    default: e = hipErrorInvalidValue;
-  }
-  timing_end(K_SCORE_FUSED);
-  if (e != hipSuccess) return e;
-  CombineParams cp{};
+  tp.heatmap = heatmap;
+  tp.best = best;
+  tp.part = tp.ng > 1 ? part : nullptr;
+  o->G = G;
+  o->uni = pl.uni;
+  o->ny = (oh + tp.tyw - 1) / tp.tyw;
+  CombineParams& cp = o->cp;
+  cp = CombineParams{};
   cp.part = tp.part;
   cp.nwin = (int64_t)ow * oh;
   cp.pstride = tp.pstride;
-  cp.vec_out = ((uintptr_t)a.heatmap % 16) == 0;
-  cp.ngroups = tp.kpad / kKG;
-  // accumulator a covers filters: UNI -> {0}, {1..NF-1}; else {a}
-  for (int f = 0; f < t.n_filters; ++f) {
-    const int32_t* b = &t.boxes[(size_t)f * 4];
-    const int area = (b[2] - b[0]) * (b[3] - b[1]);
-    const int ai = pl.uni ? (f == 0 ? 0 : 1) : f;
-    cp.wt[ai] = t.weights[f];
-    cp.area2[ai] += 2 * area;
+  cp.vec_out = ((uintptr_t)heatmap % 16) == 0;
+  cp.ngroups = tp.ng;
+  for (int a = 0; a < kMaxAcc; ++a) {
+    cp.wt[a] = pl.wt[a];
+    cp.area2[a] = pl.area2[a];
   }
-  cp.heatmap = a.heatmap;
-  cp.best = a.best;
+  cp.heatmap = heatmap;
+  cp.best = best;
+  o->ncblk = tp.ng > 1 ? (cp.nwin + 1023) / 1024 : 0;
+}
+
+size_t partial_bytes(const DeviceTemplate& t, const TilePlan& pl, int H, int W) {
+  const int ng = t.geom.kpad / kKG;
+  if (ng <= 1) return 0;
+  const int64_t nwin = (int64_t)(H - t.h + 1) * (W - t.w + 1);
+  return (size_t)ng * pl.nacc * ((nwin + 3) / 4 * 4) * 2;
+}
+
+template <int G, bool UNI>
+hipError_t go_tile(const TileParams& tp, int ny, hipStream_t s) {
+  const dim3 grid((unsigned)tp.nx, (unsigned)ny, (unsigned)tp.ng);
+  hipLaunchKernelGGL((score_tile_kernel<G, UNI>), grid, dim3(kST), 0, s, tp);
+  return hipGetLastError();
+}
+
+template <int G, bool UNI>
+hipError_t go_tile_b(const TileParams* tab, const uint32_t* blk, uint32_t nblk, hipStream_t s) {
+  hipLaunchKernelGGL((score_tile_batch_kernel<G, UNI>), dim3(nblk), dim3(kST), 0, s, tab, blk);
+  return hipGetLastError();
+}
+
+// One pair (tab == nullptr) or a batch.
+hipError_t go_tile_any(int G, bool uni, const TileParams& tp, int ny, const TileParams* tab,
+                       const uint32_t* blk, uint32_t nblk, hipStream_t s) {
+#define VQ_TILE(g, u) return tab ? go_tile_b<g, u>(tab, blk, nblk, s) : go_tile<g, u>(tp, ny, s)
+  switch (G * 2 + (uni ? 1 : 0)) {
+    case 2: VQ_TILE(1, false);
+    case 3: VQ_TILE(1, true);
+    case 4: VQ_TILE(2, false);
+    case 5: VQ_TILE(2, true);
+    case 6: VQ_TILE(3, false);
+    case 7: VQ_TILE(3, true);
+    case 8: VQ_TILE(4, false);
+    case 9: VQ_TILE(4, true);
+    default: return hipErrorInvalidValue;
+  }
+#undef VQ_TILE
+}
+
+template <int NACC>
+hipError_t go_comb(const CombineParams& cp, int64_t nblk, const CombineParams* tab, const uint32_t* blk,
+                   hipStream_t s) {
+  if (tab)
+    hipLaunchKernelGGL((score_combine_batch_kernel<NACC>), dim3((unsigned)nblk), dim3(256), 0, s, tab, blk);
+  else
+    hipLaunchKernelGGL((score_combine_kernel<NACC>), dim3((unsigned)nblk), dim3(256), 0, s, cp);
+  return hipGetLastError();
+}
+
+hipError_t go_combine_any(int nacc, const CombineParams& cp, int64_t nblk, const CombineParams* tab,
+                          const uint32_t* blk, hipStream_t s) {
+#define VQ_COMB(n) return go_comb<n>(cp, nblk, tab, blk, s)
+  switch (nacc) {
+    case 2: VQ_COMB(2);
+    case 3: VQ_COMB(3);
+    case 4: VQ_COMB(4);
+    case 5: VQ_COMB(5);
+    case 10: VQ_COMB(10);
+    case 17: VQ_COMB(17);
+    default: return hipErrorInvalidValue;
+  }
+#undef VQ_COMB
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W) {
+  TilePlan pl = plan_tile(t);
+  if (!pl.ok) return 0;
+  return partial_bytes(t, pl, H, W);
+}
+
+hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out) {
+  const DeviceTemplate& t = *a.t;
+  TilePlan pl = plan_tile(t);
+  if (!pl.ok) return hipErrorInvalidConfiguration;
+  if (partial_bytes(t, pl, a.H, a.W) > 0 && !a.partials) return hipErrorInvalidValue;
+  // tile height from the caller (autotuned) or the default
+  const int tyw = a.tyw > 0 ? a.tyw : fused_default_tyw(t, a.H, a.W, a.n_cu);
+  PairTables pt;
+  make_pair(t, pl, a.labels, a.H, a.W, tyw, (uint16_t*)a.partials, a.heatmap, a.best, &pt);
+  if (lds_bytes_out) {
+    const int NR = pt.G * kPQ;
+    *lds_bytes_out = (size_t)2 * NR * kHS * 16 + (size_t)(pl.uni ? 2 : t.n_filters) * kTXW * 4;
+  }
+  timing_begin(K_SCORE_FUSED);
+  hipError_t e = go_tile_any(pt.G, pt.uni, pt.tp, pt.ny, nullptr, nullptr, 0, s);
+  timing_end(K_SCORE_FUSED);
+  if (e != hipSuccess || pt.ncblk == 0) return e;
   timing_begin(K_SCORE_COMBINE);
-  e = go_combine(cp, pl.nacc, s);
+  e = go_combine_any(pl.nacc, pt.cp, pt.ncblk, nullptr, nullptr, s);
   timing_end(K_SCORE_COMBINE);
   return e;
+}
+
+bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, ScoreBatchPlan* out) {
+  out->blob.clear();
+  out->launches.clear();
+  out->part_bytes = 0;
+  std::vector<PairTables> pts(items.size());
+  std::vector<TilePlan> pls(items.size());
+  for (size_t i = 0; i < items.size(); ++i) {
+    const ScoreBatchItem& it = items[i];
+    pls[i] = plan_tile(*it.t);
+    if (!pls[i].ok || it.tyw < 1) return false;
+    const size_t pb = partial_bytes(*it.t, pls[i], it.H, it.W);
+    uint16_t* pp = part ? (uint16_t*)((char*)part + out->part_bytes) : nullptr;
+    make_pair(*it.t, pls[i], it.labels, it.H, it.W, it.tyw, pp, it.heatmap, it.best, &pts[i]);
+    out->part_bytes += align_up(pb, 256);
+  }
+  // tile launches per (G, uniform bins); pairs with the largest templates
+  // (the costliest tile set-up) first
+  std::vector<size_t> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    return (int64_t)items[a].t->w * items[a].t->h > (int64_t)items[b].t->w * items[b].t->h;
+  });
+  auto put = [&](const void* src, size_t bytes) {
+    const size_t off = align_up(out->blob.size(), 64);
+    out->blob.resize(off + bytes);
+    std::memcpy(out->blob.data() + off, src, bytes);
+    return off;
+  };
+  for (int G = 1; G <= 4; ++G)
+    for (int u = 0; u < 2; ++u) {
+      std::vector<TileParams> tab;
+      std::vector<uint32_t> blk;
+      for (size_t i : order) {
+        PairTables& pt = pts[i];
+        if (pt.G != G || pt.uni != (u == 1)) continue;
+        pt.tp.b0 = (uint32_t)blk.size();
+        const int64_t nb = (int64_t)pt.tp.nx * pt.ny * pt.tp.ng;
+        if ((int64_t)blk.size() + nb > 0x7FFFFFFF) return false;
+        blk.insert(blk.end(), (size_t)nb, (uint32_t)tab.size());
+        tab.push_back(pt.tp);
+      }
+      if (tab.empty()) continue;
+      ScoreBatchLaunch l{};
+      l.kind = 0;
+      l.G = G;
+      l.uni = u;
+      l.tab_off = put(tab.data(), tab.size() * sizeof(TileParams));
+      l.blk_off = put(blk.data(), blk.size() * 4);
+      l.nblk = (uint32_t)blk.size();
+      out->launches.push_back(l);
+    }
+  for (int nacc : {2, 3, 4, 5, 10, 17}) {
+      std::vector<CombineParams> tab;
+      std::vector<uint32_t> blk;
+      for (size_t i : order) {
+        PairTables& pt = pts[i];
+        if (pt.ncblk == 0 || pls[i].nacc != nacc) continue;
+        pt.cp.b0 = (uint32_t)blk.size();
+        if ((int64_t)blk.size() + pt.ncblk > 0x7FFFFFFF) return false;
+        blk.insert(blk.end(), (size_t)pt.ncblk, (uint32_t)tab.size());
+        tab.push_back(pt.cp);
+      }
+      if (tab.empty()) continue;
+      ScoreBatchLaunch l{};
+      l.kind = 1;
+      l.nacc = nacc;
+      l.tab_off = put(tab.data(), tab.size() * sizeof(CombineParams));
+      l.blk_off = put(blk.data(), blk.size() * 4);
+      l.nblk = (uint32_t)blk.size();
+      out->launches.push_back(l);
+    }
+  return true;
+}
+
+hipError_t launch_score_batch(const ScoreBatchPlan& pl, const uint8_t* d_blob, hipStream_t s) {
+  for (const ScoreBatchLaunch& l : pl.launches) {
+    const uint32_t* blk = (const uint32_t*)(d_blob + l.blk_off);
+    hipError_t e;
+    if (l.kind == 0) {
+      timing_begin(K_SCORE_FUSED);
+      e = go_tile_any(l.G, l.uni != 0, TileParams{}, 0, (const TileParams*)(d_blob + l.tab_off), blk, l.nblk, s);
+      timing_end(K_SCORE_FUSED);
+    } else {
+      timing_begin(K_SCORE_COMBINE);
+      e = go_combine_any(l.nacc, CombineParams{}, l.nblk, (const CombineParams*)(d_blob + l.tab_off),
+                         blk, s);
+      timing_end(K_SCORE_COMBINE);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 bool fused_supported(const DeviceTemplate& t) { return plan_tile(t).ok; }

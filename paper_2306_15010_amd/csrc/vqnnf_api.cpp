@@ -82,9 +82,16 @@ struct vqnnf_ctx {
     std::vector<uint64_t> sig;
     Buffer frag, cnorm, passes, outs;
     int n_pass = 0;
+    int n_groups = 0;                  // load groups of 32 elements along D
     std::vector<int> slot_pair;        // output slot -> index in the map group
   };
   std::vector<MultiPlan> mplans;       // one per map group of the last batch
+  // batched re-score and score of the fused groups' pairs
+  Buffer b_part;       // partial sums of every pair's on-chip score
+  Buffer b_tab;        // argument tables (re-score, then score)
+  std::vector<uint8_t> b_tab_host;     // what b_tab holds
+  void* b_tab_at = nullptr;            // ... at this allocation
+  std::map<std::vector<int>, int> btyw_cache;   // batch shapes -> window rows per tile
   // autotuned window rows per score tile, by shape (w, h, g, kpad, H, W, uniform bins)
   bool autotune = true;
   bool capturing = false;
@@ -824,7 +831,8 @@ void vqnnf_ctx_destroy(vqnnf_ctx* c) {
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     Buffer* bs[] = {&c->control, &c->labels, &c->wl_pix, &c->wl_mask, &c->int_side, &c->int_p,
-                    &c->partials, &c->keys, &c->pca, &c->m_labels, &c->m_count, &c->m_wl_pix, &c->m_wl_mask};
+                    &c->partials, &c->keys, &c->pca, &c->m_labels, &c->m_count, &c->m_wl_pix, &c->m_wl_mask,
+                    &c->b_part, &c->b_tab};
     for (Buffer* b : bs)
       if (b->p) hipFree(b->p);
     for (auto& mp : c->mplans)
@@ -1442,8 +1450,10 @@ bool multi_ok(const std::vector<int>& gr, const vqnnf_template* const* t, const 
 // 8 blocks per pass; fragments, norms, pass and output tables on the device.
 vqnnf_status build_multi_plan(vqnnf_ctx* c, vqnnf_ctx::MultiPlan& mp, const std::vector<int>& gr,
                               const vqnnf_template* const* t, const vqnnf_fmap* q0,
-                              const std::vector<const ScaledSet*>& sets, int64_t n_pix) {
-  std::vector<uint64_t> sig = {(uint64_t)q0->D, (uint64_t)q0->dtype, (uint64_t)n_pix,
+                              const std::vector<const ScaledSet*>& sets, int64_t n_pix, int64_t lab0,
+                              int slot0) {
+  std::vector<uint64_t> sig = {(uint64_t)q0->D, (uint64_t)q0->dtype, (uint64_t)n_pix, (uint64_t)lab0,
+                               (uint64_t)slot0,
                                (uint64_t)(uintptr_t)c->m_labels.p, (uint64_t)(uintptr_t)c->m_count.p,
                                (uint64_t)(uintptr_t)c->m_wl_pix.p, (uint64_t)(uintptr_t)c->m_wl_mask.p};
   for (int i : gr) sig.insert(sig.end(), {(uint64_t)(uintptr_t)t[i], (uint64_t)(uintptr_t)sets[i]});
@@ -1498,10 +1508,11 @@ vqnnf_status build_multi_plan(vqnnf_ctx* c, vqnnf_ctx::MultiPlan& mp, const std:
                         (size_t)kb * 16 * 4, hipMemcpyDeviceToDevice));
       const BoundCoef& b = ss ? ss->bound : d.bound_bf16q;
       MultiOut& o = outs[slot];
-      o.labels = (uint8_t*)c->m_labels.p + (size_t)slot * n_pix;
-      o.wl_count = (uint32_t*)c->m_count.p + slot;
-      o.wl_pix = (uint32_t*)c->m_wl_pix.p + (size_t)slot * n_pix;
-      o.wl_mask = (uint32_t*)c->m_wl_mask.p + (size_t)slot * n_pix * 4;
+      const int64_t px0 = lab0 + (int64_t)slot * n_pix;
+      o.labels = (uint8_t*)c->m_labels.p + px0;
+      o.wl_count = (uint32_t*)c->m_count.p + slot0 + slot;
+      o.wl_pix = (uint32_t*)c->m_wl_pix.p + px0;
+      o.wl_mask = (uint32_t*)c->m_wl_mask.p + px0 * 4;
       o.a0 = b.a0;
       o.a1 = b.a1;
       o.a2 = b.a2;
@@ -1510,54 +1521,111 @@ vqnnf_status build_multi_plan(vqnnf_ctx* c, vqnnf_ctx::MultiPlan& mp, const std:
   HIP_TRY(hipMemcpy(mp.passes.p, passes.data(), passes.size() * sizeof(MultiPass), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(mp.outs.p, outs.data(), outs.size() * sizeof(MultiOut), hipMemcpyHostToDevice));
   mp.n_pass = np;
+  mp.n_groups = ngr;
   mp.slot_pair = slot_pair;
   mp.sig = sig;
   return ok();
 }
 
-// Enqueues a fused map group: one multi-template assignment, then per
-// template its FP64 re-score and its score.
-vqnnf_status enqueue_multi(vqnnf_ctx* c, const vqnnf_ctx::MultiPlan& mp, const std::vector<int>& gr,
-                           const vqnnf_template* const* t, const vqnnf_fmap* const* q,
-                           const std::vector<const ScaledSet*>& sets, float* const* heatmaps,
-                           unsigned long long* keys) {
-  const vqnnf_fmap* q0 = q[gr[0]];
-  const int64_t n_pix = (int64_t)q0->H * q0->W;
-  const int nt = (int)gr.size();
-  HIP_TRY(launch_fill_u32((uint32_t*)c->m_count.p, 0u, nt, c->stream));
+// The fused multi-template assignment of one map group (labels, worklists).
+hipError_t enqueue_multi_assign(vqnnf_ctx* c, const vqnnf_ctx::MultiPlan& mp, const vqnnf_fmap* q0) {
   MultiArgs ma{};
   ma.kp.q = q0->data;
-  ma.kp.stride = q0->pixel_stride ? q0->pixel_stride : q0->D;
-  ma.kp.n_pix = n_pix;
+  ma.kp.stride = map_stride(q0);
+  ma.kp.n_pix = (int64_t)q0->H * q0->W;
   ma.kp.D = q0->D;
   ma.kp.frag = (const uint4*)mp.frag.p;
   ma.kp.cnorm = (const float*)mp.cnorm.p;
-  ma.kp.n_groups = t[gr[0]]->t.geom.d_pad_bf16 / 32;
+  ma.kp.n_groups = mp.n_groups;
   ma.kp.n_pass = mp.n_pass;
   ma.kp.passes = (const MultiPass*)mp.passes.p;
   ma.kp.outs = (const MultiOut*)mp.outs.p;
   ma.fp8 = q0->dtype == VQNNF_FP8_E4M3;
-  HIP_TRY(launch_assign_multi(ma, c->stream, c->n_cu));
-  for (int slot = 0; slot < nt; ++slot) {
+  return launch_assign_multi(ma, c->stream, c->n_cu);
+}
+
+// Pair work of the fused groups after their assignment: re-score arguments,
+// on-chip score items and the pairs scored one by one.
+struct FusedWork {
+  std::vector<AssignArgs> rescore;
+  std::vector<ScoreBatchItem> score;
+  std::vector<int> loose;              // pair index
+  std::vector<const uint8_t*> loose_lab;
+};
+
+void fused_work(vqnnf_ctx* c, const vqnnf_ctx::MultiPlan& mp, const std::vector<int>& gr,
+                const vqnnf_template* const* t, const vqnnf_fmap* const* q,
+                const std::vector<const ScaledSet*>& sets, float* const* heatmaps, unsigned long long* keys,
+                int64_t lab0, int slot0, FusedWork& w) {
+  const vqnnf_fmap* q0 = q[gr[0]];
+  const int64_t n_pix = (int64_t)q0->H * q0->W;
+  for (int slot = 0; slot < (int)gr.size(); ++slot) {
     const int i = gr[mp.slot_pair[slot]];
     const DeviceTemplate& d = t[i]->t;
-    uint8_t* lab = (uint8_t*)c->m_labels.p + (size_t)slot * n_pix;
+    const int64_t px0 = lab0 + (int64_t)slot * n_pix;
+    uint8_t* lab = (uint8_t*)c->m_labels.p + px0;
     AssignArgs a{};
     a.q = q0->data;
-    a.stride = ma.kp.stride;
+    a.stride = map_stride(q0);
     a.n_pix = n_pix;
     a.D = q0->D;
     a.dtype = q0->dtype;
     a.t = &d;
     a.scale = sets[i] ? sets[i]->d_scale : nullptr;
     a.labels = lab;
-    a.wl_count = (uint32_t*)c->m_count.p + slot;
-    a.wl_pix = (uint32_t*)c->m_wl_pix.p + (size_t)slot * n_pix;
-    a.wl_mask = (uint32_t*)c->m_wl_mask.p + (size_t)slot * n_pix * 4;
-    HIP_TRY(launch_rescore(a, c->stream, c->n_cu));
-    vqnnf_status s = enqueue_score_labels(c, t[i], lab, q0->H, q0->W, heatmaps[i], keys + i);
-    if (s) return s;
+    a.wl_count = (uint32_t*)c->m_count.p + slot0 + slot;
+    a.wl_pix = (uint32_t*)c->m_wl_pix.p + px0;
+    a.wl_mask = (uint32_t*)c->m_wl_mask.p + px0 * 4;
+    a.mask_words = (pow2_blocks(d.geom.kb) + 1) / 2;   // as the fused kernel writes them
+    w.rescore.push_back(a);
+    if (fused_supported(d)) {
+      w.score.push_back({&d, lab, q0->H, q0->W, heatmaps[i], keys + i, 0});
+    } else {
+      w.loose.push_back(i);
+      w.loose_lab.push_back(lab);
+    }
   }
+}
+
+// Window rows per tile of a batched score: the tallest tiles (least tile
+// set-up per window) that still give every compute unit 8 blocks.
+int batch_default_tyw(const std::vector<ScoreBatchItem>& items, int n_cu) {
+  for (int cap : {256, 128, 64, 32, 16}) {
+    int64_t blocks = 0;
+    for (const ScoreBatchItem& it : items) {
+      const int ow = it.W - it.t->w + 1, oh = it.H - it.t->h + 1;
+      const int64_t nx = (ow + 255) / 256;
+      blocks += nx * ((oh + std::min(cap, oh) - 1) / std::min(cap, oh)) * (it.t->geom.kpad / 16);
+    }
+    if (blocks >= 8LL * n_cu) return cap;
+  }
+  return 8;
+}
+
+std::vector<int> batch_shape_key(const std::vector<ScoreBatchItem>& items, int n_cu) {
+  std::vector<int> key = {n_cu};
+  for (const ScoreBatchItem& it : items) {
+    const DeviceTemplate& d = *it.t;
+    key.insert(key.end(), {d.w, d.h, d.grid.g, d.geom.kpad, it.H, it.W});
+    for (int f = 0; f < d.n_filters; ++f) {
+      uint32_t b;
+      std::memcpy(&b, &d.weights[f], 4);
+      key.push_back((int)b);
+    }
+  }
+  return key;
+}
+
+// Builds the batched score tables for window rows `tyw` (partial sums in
+// b_part) and appends them to blob at a 256-byte boundary; returns the offset.
+vqnnf_status plan_batch_score(vqnnf_ctx* c, std::vector<ScoreBatchItem> items, int tyw, ScoreBatchPlan& pl,
+                              std::vector<uint8_t>& blob, size_t* off) {
+  for (ScoreBatchItem& it : items) it.tyw = tyw;
+  if (!plan_score_batch(items, c->b_part.p, &pl))
+    return fail(VQNNF_EINVAL, "batched score: a pair's bank or size is outside the on-chip kernel's range");
+  *off = (blob.size() + 255) / 256 * 256;
+  blob.resize(*off + pl.blob.size());
+  std::memcpy(blob.data() + *off, pl.blob.data(), pl.blob.size());
   return ok();
 }
 
@@ -1609,34 +1677,139 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     groups.push_back(cur);
   }
   std::vector<char> fused(groups.size(), 0);
+  // the fused groups' label maps, worklists and counters one after another
+  std::vector<int64_t> lab0(groups.size(), 0);
+  std::vector<int> slot0(groups.size(), 0);
   size_t ml = 0;
+  int nslot = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     fused[gi] = multi_ok(groups[gi], t, q[groups[gi][0]], prec);
-    if (fused[gi]) ml = std::max(ml, groups[gi].size() * (size_t)q[groups[gi][0]]->H * q[groups[gi][0]]->W);
+    if (!fused[gi]) continue;
+    lab0[gi] = (int64_t)ml;
+    slot0[gi] = nslot;
+    ml += groups[gi].size() * (size_t)q[groups[gi][0]]->H * q[groups[gi][0]]->W;
+    nslot += (int)groups[gi].size();
   }
   if (ml) {
-    if ((s = check_cap(c, {{&c->m_labels, ml}, {&c->m_count, 4096}, {&c->m_wl_pix, ml * 4},
+    const size_t cb = std::max<size_t>(4096, (size_t)nslot * 4);
+    if ((s = check_cap(c, {{&c->m_labels, ml}, {&c->m_count, cb}, {&c->m_wl_pix, ml * 4},
                            {&c->m_wl_mask, ml * 16}})) ||
         (s = ensure(c, c->m_labels, ml, "batched label maps")) ||
-        (s = ensure(c, c->m_count, 4096, "batched worklist counters")) ||
+        (s = ensure(c, c->m_count, cb, "batched worklist counters")) ||
         (s = ensure(c, c->m_wl_pix, ml * 4, "batched re-score worklists")) ||
         (s = ensure(c, c->m_wl_mask, ml * 16, "batched candidate masks")))
       return s;
   }
   if (c->mplans.size() < groups.size()) c->mplans.resize(groups.size());
+  unsigned long long* keys = (unsigned long long*)c->keys.p;
+  FusedWork fw;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     if (!fused[gi]) continue;
     const vqnnf_fmap* q0 = q[groups[gi][0]];
-    if ((s = build_multi_plan(c, c->mplans[gi], groups[gi], t, q0, sets, (int64_t)q0->H * q0->W)))
+    if ((s = build_multi_plan(c, c->mplans[gi], groups[gi], t, q0, sets, (int64_t)q0->H * q0->W, lab0[gi],
+                              slot0[gi])))
       return s;
+    fused_work(c, c->mplans[gi], groups[gi], t, q, sets, heatmaps, keys, lab0[gi], slot0[gi], fw);
   }
-  unsigned long long* keys = (unsigned long long*)c->keys.p;
+  // batched re-score and score tables of the fused pairs
+  RescoreBatchPlan rplan;
+  ScoreBatchPlan splan;
+  std::vector<uint8_t> blob;
+  size_t soff = 0;
+  std::vector<int> bkey;
+  bool tune = false;
+  int tyw = 0;
+  // (re)builds the tables for the cached or default tile height and uploads
+  // them when they changed
+  auto prepare_tables = [&]() -> vqnnf_status {
+    vqnnf_status st;
+    blob.clear();
+    rplan = RescoreBatchPlan{};
+    splan = ScoreBatchPlan{};
+    if (!fw.rescore.empty()) {
+      plan_rescore_batch(fw.rescore, &rplan);
+      blob = rplan.blob;
+    }
+    if (!fw.score.empty()) {
+      std::vector<ScoreBatchItem> sized = fw.score;   // partial sizes do not depend on the tile height
+      for (ScoreBatchItem& it : sized) it.tyw = 1;
+      if (!plan_score_batch(sized, nullptr, &splan))
+        return fail(VQNNF_EINVAL, "batched score: a pair's bank or size is outside the on-chip kernel's range");
+      if ((st = check_cap(c, {{&c->b_part, splan.part_bytes}})) ||
+          (st = ensure(c, c->b_part, std::max<size_t>(splan.part_bytes, 256), "batched score partial sums")))
+        return st;
+      bkey = batch_shape_key(fw.score, c->n_cu);
+      auto it = c->btyw_cache.find(bkey);
+      tune = it == c->btyw_cache.end() && c->autotune;
+      tyw = it != c->btyw_cache.end() ? it->second : batch_default_tyw(fw.score, c->n_cu);
+      if ((st = plan_batch_score(c, fw.score, tyw, splan, blob, &soff))) return st;
+    }
+    if (!blob.empty()) {
+      if ((st = check_cap(c, {{&c->b_tab, blob.size()}})) ||
+          (st = ensure(c, c->b_tab, blob.size(), "batched argument tables")))
+        return st;
+      if (c->b_tab_at != c->b_tab.p || c->b_tab_host != blob) {
+        // kernels of an earlier batch may still read the tables being replaced
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        HIP_TRY(hipMemcpy(c->b_tab.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
+        c->b_tab_host = blob;
+        c->b_tab_at = c->b_tab.p;
+      }
+    }
+    return ok();
+  };
+  if ((s = prepare_tables())) return s;
+  // Times each candidate tile height on this very call (every run writes the
+  // same heatmaps and keys) and keeps the fastest for the batch's shapes.
+  auto tune_score = [&]() -> vqnnf_status {
+    std::vector<int> cand = {tyw};
+    for (int v : {16, 32, 64, 128, 256})
+      if (std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
+    std::vector<ScoreBatchPlan> pls(cand.size());
+    std::vector<uint8_t> cblob;
+    std::vector<size_t> offs(cand.size());
+    vqnnf_status st;
+    for (size_t ci = 0; ci < cand.size(); ++ci)
+      if ((st = plan_batch_score(c, fw.score, cand[ci], pls[ci], cblob, &offs[ci]))) return st;
+    Buffer tmp;
+    if ((st = ensure(c, tmp, cblob.size(), "autotuning argument tables"))) return st;
+    HIP_TRY(hipMemcpyAsync(tmp.p, cblob.data(), cblob.size(), hipMemcpyHostToDevice, c->stream));
+    set_timing_hook(nullptr);
+    std::vector<hipEvent_t> ev(2 * cand.size());
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
+      for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
+        if (rep == 1) e = hipEventRecord(ev[2 * ci], c->stream);
+        if (e == hipSuccess) e = launch_score_batch(pls[ci], (const uint8_t*)tmp.p + offs[ci], c->stream);
+        if (rep == 1 && e == hipSuccess) e = hipEventRecord(ev[2 * ci + 1], c->stream);
+      }
+    if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+    float best_ms = 1e30f;
+    int best = tyw;
+    for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[2 * ci], ev[2 * ci + 1]);
+      if (e == hipSuccess && ms < best_ms) { best_ms = ms; best = cand[ci]; }
+    }
+    for (auto& ee : ev) hipEventDestroy(ee);
+    hipStreamSynchronize(c->stream);
+    hipFree(tmp.p);
+    c->used -= tmp.bytes;
+    if (c->timing) {
+      TimingHook h{hook_begin, hook_end, c};
+      set_timing_hook(&h);
+    }
+    if (e != hipSuccess) return fail(VQNNF_EHIP, "batched score autotuning: %s", hipGetErrorString(e));
+    c->btyw_cache[bkey] = best;
+    return ok();   // the last candidate's run already produced the result
+  };
   auto enqueue_all = [&]() -> vqnnf_status {
     HIP_TRY(launch_fill_u32((uint32_t*)keys, 0u, 2 * (int64_t)n, c->stream));
+    if (nslot) HIP_TRY(launch_fill_u32((uint32_t*)c->m_count.p, 0u, nslot, c->stream));
     for (size_t gi = 0; gi < groups.size(); ++gi) {
       if (fused[gi]) {
-        vqnnf_status st = enqueue_multi(c, c->mplans[gi], groups[gi], t, q, sets, heatmaps, keys);
-        if (st) return st;
+        HIP_TRY(enqueue_multi_assign(c, c->mplans[gi], q[groups[gi][0]]));
         continue;
       }
       for (int i : groups[gi]) {
@@ -1644,12 +1817,46 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
         if (st) return st;
       }
     }
+    const uint8_t* d_tab = (const uint8_t*)c->b_tab.p;
+    if (!rplan.launches.empty()) HIP_TRY(launch_rescore_batch(rplan, d_tab, c->n_cu, c->stream));
+    if (!splan.launches.empty()) {
+      if (tune && !c->capturing) {
+        tune = false;
+        vqnnf_status st = tune_score();
+        if (st) return st;
+      } else {
+        HIP_TRY(launch_score_batch(splan, d_tab + soff, c->stream));
+      }
+    }
+    for (size_t li = 0; li < fw.loose.size(); ++li) {
+      const int i = fw.loose[li];
+      vqnnf_status st = enqueue_score_labels(c, t[i], fw.loose_lab[li], q[i]->H, q[i]->W, heatmaps[i], keys + i);
+      if (st) return st;
+    }
     return ok();
   };
   if (!c->graph) {
     HookScope hs(c);
     if ((s = enqueue_all())) return s;
   } else {
+    // shapes not tuned yet are tuned by one eager run before the capture
+    bool untuned = tune;
+    for (size_t gi = 0; gi < groups.size() && c->autotune; ++gi) {
+      if (fused[gi]) continue;   // pairs scored one by one
+      for (int i : groups[gi]) {
+        const DeviceTemplate& d = t[i]->t;
+        if (!fused_supported(d)) continue;
+        bool uni = true;
+        for (int f = 2; f < d.n_filters; ++f) uni = uni && d.weights[f] == d.weights[1];
+        const std::vector<int> key = {d.w, d.h, d.grid.g, d.geom.kpad, q[i]->H, q[i]->W, uni ? 1 : 0};
+        untuned = untuned || c->tyw_cache.find(key) == c->tyw_cache.end();
+      }
+    }
+    if (untuned) {
+      HookScope hs(c);
+      if ((s = enqueue_all())) return s;
+      if ((s = prepare_tables())) return s;
+    }
     // every argument the captured kernels depend on, scratch and plans included
     std::vector<uint64_t> sig = {(uint64_t)n, (uint64_t)prec, (uint64_t)(uintptr_t)c->stream,
                                  (uint64_t)(uintptr_t)c->control.p, (uint64_t)(uintptr_t)c->labels.p,
@@ -1658,6 +1865,8 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
                                  (uint64_t)(uintptr_t)c->int_p.p, (uint64_t)(uintptr_t)keys,
                                  (uint64_t)(uintptr_t)c->m_labels.p, (uint64_t)(uintptr_t)c->m_count.p,
                                  (uint64_t)(uintptr_t)c->m_wl_pix.p, (uint64_t)(uintptr_t)c->m_wl_mask.p};
+    sig.insert(sig.end(), {(uint64_t)(uintptr_t)c->b_part.p, (uint64_t)(uintptr_t)c->b_tab.p,
+                           (uint64_t)blob.size(), (uint64_t)soff, (uint64_t)tyw});
     for (size_t gi = 0; gi < groups.size(); ++gi) {
       sig.push_back(fused[gi] ? 1u : 0u);
       if (fused[gi]) {
@@ -1674,17 +1883,6 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
                              (uint64_t)(uintptr_t)sets[i], (uint64_t)(uintptr_t)heatmaps[i]});
     }
     if (!(c->gexec && sig == c->gsig)) {
-      // shapes not tuned yet are tuned by one eager run before the capture
-      bool untuned = false;
-      for (int i = 0; i < n && c->autotune; ++i) {
-        const DeviceTemplate& d = t[i]->t;
-        if (!fused_supported(d)) continue;
-        bool uni = true;
-        for (int f = 2; f < d.n_filters; ++f) uni = uni && d.weights[f] == d.weights[1];
-        const std::vector<int> key = {d.w, d.h, d.grid.g, d.geom.kpad, q[i]->H, q[i]->W, uni ? 1 : 0};
-        untuned = untuned || c->tyw_cache.find(key) == c->tyw_cache.end();
-      }
-      if (untuned && (s = enqueue_all())) return s;
       if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
       // the capture stream waits for earlier work on the context stream
       HIP_TRY(hipStreamSynchronize(c->stream));

@@ -161,6 +161,7 @@ struct AssignArgs {
   uint32_t* wl_count;    // worklist counter (must be 0 on entry)
   uint32_t* wl_pix;      // [n_pix]
   uint32_t* wl_mask;     // [n_pix][mask_words]
+  int mask_words;        // 0: ceil(kpad / 32); the fused multi-template kernel writes its own count
   BoundCoef bound;
 };
 
@@ -197,6 +198,19 @@ hipError_t launch_assign_multi(const MultiArgs& a, hipStream_t s, int n_cu);
 hipError_t launch_assign_plain(const AssignArgs& a, hipStream_t s, int n_cu);
 hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu);
 hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu);
+// Batched re-score of many pairs: one launch per (query type, vector path)
+// class, each pair's arguments read from a device table.
+struct RescoreBatchPlan {
+  struct Launch {
+    int qt, vec;
+    size_t tab_off;
+    int n;
+  };
+  std::vector<uint8_t> blob;
+  std::vector<Launch> launches;
+};
+void plan_rescore_batch(const std::vector<AssignArgs>& pairs, RescoreBatchPlan* out);
+hipError_t launch_rescore_batch(const RescoreBatchPlan& plan, const uint8_t* d_blob, int n_cu, hipStream_t s);
 // Low-dimensional features (F32 / BF16, D <= 32) and RGB colour features:
 // direct FP32 distances with a relative error bound; `refined` appends
 // near ties to the re-score worklist.
@@ -242,6 +256,33 @@ hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_byt
 hipError_t launch_score_integral(const ScoreArgs& a, hipStream_t s);
 // Weighted banks: heatmap + best from the integral image a.P.
 hipError_t launch_score_bank(const ScoreArgs& a, hipStream_t s);
+// Batched on-chip score of many (template, label map) pairs: one tile launch
+// per (grid size, uniform bins) class and one combine launch per stored-sum
+// layout, each reading its pairs' arguments from a device table.
+struct ScoreBatchItem {
+  const DeviceTemplate* t;
+  const uint8_t* labels;
+  int H, W;
+  float* heatmap;
+  unsigned long long* best;    // must be 0
+  int tyw;                     // window rows per tile (>= 1)
+};
+struct ScoreBatchLaunch {
+  int kind;                    // 0 tile, 1 combine
+  int G, uni, nacc;
+  size_t tab_off, blk_off;     // byte offsets into the table blob
+  uint32_t nblk;
+};
+struct ScoreBatchPlan {
+  std::vector<uint8_t> blob;   // argument tables and block -> pair maps
+  std::vector<ScoreBatchLaunch> launches;
+  size_t part_bytes = 0;       // partial sums of all pairs
+};
+// Plans the launches with the partial sums placed in `part` (nullptr: sizes
+// only).  False when a pair's bank is not on-chip or a size overflows.
+bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, ScoreBatchPlan* out);
+// d_blob: a device copy of plan.blob.
+hipError_t launch_score_batch(const ScoreBatchPlan& plan, const uint8_t* d_blob, hipStream_t s);
 // True when the on-chip score kernel can take this template's bank.
 bool fused_supported(const DeviceTemplate& t);
 // Scratch bytes of the on-chip path's per-channel-group partial sums.

@@ -194,3 +194,37 @@ def test_autotune_keeps_results(ctx):
             h.fill_(float("nan"))
         assert B.vqnnf_match_batched(ctx, tpls, fms, P, heats) == ref, rep
         assert all(torch.equal(a, b) for a, b in zip(heats, ref_h)), rep
+
+
+def test_batched_mask_words_and_classes(ctx):
+    """Codebook sizes whose padded block count is not a power of two (k = 80,
+    96: the fused kernel writes four candidate-mask words per pixel) next to
+    k = 8 (one channel group: the tile kernel forms the score itself), with
+    3 x 3 grids over sides not divisible by 3 (bins of unequal area: sums
+    merged by weight)."""
+    wl = synth.make_multi_template(61, 120, 136, 64, 24, 0.3, "bf16", 7, (19, 44), (80, 96, 8, 48), 3)
+    tpls, fms, heats, meta, _ = make_pairs(ctx, wl)
+    log("k per template:", [t.k for t in wl.templates[0]], "sides:", [t.data.shape[0] for t in wl.templates[0]])
+    P = B.VQNNF_PREC_BF16_REFINED
+    out = B.vqnnf_match_batched(ctx, tpls, fms, P, heats)
+    refs, bests = per_pair(ctx, tpls, fms, heats, P)
+    for i in range(len(tpls)):
+        assert torch.equal(heats[i], refs[i]), f"pair {i} (k={tpls[i].k})"
+        assert out[i] == bests[i]
+    for i in range(len(tpls)):
+        check_oracle(wl, tpls[i], *meta[i], heats[i])
+
+
+def test_largest_template(ctx):
+    """Templates of the largest side (255): the per-group sums of a window
+    reach their 16-bit storage's largest values (single and batched)."""
+    wl = synth.make_multi_template(67, 290, 300, 16, 12, 0.3, "bf16", 2, (255, 255), (32, 48), 2)
+    tpls, fms, heats, meta, _ = make_pairs(ctx, wl)
+    log("sides:", [t.data.shape[:2] for t in wl.templates[0]])
+    P = B.VQNNF_PREC_BF16_REFINED
+    out = B.vqnnf_match_batched(ctx, tpls, fms, P, heats)
+    refs, bests = per_pair(ctx, tpls, fms, heats, P)
+    for i in range(len(tpls)):
+        assert torch.equal(heats[i], refs[i]), f"pair {i}"
+        assert out[i] == bests[i]
+        check_oracle(wl, tpls[i], *meta[i], heats[i])
