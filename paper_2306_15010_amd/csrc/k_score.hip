@@ -102,8 +102,8 @@ constexpr int kKG = 16;                // channels per block
 constexpr int kPQ = kKG / 8;           // 16-byte entries (four pairs) per column per band
 constexpr int kTXW = 256;              // windows per tile row
 constexpr int kST = 512;               // threads per block: kTXW windows x kPQ pair groups
-constexpr int kMaxAcc = 17;            // sums per window: full window + up to 4 x 4 bins
-constexpr int kMaxCls = 4;             // merged bin classes (distinct bin weights)
+constexpr int kMaxCls = 4;             // bin weight classes (distinct bin weights)
+constexpr int kMaxAcc = 1 + kMaxCls;   // stored sums per window: full window + classes
 
 struct TileParams {
   const uint8_t* labels;
@@ -116,8 +116,8 @@ struct TileParams {
   const uint32_t* t16;  // [nf][kpad/2] template counts, u16 pairs
   uint16_t* part;       // [ng][nacc][pstride] sums of min(T_j, C_j)
   int64_t pstride;      // windows per partial row, oh*ow rounded up to 4
-  int nacc;             // sums per window: 2 (one bin weight), 1 + classes, or 1 + g*g
-  uint32_t cmask[kMaxCls];  // merged classes: bit f of cmask[c - 1] = bin filter f in sum c
+  int nacc;             // sums per window: 1 + weight classes of the bins
+  uint32_t cmask[kMaxCls];  // bit f of cmask[c - 1]: bin filter f in sum c (unused: 0)
   int nx, ng;           // tiles per heatmap row, channel groups
   uint32_t b0;          // batched launches: first block of the pair
   // one channel group: eq. 2 per sum a, the heatmap and the best key
@@ -170,12 +170,13 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
 template <int G, bool UNI>
 __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int by, int grp) {
   constexpr int NF = 1 + G * G;
-  constexpr int NACC = UNI ? 2 : NF;
+  constexpr int NACC = UNI ? 2 : NF;                 // accumulators while scoring
+  constexpr int NOUT = UNI ? 2 : 1 + kMaxCls;        // sums after merging bins of equal weight
   constexpr int NR = G * kPQ;                        // (band, pair group) rows
   static_assert(NR <= kST / 64, "one wave per prefix row");
   __shared__ uint4 Qs[NR][kHS];
   __shared__ uint4 Hs[NR][kHS];
-  __shared__ uint32_t red[NACC][kTXW];
+  __shared__ uint16_t red[NOUT][kTXW];               // pair group 1's sums (<= w*h < 2^16)
   const auto labs = gbl(p.labels);
   const auto t16 = gbl(p.t16);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -232,25 +233,36 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
 
   uint32_t acc[NACC];
   unsigned long long key = 0ull;
-  // pair group 0 adds group 1's sums, merges bins of equal weight and stores
-  // the sums, or with one channel group forms the score itself
-  const bool merged = !UNI && p.nacc < NF;
-  auto store_row = [&](int yy) {
-    uint32_t v[NACC];
+  // the stored sums: full window, then the bins of each weight class
+  auto merge = [&](uint32_t (&o)[NOUT]) {
+    if constexpr (UNI) {
+      o[0] = acc[0];
+      o[1] = acc[1];
+    } else {
+      o[0] = acc[0];
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) v[a] = acc[a] + red[a][xl];
+      for (int c = 1; c < NOUT; ++c) {
+        const uint32_t cm = p.cmask[c - 1];
+        uint32_t v = 0u;
+#pragma unroll
+        for (int f = 1; f < NF; ++f) v += ((cm >> f) & 1u) ? acc[f] : 0u;
+        o[c] = v;
+      }
+    }
+  };
+  // pair group 0 adds group 1's sums and stores them, or with one channel
+  // group forms the score itself
+  auto store_row = [&](int yy) {
+    uint32_t v[NOUT];
+    merge(v);
+#pragma unroll
+    for (int a = 0; a < NOUT; ++a) v[a] += red[a][xl];
     const int64_t win = (int64_t)yy * p.ow + x0 + xl;
     float s = 0.f;
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) {
+    for (int a = 0; a < NOUT; ++a) {
       if (a >= p.nacc) break;
-      uint32_t o = v[a];
-      if (!UNI && merged && a >= 1 && a <= kMaxCls) {
-        const uint32_t cm = p.cmask[a >= 1 && a <= kMaxCls ? a - 1 : 0];
-        o = 0u;
-#pragma unroll
-        for (int f = 1; f < NF; ++f) o += ((cm >> f) & 1u) ? v[f] : 0u;
-      }
+      const uint32_t o = v[a];
       if (p.ng == 1) {
         s = fmaf(p.wt[a], (float)(p.area2[a] - 2 * (int)o), s);
       } else {
@@ -314,8 +326,10 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
 #pragma unroll
       for (int s = 0; s < 4; ++s) acc[0] = min_dot(full[s], T[0][s], acc[0]);
       if (pq == 1) {
+        uint32_t o[NOUT];
+        merge(o);
 #pragma unroll
-        for (int a = 0; a < NACC; ++a) red[a][xl] = acc[a];
+        for (int a = 0; a < NOUT; ++a) red[a][xl] = (uint16_t)o[a];
       }
     }
     // ---- vertical update of Q to row y + 1, then prefetch for row y + 2
@@ -503,22 +517,23 @@ TilePlan plan_tile(const DeviceTemplate& t) {
   if ((int64_t)maxband * (kColsMax + 1) >= 65536) return pl;   // u16 prefix counts
   // bins of equal weight share a sum: classes in order of first appearance
   std::vector<float> wd;
-  int cls[kMaxAcc] = {};
+  int cls[17] = {};
   for (int f = 1; f < NF; ++f) {
     const auto it = std::find(wd.begin(), wd.end(), t.weights[f]);
     cls[f] = (int)(it - wd.begin());
     if (it == wd.end()) wd.push_back(t.weights[f]);
   }
+  // more distinct bin weights than stored sums: the integral-image path
+  if ((int)wd.size() > kMaxCls) return pl;
   pl.uni = wd.size() == 1;
-  const bool merged = !pl.uni && (int)wd.size() <= kMaxCls;
-  pl.nacc = pl.uni ? 2 : merged ? 1 + (int)wd.size() : NF;
+  pl.nacc = 1 + (int)wd.size();
   for (int f = 0; f < NF; ++f) {
     const int32_t* b = &t.boxes[(size_t)f * 4];
     const int area = (b[2] - b[0]) * (b[3] - b[1]);
-    const int a = f == 0 ? 0 : pl.uni ? 1 : merged ? 1 + cls[f] : f;
+    const int a = f == 0 ? 0 : 1 + cls[f];
     pl.wt[a] = t.weights[f];
     pl.area2[a] += 2 * area;
-    if (merged && f > 0) pl.cmask[cls[f]] |= 1u << f;
+    if (f > 0) pl.cmask[cls[f]] |= 1u << f;
   }
   if ((int64_t)t.w * t.h > 65535) return pl;   // 16-bit partial sums
   pl.ok = true;
@@ -645,8 +660,6 @@ hipError_t go_combine_any(int nacc, const CombineParams& cp, int64_t nblk, const
     case 3: VQ_COMB(3);
     case 4: VQ_COMB(4);
     case 5: VQ_COMB(5);
-    case 10: VQ_COMB(10);
-    case 17: VQ_COMB(17);
     default: return hipErrorInvalidValue;
   }
 #undef VQ_COMB
@@ -673,7 +686,7 @@ hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_byt
   make_pair(t, pl, a.labels, a.H, a.W, tyw, (uint16_t*)a.partials, a.heatmap, a.best, &pt);
   if (lds_bytes_out) {
     const int NR = pt.G * kPQ;
-    *lds_bytes_out = (size_t)2 * NR * kHS * 16 + (size_t)(pl.uni ? 2 : t.n_filters) * kTXW * 4;
+    *lds_bytes_out = (size_t)2 * NR * kHS * 16 + (size_t)(pl.uni ? 2 : kMaxAcc) * kTXW * 2;
   }
   timing_begin(K_SCORE_FUSED);
   hipError_t e = go_tile_any(pt.G, pt.uni, pt.tp, pt.ny, nullptr, nullptr, 0, s);
@@ -736,7 +749,7 @@ bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, Scor
       l.nblk = (uint32_t)blk.size();
       out->launches.push_back(l);
     }
-  for (int nacc : {2, 3, 4, 5, 10, 17}) {
+  for (int nacc : {2, 3, 4, 5}) {
       std::vector<CombineParams> tab;
       std::vector<uint32_t> blk;
       for (size_t i : order) {
