@@ -248,11 +248,16 @@ vqnnf_status vqnnf_filter(vqnnf_ctx* ctx, const vqnnf_template* t, const uint8_t
  *   heatmap[y*(W-w+1) + x] = -sum_f weight_f * sum_j |R_f,j(tau) - C_f,j(x,y)|
  * where C_f,j(x,y) counts label j in filter f's box shifted to the window
  * whose top-left is (x, y); only windows inside the map are scored.  The
- * per-filter L1 is exact integer arithmetic; the weighted sum is FP32 in
- * filter order.  best_xy/best_score: HOST, may be NULL; the first maximum in
- * row-major order (non-NULL synchronises).
+ * per-filter L1 is exact integer arithmetic, and so is its sum over the
+ * bins of one weight; the weighted sum is FP32: the full window, then one
+ * term per distinct bin weight in order of first appearance.
+ * best_xy/best_score: HOST, may be NULL; the first maximum in row-major
+ * order (non-NULL synchronises).
  *  labels: DEVICE uint8[H*W]; heatmap: DEVICE float[(H-h+1)*(W-w+1)];
- *  requires w <= W, h <= H. */
+ *  requires w <= W, h <= H.  VQNNF_ENOTSUP for banks other than the full
+ *  window + g x g grid (g <= 4) with at most four distinct bin weights, or
+ *  beyond the on-chip tile's width; vqnnf_filter + vqnnf_score_integral
+ *  take those. */
 vqnnf_status vqnnf_score(vqnnf_ctx* ctx, const vqnnf_template* t, const uint8_t* labels,
                          int32_t H, int32_t W, float* heatmap, int32_t* best_xy,
                          float* best_score);
@@ -281,7 +286,13 @@ vqnnf_status vqnnf_match(vqnnf_ctx* ctx, const vqnnf_template* t, const vqnnf_fm
  * and storage, and the same map may appear in several pairs.  best_xy
  * (host, 2*n_pairs) and best_score (host, n_pairs) receive each pair's
  * localisation (Sec. 4); both NULL skips the synchronisation.  Every pair
- * is validated before anything is enqueued (EINVAL names the pair).  With
+ * is validated before anything is enqueued (EINVAL names the pair).
+ * Launch structure (BF16-refined, BF16/FP8 maps): per query map one fused
+ * assignment of all its templates, then for the whole batch one FP64
+ * re-score launch, one score launch per grid size and one combine launch
+ * per stored-sum count, each reading its pairs' arguments from a device
+ * table; other pairs run the single-pair path in turn.  Results equal
+ * vqnnf_match's for every pair, bit for bit.  With
  * graph mode on (vqnnf_ctx_set_graph) the batch's kernels are captured into
  * one HIP graph and later calls with the same arguments (handles, pointers,
  * sizes, precision) replay it as a single launch; the inputs' contents may
@@ -291,10 +302,11 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* ctx, int32_t n_pairs, const vqnnf_te
                                  int32_t* best_xy, float* best_score);
 
 /* Autotuning of the on-chip score's tile height (1 = on, the default): the
- * first call for a shape (template size, grid, codebook size, map size)
- * times a few tile heights on that call's own data (each run writes the same
- * result) and keeps the fastest; calls made while a graph is captured use the
- * tuned value if there is one, else the default sizing.  0 turns it off and
+ * first call for a shape (template size, grid, codebook size, map size; for
+ * a batched score launch, the shapes of all its pairs) times a few tile
+ * heights on that call's own data (each run writes the same result) and
+ * keeps the fastest; calls made while a graph is captured use the tuned
+ * value if there is one, else the default sizing.  0 turns it off and
  * forgets tuned values. */
 vqnnf_status vqnnf_ctx_set_autotune(vqnnf_ctx* ctx, int32_t enable);
 

@@ -1361,7 +1361,8 @@ vqnnf_status vqnnf_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* l
   if ((s = check_score_dims(t, H, W))) return s;
   if (!fused_supported(t->t))
     return fail(VQNNF_ENOTSUP, "on-chip scoring needs the full-window + g x g grid bank (g <= 4) "
-                "within the LDS budget; use vqnnf_filter + vqnnf_score_integral");
+                "with at most four distinct bin weights, within the LDS budget; use vqnnf_filter + "
+                "vqnnf_score_integral");
   const size_t pb = fused_partial_bytes(t->t, H, W);
   if ((s = check_cap(c, {{&c->control, 64}, {&c->partials, pb}}))) return s;
   if ((s = need_device(c))) return s;
@@ -1930,7 +1931,10 @@ vqnnf_status vqnnf_ctx_set_autotune(vqnnf_ctx* c, int32_t enable) {
   vqnnf_status s = check_ctx(c);
   if (s) return s;
   c->autotune = enable != 0;
-  if (!c->autotune) c->tyw_cache.clear();
+  if (!c->autotune) {
+    c->tyw_cache.clear();
+    c->btyw_cache.clear();
+  }
   return ok();
 }
 
