@@ -1402,6 +1402,8 @@ vqnnf_status vqnnf_match(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap
   return read_best(c, q->W - t->t.w + 1, best_xy, best_score);
 }
 
+}  // extern "C"
+
 namespace {
 
 // Pairs that share one query map (same pointer, layout and scales).
@@ -1631,6 +1633,8 @@ vqnnf_status plan_batch_score(vqnnf_ctx* c, std::vector<ScoreBatchItem> items, i
 }
 
 }  // namespace
+
+extern "C" {
 
 vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* const* t,
                                  const vqnnf_fmap* const* q, int32_t prec, float* const* heatmaps,
