@@ -20,6 +20,7 @@
 namespace vqnnf {
 
 constexpr int kMultiKB = 8;   // codeword blocks per pass
+static_assert(kWPB * 4 * 16 == kMultiTilePx, "tile of the fused launch");
 
 template <int NB, int QT>
 __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) {
@@ -39,11 +40,19 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n = lane & 15, g = lane >> 4;
   const int ngr = p.n_groups;
-  const int nsteps = p.n_pass * ngr;               // steps per tile
   constexpr int TILE = kWPB * NB * 16;
-  if ((int64_t)blockIdx.x >= p.n_tiles) return;
+  // a contiguous run of the launch's tiles per block
+  const int64_t lo = p.n_tiles * blockIdx.x / gridDim.x;
+  const int64_t hi = p.n_tiles * (blockIdx.x + 1) / gridDim.x;
+  if (lo >= hi) return;
 
-  const __amdgpu_buffer_rsrc_t cb_rs = raw_rsrc(p.frag);
+  // the map being processed (uniform per block)
+  const char* mq = nullptr;
+  int64_t mstride = 0, mpix = 0, mtiles = 0;
+  __amdgpu_buffer_rsrc_t cb_rs;
+  const MultiPass* mpasses = nullptr;
+  const MultiOut* mouts = nullptr;
+  int npass = 0;
   auto dma_cb = [&](int gs, uint4* stage) {   // global group index gs
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
@@ -53,17 +62,19 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
     }
   };
   uint32_t qoff[NB];
-  auto set_tile = [&](int64_t tl) {
-    const int64_t t = tl < p.n_tiles ? tl : (int64_t)blockIdx.x;
+  // tile tl of the map; past the block's run it stands for tile `cur` (a
+  // request that is never used but reads valid memory)
+  auto set_tile = [&](int64_t tl, int64_t end, int64_t cur) {
+    const int64_t t = tl < end ? tl : cur;
     const int64_t first = t * TILE;
-    const int64_t lim = p.n_pix - 1 - first;
+    const int64_t lim = mpix - 1 - first;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       int64_t px = (int64_t)wave * NB * 16 + 16 * nb + n;
       px = px < lim ? px : lim;
-      qoff[nb] = (uint32_t)(px * p.stride * EB) + (uint32_t)(NEL * g * EB);
+      qoff[nb] = (uint32_t)(px * mstride * EB) + (uint32_t)(NEL * g * EB);
     }
-    return (const char*)p.q + first * p.stride * EB;
+    return mq + first * mstride * EB;
   };
   uint32_t qa[NB][QW], qb[NB][QW];
   auto load_q = [&](const char* tb, int gi, uint32_t (&dst)[NB][QW]) {
@@ -135,7 +146,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
   auto finish_sb = [&](auto sb_tag, int64_t tile, int pass) {
     constexpr int SB = decltype(sb_tag)::value;
     constexpr int MW = (SB + 1) / 2;               // candidate mask words per template
-    const MultiPass ps = p.passes[pass];
+    const MultiPass ps = mpasses[pass];
 #pragma unroll
     for (int mb = 0; mb < KB; ++mb) {
       const f32x4_t c0 = *(const f32x4_t*)(cn_s + (pass * KB + mb) * 16 + 4 * g);
@@ -151,11 +162,11 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
       q2 += __shfl_xor(q2, 32);
       const float nq = sqrtf(q2 * (1.0f + (float)(p.D + 8) * 0x1.0p-23f)) * (1.0f + 0x1.0p-20f);
       const int64_t pix = tile * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
-      const bool owner = (g == 0) && (pix < p.n_pix);
+      const bool owner = (g == 0) && (pix < mpix);
 #pragma unroll
       for (int sg = 0; sg < KB / SB; ++sg) {
         if (sg >= ps.n_seg) break;
-        const MultiOut o = p.outs[ps.tmpl0 + sg];
+        const MultiOut o = mouts[ps.tmpl0 + sg];
         float v1 = 3.4e38f, v2 = 3.4e38f;
         int j1 = 0;
 #pragma unroll
@@ -210,59 +221,79 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
     }
   };
   auto finish = [&](int64_t tile, int pass) {
-    const int sb = p.passes[pass].sb;
+    const int sb = mpasses[pass].sb;
     if (sb == 8) finish_sb(std::integral_constant<int, 8>{}, tile, pass);
     else if (sb == 4) finish_sb(std::integral_constant<int, 4>{}, tile, pass);
     else if (sb == 2) finish_sb(std::integral_constant<int, 2>{}, tile, pass);
     else finish_sb(std::integral_constant<int, 1>{}, tile, pass);
   };
 
-  for (int i = threadIdx.x; i < p.n_pass * 16 * KB; i += NT) cn_s[i] = p.cnorm[i];
-  const char* tb = set_tile(blockIdx.x);
-  dma_cb(0, st0);
-  load_q(tb, 0, qa);
-  load_q(tb, 1, qb);
-  wait_vm<0>();
-  // groups per pass are even, so even steps use st0 and qa, odd steps st1 and qb
-  for (int64_t tile = blockIdx.x; tile < p.n_tiles; tile += gridDim.x) {
-    const char* tb_next = tb;
-    for (int pass = 0; pass < p.n_pass; ++pass) {
-      reset();
-      for (int gi = 0; gi < ngr; gi += 2) {
-        const int gs = pass * ngr + gi;            // global group of the even step
-        const bool last_g = gi + 2 == ngr;         // last pair of the pass
-        const bool last = last_g && pass + 1 == p.n_pass;
-        {
-          wait_vm<QN>();
-          __syncthreads();
-          dma_cb(gs + 1, st1);
-          __builtin_amdgcn_sched_barrier(0);  // the copy stays ahead of later loads
-          compute(st0, qa);
-          if (last) tb_next = set_tile(tile + gridDim.x);
-          load_q(last ? tb_next : tb, last_g ? 0 : gi + 2, qa);
-        }
-        {
-          wait_vm<QN>();
-          __syncthreads();
-          dma_cb(gs + 2 == nsteps ? 0 : gs + 2, st0);
-          __builtin_amdgcn_sched_barrier(0);
-          compute(st1, qb);
-          if (last_g) finish(tile, pass);
-          load_q(last ? tb_next : tb, last_g ? 1 : gi + 3, qb);
+  // the map of the run's first tile
+  int m = 0;
+  for (int a = 0, b = p.n_maps - 1; a < b;) {
+    const int c = (a + b + 1) / 2;
+    if (p.maps[c].tile0 <= lo) a = c, m = c; else b = c - 1;
+  }
+  for (int64_t t0 = lo; t0 < hi; ++m) {
+    const MultiMap& mm = p.maps[m];
+    mq = (const char*)mm.q;
+    mstride = mm.stride;
+    mpix = mm.n_pix;
+    mtiles = multi_tiles(mpix);
+    cb_rs = raw_rsrc(mm.frag);
+    mpasses = mm.passes;
+    mouts = mm.outs;
+    npass = mm.n_pass;
+    const int64_t first = t0 - mm.tile0, end = min(hi - mm.tile0, mtiles);
+    const int nsteps = npass * ngr;                 // steps per tile
+    // norms of the map's passes (the previous map's epilogues are done)
+    __syncthreads();
+    for (int i = threadIdx.x; i < npass * 16 * KB; i += NT) cn_s[i] = mm.cnorm[i];
+    const char* tb = set_tile(first, end, first);
+    dma_cb(0, st0);
+    load_q(tb, 0, qa);
+    load_q(tb, 1, qb);
+    wait_vm<0>();
+    // groups per pass are even, so even steps use st0 and qa, odd steps st1 and qb
+    for (int64_t tile = first; tile < end; ++tile) {
+      const char* tb_next = tb;
+      for (int pass = 0; pass < npass; ++pass) {
+        reset();
+        for (int gi = 0; gi < ngr; gi += 2) {
+          const int gs = pass * ngr + gi;            // global group of the even step
+          const bool last_g = gi + 2 == ngr;         // last pair of the pass
+          const bool last = last_g && pass + 1 == npass;
+          {
+            wait_vm<QN>();
+            __syncthreads();
+            dma_cb(gs + 1, st1);
+            __builtin_amdgcn_sched_barrier(0);  // the copy stays ahead of later loads
+            compute(st0, qa);
+            if (last) tb_next = set_tile(tile + 1, end, tile);
+            load_q(last ? tb_next : tb, last_g ? 0 : gi + 2, qa);
+          }
+          {
+            wait_vm<QN>();
+            __syncthreads();
+            dma_cb(gs + 2 == nsteps ? 0 : gs + 2, st0);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(st1, qb);
+            if (last_g) finish(tile, pass);
+            load_q(last ? tb_next : tb, last_g ? 1 : gi + 3, qb);
+          }
         }
       }
+      tb = tb_next;
     }
-    tb = tb_next;
+    // nothing of this map in flight when the next one starts
+    wait_vm<0>();
+    t0 = mm.tile0 + end;
   }
-  wait_vm<0>();
 }
 
 hipError_t launch_assign_multi(const MultiArgs& a, hipStream_t s, int n_cu) {
-  MultiParams kp = a.kp;
-  const int NB = 4;
-  const int64_t tile_px = (int64_t)kWPB * NB * 16;
-  kp.n_tiles = (kp.n_pix + tile_px - 1) / tile_px;
-  if (kp.n_pass < 1 || kp.n_pass > kMultiMaxPass || kp.n_groups % 2 != 0) return hipErrorInvalidValue;
+  const MultiParams& kp = a.kp;
+  if (kp.n_maps < 1 || kp.n_tiles < 1 || kp.n_groups % 2 != 0) return hipErrorInvalidValue;
   const int grid = (int)std::min<int64_t>(kp.n_tiles, (int64_t)n_cu);
   timing_begin(K_ASSIGN_MULTI);
   if (a.fp8)

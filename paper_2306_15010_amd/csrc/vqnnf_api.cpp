@@ -1530,20 +1530,47 @@ vqnnf_status build_multi_plan(vqnnf_ctx* c, vqnnf_ctx::MultiPlan& mp, const std:
   return ok();
 }
 
-// The fused multi-template assignment of one map group (labels, worklists).
-hipError_t enqueue_multi_assign(vqnnf_ctx* c, const vqnnf_ctx::MultiPlan& mp, const vqnnf_fmap* q0) {
+// Fused assignments of the batch: one launch per (storage, D) class covering
+// every map group of that class, each map's pass plan in a device table.
+struct MultiLaunch {
+  bool fp8;
+  int D, n_groups;
+  std::vector<MultiMap> maps;
+  int64_t n_tiles = 0;
+  size_t tab_off = 0;                  // the map table's offset in the batch tables
+};
+
+void add_multi_map(std::vector<MultiLaunch>& ls, const vqnnf_ctx::MultiPlan& mp, const vqnnf_fmap* q0) {
+  const bool fp8 = q0->dtype == VQNNF_FP8_E4M3;
+  MultiLaunch* l = nullptr;
+  for (MultiLaunch& x : ls)
+    if (x.fp8 == fp8 && x.D == q0->D && x.n_groups == mp.n_groups) l = &x;
+  if (!l) {
+    ls.push_back(MultiLaunch{fp8, q0->D, mp.n_groups, {}, 0, 0});
+    l = &ls.back();
+  }
+  MultiMap m{};
+  m.q = q0->data;
+  m.stride = map_stride(q0);
+  m.n_pix = (int64_t)q0->H * q0->W;
+  m.frag = (const uint4*)mp.frag.p;
+  m.cnorm = (const float*)mp.cnorm.p;
+  m.passes = (const MultiPass*)mp.passes.p;
+  m.outs = (const MultiOut*)mp.outs.p;
+  m.n_pass = mp.n_pass;
+  m.tile0 = l->n_tiles;
+  l->n_tiles += multi_tiles(m.n_pix);
+  l->maps.push_back(m);
+}
+
+hipError_t enqueue_multi_launch(vqnnf_ctx* c, const MultiLaunch& l, const uint8_t* d_tab) {
   MultiArgs ma{};
-  ma.kp.q = q0->data;
-  ma.kp.stride = map_stride(q0);
-  ma.kp.n_pix = (int64_t)q0->H * q0->W;
-  ma.kp.D = q0->D;
-  ma.kp.frag = (const uint4*)mp.frag.p;
-  ma.kp.cnorm = (const float*)mp.cnorm.p;
-  ma.kp.n_groups = mp.n_groups;
-  ma.kp.n_pass = mp.n_pass;
-  ma.kp.passes = (const MultiPass*)mp.passes.p;
-  ma.kp.outs = (const MultiOut*)mp.outs.p;
-  ma.fp8 = q0->dtype == VQNNF_FP8_E4M3;
+  ma.kp.maps = (const MultiMap*)(d_tab + l.tab_off);
+  ma.kp.n_maps = (int)l.maps.size();
+  ma.kp.D = l.D;
+  ma.kp.n_groups = l.n_groups;
+  ma.kp.n_tiles = l.n_tiles;
+  ma.fp8 = l.fp8;
   return launch_assign_multi(ma, c->stream, c->n_cu);
 }
 
@@ -1708,6 +1735,7 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
   if (c->mplans.size() < groups.size()) c->mplans.resize(groups.size());
   unsigned long long* keys = (unsigned long long*)c->keys.p;
   FusedWork fw;
+  std::vector<MultiLaunch> mls;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     if (!fused[gi]) continue;
     const vqnnf_fmap* q0 = q[groups[gi][0]];
@@ -1715,6 +1743,7 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
                               slot0[gi])))
       return s;
     fused_work(c, c->mplans[gi], groups[gi], t, q, sets, heatmaps, keys, lab0[gi], slot0[gi], fw);
+    add_multi_map(mls, c->mplans[gi], q0);
   }
   // batched re-score and score tables of the fused pairs
   RescoreBatchPlan rplan;
@@ -1734,6 +1763,11 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     if (!fw.rescore.empty()) {
       plan_rescore_batch(fw.rescore, &rplan);
       blob = rplan.blob;
+    }
+    for (MultiLaunch& l : mls) {
+      l.tab_off = (blob.size() + 255) / 256 * 256;
+      blob.resize(l.tab_off + l.maps.size() * sizeof(MultiMap));
+      std::memcpy(blob.data() + l.tab_off, l.maps.data(), l.maps.size() * sizeof(MultiMap));
     }
     if (!fw.score.empty()) {
       std::vector<ScoreBatchItem> sized = fw.score;   // partial sizes do not depend on the tile height
@@ -1812,17 +1846,15 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
   auto enqueue_all = [&]() -> vqnnf_status {
     HIP_TRY(launch_fill_u32((uint32_t*)keys, 0u, 2 * (int64_t)n, c->stream));
     if (nslot) HIP_TRY(launch_fill_u32((uint32_t*)c->m_count.p, 0u, nslot, c->stream));
+    const uint8_t* d_tab = (const uint8_t*)c->b_tab.p;
+    for (const MultiLaunch& l : mls) HIP_TRY(enqueue_multi_launch(c, l, d_tab));
     for (size_t gi = 0; gi < groups.size(); ++gi) {
-      if (fused[gi]) {
-        HIP_TRY(enqueue_multi_assign(c, c->mplans[gi], q[groups[gi][0]]));
-        continue;
-      }
+      if (fused[gi]) continue;
       for (int i : groups[gi]) {
         vqnnf_status st = enqueue_pair(c, t[i], q[i], prec, heatmaps[i], keys + i, false);
         if (st) return st;
       }
     }
-    const uint8_t* d_tab = (const uint8_t*)c->b_tab.p;
     if (!rplan.launches.empty()) HIP_TRY(launch_rescore_batch(rplan, d_tab, c->n_cu, c->stream));
     if (!splan.launches.empty()) {
       if (tune && !c->capturing) {

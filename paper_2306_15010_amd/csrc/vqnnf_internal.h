@@ -177,22 +177,33 @@ struct MultiOut {                    // per template: outputs and error bound
   uint32_t* wl_mask;                 // [n_pix][(sb+1)/2]
   float a0, a1, a2, pad;
 };
-struct MultiParams {
+// One query map of a fused launch: its templates' pass plan and outputs.
+struct MultiMap {
   const void* q;
   int64_t stride;
   int64_t n_pix;
-  int D;
   const uint4* frag;                 // [n_pass][n_groups][2][8][64] BF16 fragment pairs
   const float* cnorm;                // [n_pass][128] ||c||^2 (pad 3e38)
-  int n_groups, n_pass;
-  int64_t n_tiles;
   const MultiPass* passes;
   const MultiOut* outs;
+  int n_pass, pad;
+  int64_t tile0;                     // first tile of the map in the launch's tile list
+};
+struct MultiParams {
+  const MultiMap* maps;              // device table, tile0 ascending
+  int n_maps;
+  int D, n_groups;                   // shared by every map of the launch
+  int64_t n_tiles;                   // all maps
 };
 struct MultiArgs {
   MultiParams kp;
   bool fp8;
 };
+// Pixels per tile of the fused launch and the tiles of one map.
+constexpr int kMultiTilePx = 512;
+__host__ __device__ inline int64_t multi_tiles(int64_t n_pix) {
+  return (n_pix + kMultiTilePx - 1) / kMultiTilePx;
+}
 hipError_t launch_assign_multi(const MultiArgs& a, hipStream_t s, int n_cu);
 
 hipError_t launch_assign_plain(const AssignArgs& a, hipStream_t s, int n_cu);

@@ -228,3 +228,24 @@ def test_largest_template(ctx):
         assert torch.equal(heats[i], refs[i]), f"pair {i}"
         assert out[i] == bests[i]
         check_oracle(wl, tpls[i], *meta[i], heats[i])
+
+
+def test_batched_many_maps_one_launch(ctx):
+    """Maps of uneven size (one smaller than a tile row of the chip) and two
+    feature sizes: one fused assignment launch per feature size, each block
+    walking a contiguous run of tiles that crosses map boundaries."""
+    wa = synth.make_multi_map(71, 4, (24, 200), 64, 24, 0.3, "bf16", 3, (8, 20), 16, 2)
+    wb = synth.make_multi_map(73, 3, (40, 160), 128, 24, 0.3, "bf16", 2, (10, 24), 32, 3)
+    pa = make_pairs(ctx, wa)
+    pb = make_pairs(ctx, wb)
+    tpls, fms, heats = pa[0] + pb[0], pa[1] + pb[1], pa[2] + pb[2]
+    log("maps:", [(m.H, m.W, m.D) for m in wa.maps + wb.maps])
+    P = B.VQNNF_PREC_BF16_REFINED
+    out = B.vqnnf_match_batched(ctx, tpls, fms, P, heats)
+    refs, bests = per_pair(ctx, tpls, fms, heats, P)
+    for i in range(len(tpls)):
+        assert torch.equal(heats[i], refs[i]), f"pair {i}"
+        assert out[i] == bests[i]
+    check_oracle(wa, tpls[0], *pa[3][0], heats[0])
+    n_a = len(pa[0])
+    check_oracle(wb, tpls[n_a + 1], *pb[3][1], heats[n_a + 1])
