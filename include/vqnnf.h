@@ -287,11 +287,12 @@ vqnnf_status vqnnf_match(vqnnf_ctx* ctx, const vqnnf_template* t, const vqnnf_fm
  * (host, 2*n_pairs) and best_score (host, n_pairs) receive each pair's
  * localisation (Sec. 4); both NULL skips the synchronisation.  Every pair
  * is validated before anything is enqueued (EINVAL names the pair).
- * Launch structure (BF16-refined, BF16/FP8 maps): per query map one fused
- * assignment of all its templates, then for the whole batch one FP64
- * re-score launch, one score launch per grid size and one combine launch
- * per stored-sum count, each reading its pairs' arguments from a device
- * table; other pairs run the single-pair path in turn.  Results equal
+ * Launch structure (BF16-refined, BF16/FP8 maps): one fused assignment
+ * launch per (storage, D) class that assigns every map of the class against
+ * all of its templates, then for the whole batch one FP64 re-score launch,
+ * one score launch per grid size and one combine launch per stored-sum
+ * count, each reading its pairs' arguments from a device table; other pairs
+ * run the single-pair path in turn.  Results equal
  * vqnnf_match's for every pair, bit for bit.  With
  * graph mode on (vqnnf_ctx_set_graph) the batch's kernels are captured into
  * one HIP graph and later calls with the same arguments (handles, pointers,
