@@ -27,7 +27,11 @@ METRIC = "query px/s for VQ-NNF assign+filter+score, BF16-refined vs FP32, label
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12    # 32-bit integer lane-ops per second (39.3 T)
+# 32-bit vector lane-ops per second: 256 CUs x 128 lanes per clock x 2.4 GHz =
+# 78.6 T, the FP32 vector peak (157.3 TFLOP/s) with an FMA as one lane-op.
+# (A low-dimensional assignment kernel of plain FP32 subtract/FMA measured
+# 39 T lane-ops/s, above what 64 lanes per clock per CU would allow.)
+ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 
 
 def log(*a):

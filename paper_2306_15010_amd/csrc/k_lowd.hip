@@ -3,7 +3,7 @@
 // built on the fly from an RGB image (Sec. 5.2 "Feature Extraction": the 3x3
 // neighbourhood of RGB values, D = 27, edges replicated).
 //
-// One thread per pixel: its features in registers, the codebook read through
+// Two pixels per thread: their features in registers, the codebook read through
 // scalar loads (the same value for every lane: an SGPR operand of the FMA), the
 // direct distances d~_j = sum_t (q_t - c_jt)^2 in FP32 (subtract, then FMA).
 // Their error is relative: |d~_j - d_j| <= e32 * d_j with
@@ -69,11 +69,13 @@ __device__ __forceinline__ void load_features(const LowParams& p, int64_t px, fl
   }
 }
 
+// DT > 0: the feature size as a compile-time constant (no per-element test).
+template <int DT>
 __device__ __forceinline__ float dist(const float (&qv)[kLowMaxD], const float* __restrict__ c, int D) {
   float d = 0.f;
 #pragma unroll
-  for (int t = 0; t < kLowMaxD; ++t) {
-    if (t < D) {
+  for (int t = 0; t < (DT > 0 ? DT : kLowMaxD); ++t) {
+    if (DT > 0 || t < D) {
       const float diff = qv[t] - c[t];
       d = __builtin_fmaf(diff, diff, d);
     }
@@ -81,46 +83,77 @@ __device__ __forceinline__ float dist(const float (&qv)[kLowMaxD], const float* 
   return d;
 }
 
-template <int QT>
+// Two pixels per thread (px and px + 256 of a block's 512): every codeword
+// value read through a scalar load serves both.
+template <int QT, int DT>
 __global__ __launch_bounds__(256) void assign_lowd_kernel(LowParams p, const float* __restrict__ cb) {
-  const int64_t px = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const bool valid = px < p.n_pix;
-  float qv[kLowMaxD];
-  load_features<QT>(p, valid ? px : p.n_pix - 1, qv);
-  float d1 = __builtin_inff(), d2 = __builtin_inff();
-  int j1 = 0;
+  constexpr int PPT = 2;
+  float qv[PPT][kLowMaxD];
+  int64_t px[PPT];
+  bool valid[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    px[u] = (int64_t)blockIdx.x * (256 * PPT) + 256 * u + threadIdx.x;
+    valid[u] = px[u] < p.n_pix;
+    load_features<QT>(p, valid[u] ? px[u] : p.n_pix - 1, qv[u]);
+  }
+  const int D = DT > 0 ? DT : p.D;
+  float d1[PPT], d2[PPT];
+  int j1[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    d1[u] = __builtin_inff();
+    d2[u] = __builtin_inff();
+    j1[u] = 0;
+  }
   for (int j = 0; j < p.k; ++j) {
-    const float d = dist(qv, cb + j * p.D, p.D);
-    if (d < d1) {
-      d2 = d1;
-      d1 = d;
-      j1 = j;
-    } else if (d < d2) {
-      d2 = d;
+    const float* c = cb + j * D;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      // first index on ties: equal values never displace the best
+      const float d = dist<DT>(qv[u], c, D);
+      const bool lt1 = d < d1[u], lt2 = d < d2[u];
+      d2[u] = lt1 ? d1[u] : (lt2 ? d : d2[u]);
+      j1[u] = lt1 ? j : j1[u];
+      d1[u] = lt1 ? d : d1[u];
     }
   }
-  if (valid) p.labels[px] = (uint8_t)j1;
-  if (!p.refined) return;
-  const bool flag = valid && p.k > 1 && (d2 - d1 <= p.tau * (d1 + d2) + p.floor);
-  const uint64_t bal = __ballot(flag);
-  if (bal == 0) return;
   const int lane = threadIdx.x & 63;
-  uint32_t base = 0;
-  const int leader = __builtin_amdgcn_readfirstlane(__ffsll((long long)bal) - 1);
-  if (lane == leader) base = atomicAdd(p.wl_count, (uint32_t)__popcll(bal));
-  base = __shfl(base, leader);
-  if (!flag) return;
-  const uint32_t pos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-  p.wl_pix[pos] = (uint32_t)px;
-  for (int w = 0; w < p.mask_words; ++w) {
-    uint32_t bits = 0u;
-    for (int b = 0; b < 32; ++b) {
-      const int j = 32 * w + b;
-      if (j >= p.k) break;
-      const float d = dist(qv, cb + j * p.D, p.D);
-      if (d - d1 <= p.tau * (d1 + d) + p.floor) bits |= 1u << b;
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    if (valid[u]) p.labels[px[u]] = (uint8_t)j1[u];
+    if (!p.refined) continue;
+    const bool flag = valid[u] && p.k > 1 && (d2[u] - d1[u] <= p.tau * (d1[u] + d2[u]) + p.floor);
+    const uint64_t bal = __ballot(flag);
+    if (bal == 0) continue;
+    uint32_t base = 0;
+    const int leader = __builtin_amdgcn_readfirstlane(__ffsll((long long)bal) - 1);
+    if (lane == leader) base = atomicAdd(p.wl_count, (uint32_t)__popcll(bal));
+    base = __shfl(base, leader);
+    if (!flag) continue;
+    const uint32_t pos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+    p.wl_pix[pos] = (uint32_t)px[u];
+    for (int w = 0; w < p.mask_words; ++w) {
+      uint32_t bits = 0u;
+      for (int b = 0; b < 32; ++b) {
+        const int j = 32 * w + b;
+        if (j >= p.k) break;
+        const float d = dist<DT>(qv[u], cb + j * D, D);
+        if (d - d1[u] <= p.tau * (d1[u] + d) + p.floor) bits |= 1u << b;
+      }
+      p.wl_mask[(int64_t)pos * p.mask_words + w] = bits;
     }
-    p.wl_mask[(int64_t)pos * p.mask_words + w] = bits;
+  }
+}
+
+template <int QT>
+void go_lowd(const LowParams& p, const float* cb, int D, hipStream_t s) {
+  const dim3 grid((unsigned)((p.n_pix + 511) / 512));
+  switch (D) {
+    case 9: hipLaunchKernelGGL((assign_lowd_kernel<QT, 9>), grid, dim3(256), 0, s, p, cb); break;
+    case 18: hipLaunchKernelGGL((assign_lowd_kernel<QT, 18>), grid, dim3(256), 0, s, p, cb); break;
+    case 27: hipLaunchKernelGGL((assign_lowd_kernel<QT, 27>), grid, dim3(256), 0, s, p, cb); break;
+    default: hipLaunchKernelGGL((assign_lowd_kernel<QT, 0>), grid, dim3(256), 0, s, p, cb); break;
   }
 }
 
@@ -153,12 +186,11 @@ hipError_t launch_assign_lowd(const AssignArgs& a, bool refined, hipStream_t s) 
   const double e64 = (1.0 + u64) * (1.0 + u64) * (1.0 + g64) - 1.0;
   p.tau = (float)((e32 + e64) * (1.0 + 0x1.0p-10) * (1.0 + 0x1.0p-20));
   p.floor = (float)(4.0 * (D + 2) * 0x1.0p-126);
-  const dim3 grid((unsigned)((a.n_pix + 255) / 256));
   timing_begin(K_ASSIGN_LOWD);
   const float* cb = t.d_codebook;
-  if (a.dtype == VQNNF_RGB8) hipLaunchKernelGGL(assign_lowd_kernel<kQRGB8>, grid, dim3(256), 0, s, p, cb);
-  else if (a.dtype == VQNNF_F32) hipLaunchKernelGGL(assign_lowd_kernel<kQF32>, grid, dim3(256), 0, s, p, cb);
-  else hipLaunchKernelGGL(assign_lowd_kernel<kQBF16>, grid, dim3(256), 0, s, p, cb);
+  if (a.dtype == VQNNF_RGB8) go_lowd<kQRGB8>(p, cb, 27, s);
+  else if (a.dtype == VQNNF_F32) go_lowd<kQF32>(p, cb, a.D, s);
+  else go_lowd<kQBF16>(p, cb, a.D, s);
   timing_end(K_ASSIGN_LOWD);
   return hipGetLastError();
 }
