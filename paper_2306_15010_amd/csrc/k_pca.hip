@@ -153,7 +153,7 @@ hipError_t go_proj(const ProjParams& p, const float* bt, const float* mean, cons
 // out = sum_t q_t b_t - sum_t m_t b_t, with the second sum from the host in
 // FP64.  The basis fragments of all groups sit in LDS (the block is
 // persistent); a wave takes 64 pixels (4 MFMA column blocks), and each lane
-// requests its pixels' next group two steps ahead.
+// requests its pixels' groups four steps ahead.
 struct PMParams {
   const uint16_t* q;
   int64_t stride, n_pix, n_tiles;
@@ -201,14 +201,21 @@ __global__ __launch_bounds__(512) void pca_mfma_kernel(PMParams p) {
           for (int nb = 0; nb < 4; ++nb) acc[rb][nb] = mfma_bf16(a, v[nb], acc[rb][nb]);
         }
     };
-    uint4 qa[4], qb[4];
+    // four steps of query elements in flight
+    uint4 qa[4], qb[4], qc[4], qd[4];
     load(0, qa);
     load(1, qb);
-    for (int st = 0; st < p.steps; st += 2) {
+    load(2, qc);
+    load(3, qd);
+    for (int st = 0; st < p.steps; st += 4) {
       compute(st, qa);
-      load(st + 2, qa);
+      load(st + 4, qa);
       if (st + 1 < p.steps) compute(st + 1, qb);
-      load(st + 3, qb);
+      load(st + 5, qb);
+      if (st + 2 < p.steps) compute(st + 2, qc);
+      load(st + 6, qc);
+      if (st + 3 < p.steps) compute(st + 3, qd);
+      load(st + 7, qd);
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
