@@ -1810,36 +1810,51 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     vqnnf_status st;
     for (size_t ci = 0; ci < cand.size(); ++ci)
       if ((st = plan_batch_score(c, fw.score, cand[ci], pls[ci], cblob, &offs[ci]))) return st;
-    Buffer tmp;
-    if ((st = ensure(c, tmp, cblob.size(), "autotuning argument tables"))) return st;
-    HIP_TRY(hipMemcpyAsync(tmp.p, cblob.data(), cblob.size(), hipMemcpyHostToDevice, c->stream));
-    set_timing_hook(nullptr);
-    std::vector<hipEvent_t> ev(2 * cand.size());
-    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
-    hipError_t e = hipSuccess;
-    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
-      for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
-        if (rep == 1) e = hipEventRecord(ev[2 * ci], c->stream);
-        if (e == hipSuccess) e = launch_score_batch(pls[ci], (const uint8_t*)tmp.p + offs[ci], c->stream);
-        if (rep == 1 && e == hipSuccess) e = hipEventRecord(ev[2 * ci + 1], c->stream);
+    // temporary tables, events and the paused timing hook are released on
+    // every path out of here
+    struct Scratch {
+      vqnnf_ctx* c;
+      Buffer tmp;
+      std::vector<hipEvent_t> ev;
+      ~Scratch() {
+        (void)hipStreamSynchronize(c->stream);
+        for (auto e : ev) (void)hipEventDestroy(e);
+        if (tmp.p) {
+          (void)hipFree(tmp.p);
+          c->used -= tmp.bytes;
+        }
+        if (c->timing) {
+          TimingHook h{hook_begin, hook_end, c};
+          set_timing_hook(&h);
+        }
       }
-    if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+    } sc{c, {}, {}};
+    set_timing_hook(nullptr);
+    if ((st = ensure(c, sc.tmp, cblob.size(), "autotuning argument tables"))) return st;
+    HIP_TRY(hipMemcpyAsync(sc.tmp.p, cblob.data(), cblob.size(), hipMemcpyHostToDevice, c->stream));
+    for (size_t i = 0; i < 2 * cand.size(); ++i) {
+      hipEvent_t e = nullptr;
+      HIP_TRY(hipEventCreate(&e));
+      sc.ev.push_back(e);
+    }
+    const std::vector<hipEvent_t>& ev = sc.ev;
+    for (int rep = 0; rep < 2; ++rep)
+      for (size_t ci = 0; ci < cand.size(); ++ci) {
+        if (rep == 1) HIP_TRY(hipEventRecord(ev[2 * ci], c->stream));
+        HIP_TRY(launch_score_batch(pls[ci], (const uint8_t*)sc.tmp.p + offs[ci], c->stream));
+        if (rep == 1) HIP_TRY(hipEventRecord(ev[2 * ci + 1], c->stream));
+      }
+    HIP_TRY(hipEventSynchronize(ev.back()));
     float best_ms = 1e30f;
     int best = tyw;
-    for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
+    for (size_t ci = 0; ci < cand.size(); ++ci) {
       float ms = 0.f;
-      e = hipEventElapsedTime(&ms, ev[2 * ci], ev[2 * ci + 1]);
-      if (e == hipSuccess && ms < best_ms) { best_ms = ms; best = cand[ci]; }
+      HIP_TRY(hipEventElapsedTime(&ms, ev[2 * ci], ev[2 * ci + 1]));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cand[ci];
+      }
     }
-    for (auto& ee : ev) hipEventDestroy(ee);
-    hipStreamSynchronize(c->stream);
-    hipFree(tmp.p);
-    c->used -= tmp.bytes;
-    if (c->timing) {
-      TimingHook h{hook_begin, hook_end, c};
-      set_timing_hook(&h);
-    }
-    if (e != hipSuccess) return fail(VQNNF_EHIP, "batched score autotuning: %s", hipGetErrorString(e));
     c->btyw_cache[bkey] = best;
     return ok();   // the last candidate's run already produced the result
   };
