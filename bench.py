@@ -278,7 +278,8 @@ def batched_bench(args, ctx, B, synth, torch):
     sequential vqnnf_match calls."""
     log(f"generating workload {args.workload} (map sides / {args.scale_down})")
     t0 = time.perf_counter()
-    wl = synth.make_config(args.workload, scale_down=args.scale_down)
+    wl = synth.make_config(args.workload, scale_down=args.scale_down,
+                           progress=lambda i, n: log(f"  map {i} of {n} made"))
     log(f"  {time.perf_counter() - t0:.1f} s")
     tpls, fms, heats, devs = [], [], [], []
     flat = [t for row in wl.templates for t in row]
@@ -443,7 +444,10 @@ def main():
         copy_probe()
         return
     if args.workload in ("c4", "c5"):
-        batched_bench(args, B.Context(stream=torch.cuda.current_stream()), B, synth, torch)
+        # the full batches need more scratch than the default cap (re-score
+        # worklists and partial sums of every pair at once)
+        batched_bench(args, B.Context(stream=torch.cuda.current_stream(), scratch_cap=64 << 30), B, synth,
+                      torch)
         return
     log(f"generating workload {args.workload}")
     wl = synth.make_config(args.workload)

@@ -262,7 +262,7 @@ def make_single(name: str, seed: int, H: int, W: int, D: int, M: int, sigma: flo
 CONFIGS = ("c1", "c2", "c3", "c4", "c5")
 
 
-def make_config(name: str, seed: Optional[int] = None, scale_down: int = 1) -> Workload:
+def make_config(name: str, seed: Optional[int] = None, scale_down: int = 1, progress=None) -> Workload:
     """Workloads shaped like the five benchmark configurations.
 
     c1: 64x64, D=27, FP32, 32 components, 16x16 template, k=8, full + 2x2 grid.
@@ -275,7 +275,8 @@ def make_config(name: str, seed: Optional[int] = None, scale_down: int = 1) -> W
     c5: 32 maps with sides U{256,320,...,2048}, D=256, FP8 E4M3FN with
         per-channel scales, 128 components; 4 templates per map, sides
         U{32..128}, k=64, full + 3x3 grid.
-    `scale_down` divides map sides (tests use it for reduced-size variants).
+    `scale_down` divides map sides (tests use it for reduced-size variants);
+    `progress(done, total)`, if given, is called as the maps of c5 are made.
     """
     idx = CONFIGS.index(name)
     if seed is None:
@@ -294,7 +295,7 @@ def make_config(name: str, seed: Optional[int] = None, scale_down: int = 1) -> W
                                    (24, 160), (16, 32, 64, 128), 2)
     if name == "c5":
         return make_multi_map(seed, 32, (256 // s, 2048 // s), 256, 128, 0.3, "fp8", 4,
-                              (32, 128), 64, 3)
+                              (32, 128), 64, 3, progress=progress)
     raise ValueError(name)
 
 
@@ -340,7 +341,7 @@ def _multi_map_one(job):
 
 
 def make_multi_map(seed, n_maps, side_rng, D, M, sigma, dtype, t_per_map, tside_rng, k, grid,
-                   noise=0.1) -> Workload:
+                   noise=0.1, progress=None) -> Workload:
     r_means, r_sizes, *r_maps = _streams(seed, 2 + n_maps)
     means = r_means.standard_normal(size=(M, D))
     lo, hi = side_rng
@@ -359,9 +360,17 @@ def make_multi_map(seed, n_maps, side_rng, D, M, sigma, dtype, t_per_map, tside_
         import os
         n = max(1, min(16, len(os.sched_getaffinity(0)), n_maps))
         with mp.get_context("spawn").Pool(n) as pool:
-            done = pool.map(_multi_map_one, jobs, chunksize=1)
+            done = []
+            for d in pool.imap(_multi_map_one, jobs, chunksize=1):
+                done.append(d)
+                if progress:
+                    progress(len(done), n_maps)
     else:
-        done = [_multi_map_one(j) for j in jobs]
+        done = []
+        for j in jobs:
+            done.append(_multi_map_one(j))
+            if progress:
+                progress(len(done), n_maps)
     maps = [d[0] for d in done]
     tpls = [d[1] for d in done]
     return Workload("c5", seed, maps, tpls)
