@@ -182,13 +182,13 @@ __global__ __launch_bounds__(256) void score_bank_kernel(BankParams p, const Ban
       for (int b = 0; b < G; ++b)
 #pragma unroll
         for (int a = 0; a < G; ++a) {
+          // a zero coefficient leaves the chain unchanged (fma(0, n, r) = r for
+          // a finite count n), so every bin takes part: no branch per bin
           const float cv = cf[b * 4 + a];
-          if (cv != 0.f) {
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-              r[c][0] = __builtin_fmaf(cv, cnt[b][a][c][0], r[c][0]);
-              r[c][1] = __builtin_fmaf(cv, cnt[b][a][c][1], r[c][1]);
-            }
+          for (int c = 0; c < CPL; ++c) {
+            r[c][0] = __builtin_fmaf(cv, cnt[b][a][c][0], r[c][0]);
+            r[c][1] = __builtin_fmaf(cv, cnt[b][a][c][1], r[c][1]);
           }
         }
       const float* rt = rs + f * p.kpad;
