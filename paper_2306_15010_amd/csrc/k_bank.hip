@@ -119,8 +119,7 @@ __global__ __launch_bounds__(256) void score_bank_kernel(BankParams p, const Ban
   // Taps through a buffer resource based at the P row of the step's first
   // window: per lane one 32-bit offset per step, per tap a scalar offset
   // (every offset inside a band of h + 2 rows of P stays below 2^32).
-  auto load = [&](int s, Taps& t) {
-    const int it = s / ng, gi = s - it * ng;
+  auto load = [&](int it, int gi, Taps& t) {
     const int64_t w = win_of(it);
     const int wc = (int)(w < nwin ? w : nwin - 1);  // clamped: every tap stays inside P
     const int64_t w0 = win_of(it) - sub;
@@ -130,12 +129,13 @@ __global__ __launch_bounds__(256) void score_bank_kernel(BankParams p, const Ban
     const __amdgpu_buffer_rsrc_t rsrc = raw_rsrc(P + (int64_t)y0 * p.row);
     const uint32_t vb = ((uint32_t)(y - y0) * (uint32_t)p.row + (uint32_t)x * (uint32_t)p.pix) * 4u;
     const BankGroup& g = groups[gi];
+    const uint32_t rowb = (uint32_t)p.row * 4u, pixb = (uint32_t)p.pix * 4u;
 #pragma unroll
     for (int tb = 0; tb <= G; ++tb) {
-      const uint32_t ro = (uint32_t)g.ye[tb] * (uint32_t)p.row;
+      const uint32_t ro = (uint32_t)g.ye[tb] * rowb;
 #pragma unroll
       for (int ta = 0; ta <= G; ++ta) {
-        const uint32_t so = (ro + (uint32_t)g.xe[ta] * (uint32_t)p.pix) * 4u;
+        const uint32_t so = ro + (uint32_t)g.xe[ta] * pixb;
 #pragma unroll
         for (int c = 0; c < CPL; ++c)
 #pragma unroll
@@ -146,8 +146,7 @@ __global__ __launch_bounds__(256) void score_bank_kernel(BankParams p, const Ban
   };
   float acc = 0.f;
   unsigned long long key = 0ull;
-  auto compute = [&](int s, const Taps& t) {
-    const int it = s / ng, gi = s - it * ng;
+  auto compute = [&](int it, int gi, const Taps& t) {
     const BankGroup& g = groups[gi];
     float cnt[G][G][CPL][2];
 #pragma unroll
@@ -174,7 +173,7 @@ __global__ __launch_bounds__(256) void score_bank_kernel(BankParams p, const Ban
           }
         }
     for (int f = g.f0; f < g.f1; ++f) {
-      const float* cf = coef + f * 16;
+      const float* cf = (const float*)__builtin_assume_aligned(coef + f * 16, 64);
       float r[CPL][2];
 #pragma unroll
       for (int c = 0; c < CPL; ++c) r[c][0] = r[c][1] = 0.f;
@@ -221,20 +220,38 @@ __global__ __launch_bounds__(256) void score_bank_kernel(BankParams p, const Ban
   constexpr int LPS = (G + 1) * (G + 1) * CPL * NV;
   constexpr int WN = LPS <= 63 ? LPS : 0;
   Taps ta, tb;
+  // (window, group) cursors of steps s and s + 1, advanced without divisions
+  auto advance = [&](int& it, int& gi) {
+    if (++gi == ng) {
+      gi = 0;
+      ++it;
+    }
+  };
   if (win_of(0) - sub < nwin) {                // uniform per wave
-    load(0, ta);
+    int ci = 0, cg = 0, ni = 0, ngi = 0;
+    advance(ni, ngi);
+    load(0, 0, ta);
     for (int s = 0; s < nsteps; s += 2) {
-      load(s + 1 < nsteps ? s + 1 : s, tb);    // always issued: the count stays fixed
+      const bool h1 = s + 1 < nsteps;
+      load(h1 ? ni : ci, h1 ? ngi : cg, tb);   // always issued: the count stays fixed
       __builtin_amdgcn_sched_barrier(0);
       wait_vm<WN>();
       __builtin_amdgcn_sched_barrier(0);
-      compute(s, ta);
-      if (s + 1 < nsteps) {
-        load(s + 2 < nsteps ? s + 2 : s + 1, ta);
+      compute(ci, cg, ta);
+      if (h1) {
+        int i2 = ni, g2 = ngi;
+        advance(i2, g2);
+        const bool h2 = s + 2 < nsteps;
+        load(h2 ? i2 : ni, h2 ? g2 : ngi, ta);
         __builtin_amdgcn_sched_barrier(0);
         wait_vm<WN>();
         __builtin_amdgcn_sched_barrier(0);
-        compute(s + 1, tb);
+        compute(ni, ngi, tb);
+        ci = i2;
+        cg = g2;
+        ni = i2;
+        ngi = g2;
+        advance(ni, ngi);
       }
     }
     wait_vm<0>();
