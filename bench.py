@@ -187,7 +187,8 @@ def paper_bank_leg(ctx, B, t, fm, qm, steps, torch):
                                       "unit": "Tops/s", "frac": ach / ALU_PEAK_TOPS,
                                       "ops_per_window": bank_ops_per_window(bank, t.k)}
     if "integral_main" in avg:
-        pbytes = (qm.H + 1) * (qm.W + 1) * t.k * 4 + qm.H * qm.W
+        # weighted banks read the integral image mod 2^16: 2 bytes per entry
+        pbytes = (qm.H + 1) * (qm.W + 1) * (t.k + t.k % 2) * 2 + qm.H * qm.W
         out["integral_hbm_tbs"] = pbytes / (avg["integral_main"] * 1e-3) / 1e12
     return out
 

@@ -13,10 +13,10 @@
 //   edges : per tile, per-row and per-column label histograms and the tile
 //           histogram (small side arrays);
 //   prefix: exclusive prefix sums of those histograms across tiles;
-//   main  : per tile, walks its 64 rows: a row of P is the row above plus the
-//           per-channel running count along the row (per-channel bit masks of
-//           the row's labels and a popcount), streamed out with coalesced
-//           stores (one tile row of P is one contiguous block of memory).
+//   main  : per tile and chunk of 32 channels, walks its 64 rows: a row of P
+//           is the row above plus the per-channel running count along the row
+//           (per-channel bit masks of the row's labels and a popcount),
+//           streamed out as 16-byte stores of 8 channels per thread.
 #include "vqnnf_internal.h"
 
 namespace vqnnf {
@@ -100,95 +100,125 @@ __global__ __launch_bounds__(256) void integral_prefix_kernel(IntegralArgs a, in
   }
 }
 
-// VPT: values of one tile row held per thread, ceil(64 * k / 256).
-template <int VPT>
-__global__ __launch_bounds__(256) void integral_main_kernel(IntegralArgs a, int R, int S) {
-  extern __shared__ int smem[];
-  const int k = a.k, W = a.W, H = a.H;
-  const int s = blockIdx.x, r = blockIdx.y;
-  const int x0 = s * T, y0 = r * T;
-  const int tw = min(T, W - x0), th = min(T, H - y0);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int* abv = smem;                                              // [64][k]
-  unsigned long long* masks = (unsigned long long*)(smem + T * k);  // [2][k]
-  int* left = (int*)(masks + 2 * k);                            // [2][k]
-  const int64_t rowlen = (int64_t)(W + 1) * k;
+// One block per (tile, chunk of kCK channels); thread t owns pixel column
+// t / 4 of the tile and channels [8 (t % 4), +8) of the chunk, so a tile row of
+// the chunk is 64 pixels x 32 channels and every thread stores its 8 values
+// with one 16-byte (P16) or two 16-byte (int32) stores when the channel
+// count is a multiple of 8.
+constexpr int kCK = 32;
 
-  for (int i = tid; i < tw * k; i += 256) {
-    int dx = i / k, j = i % k;
-    abv[i] = a.cbh[((int64_t)r * W + x0 + dx) * k + j];
+template <bool P16>
+__global__ __launch_bounds__(256) void integral_main_kernel(IntegralArgs a, int R, int S) {
+  __shared__ int abv[T][kCK];                    // counts above the tile, then their prefix
+  __shared__ unsigned long long masks[2][kCK];   // per channel: the row's label bit mask
+  const int k = a.k, W = a.W;
+  const int s = blockIdx.x, r = blockIdx.y, j0 = blockIdx.z * kCK;
+  const int ck = min(kCK, k - j0);
+  const int x0 = s * T, y0 = r * T;
+  const int tw = min(T, W - x0), th = min(T, a.H - y0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int dx = tid >> 2, c0 = 8 * (tid & 3);   // pixel column and first channel in the chunk
+  const int64_t rowlen = (int64_t)(W + 1) * k;
+  // whole 16-byte stores: 8-channel groups start 16-byte aligned
+  const bool vec = (k % 8) == 0 && ((uintptr_t)(P16 ? (const void*)a.P16 : (const void*)a.P) % 16) == 0;
+
+  for (int i = tid; i < T * kCK; i += 256) {
+    const int x = i / kCK, c = i % kCK;
+    abv[x][c] = (x < tw && c < ck) ? a.cbh[((int64_t)r * W + x0 + x) * k + j0 + c] : 0;
   }
   __syncthreads();
-  // P[y0][x0 + dx + 1][j] = corner + sum_{x' <= dx} above[x']
-  for (int j = tid; j < k; j += 256) {
-    int c = 0;
-    for (int rr = 0; rr < r; ++rr) c += a.th[((int64_t)rr * S + s) * k + j];
-    for (int dx = 0; dx < tw; ++dx) {
-      c += abv[dx * k + j];
-      abv[dx * k + j] = c;
+  // P[y0][x0 + x + 1][j] = corner + sum_{x' <= x} above[x']
+  if (tid < ck) {
+    int cnt = 0;
+    for (int rr = 0; rr < r; ++rr) cnt += a.th[((int64_t)rr * S + s) * k + j0 + tid];
+    for (int x = 0; x < tw; ++x) {
+      cnt += abv[x][tid];
+      abv[x][tid] = cnt;
     }
   }
   __syncthreads();
-  int V[VPT];
-  int vdx[VPT], vj[VPT];
+  const bool own = dx < tw;
+  int V[8];
 #pragma unroll
-  for (int i = 0; i < VPT; ++i) {
-    int f = tid + 256 * i;
-    vdx[i] = f / k;
-    vj[i] = f % k;
-    V[i] = (f < tw * k) ? abv[f] : 0;
-  }
-  // 32-bit P, or P mod 2^16 (differences of taps still give exact counts
-  // below 2^16 in wrapping 16-bit arithmetic)
-  auto put = [&](int64_t i, int v) {
-    if (a.P16) a.P16[i] = (uint16_t)v;
-    else a.P[i] = v;
-  };
-  if (r == 0) {
-#pragma unroll
-    for (int i = 0; i < VPT; ++i)
-      if (tid + 256 * i < tw * k) put((int64_t)(x0 + vdx[i] + 1) * k + vj[i], 0);
-    if (s == 0)
-      for (int j = tid; j < k; j += 256) put(j, 0);
-  }
-  // per-channel slice of the mask computation for this wave
-  const int jw0 = (k * wave) / 4, jw1 = (k * (wave + 1)) / 4;
-  for (int dy = 0; dy < th; ++dy) {
-    const int y = y0 + dy;
-    const int buf = dy & 1;
-    const int l = (lane < tw) ? (int)a.labels[(int64_t)y * W + x0 + lane] : 0xFFFF;
-    for (int j = jw0; j < jw1; ++j) {
-      unsigned long long m = __ballot(l == j);
-      if (lane == 0) masks[buf * k + j] = m;
-    }
-    for (int j = tid; j < k; j += 256) left[buf * k + j] = a.rsh[((int64_t)y * S + s) * k + j];
-    __syncthreads();
-    const int64_t prow = (int64_t)(y + 1) * rowlen + (int64_t)(x0 + 1) * k;
-#pragma unroll
-    for (int i = 0; i < VPT; ++i) {
-      if (tid + 256 * i < tw * k) {
-        const unsigned long long below = (2ull << vdx[i]) - 1ull;
-        const int cnt = __popcll(masks[buf * k + vj[i]] & below);
-        V[i] += left[buf * k + vj[i]] + cnt;
-        put(prow + tid + 256 * i, V[i]);
+  for (int c = 0; c < 8; ++c) V[c] = abv[dx][c0 + c];
+  // the 8 values of this thread at P entry e (channels j0 + c0 ..); threads
+  // whose channel group lies past the chunk's channels store nothing
+  auto store = [&](int64_t e) {
+    if (c0 >= ck) return;
+    if (vec) {   // c0 + 8 <= ck: k and so ck are multiples of 8
+      if constexpr (P16) {
+        uint4 w;
+        w.x = (uint32_t)(uint16_t)V[0] | ((uint32_t)(uint16_t)V[1] << 16);
+        w.y = (uint32_t)(uint16_t)V[2] | ((uint32_t)(uint16_t)V[3] << 16);
+        w.z = (uint32_t)(uint16_t)V[4] | ((uint32_t)(uint16_t)V[5] << 16);
+        w.w = (uint32_t)(uint16_t)V[6] | ((uint32_t)(uint16_t)V[7] << 16);
+        *(uint4*)(a.P16 + e) = w;
+      } else {
+        *(int4*)(a.P + e) = make_int4(V[0], V[1], V[2], V[3]);
+        *(int4*)(a.P + e + 4) = make_int4(V[4], V[5], V[6], V[7]);
       }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c0 + c < ck) {
+          if constexpr (P16) a.P16[e + c] = (uint16_t)V[c];
+          else a.P[e + c] = V[c];
+        }
     }
-    if (s == 0)
-      for (int j = tid; j < k; j += 256) put((int64_t)(y + 1) * rowlen + j, 0);
+  };
+  auto store_zero = [&](int64_t e) {   // zero border entries of the block's channels
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (c0 + c < ck) {
+        if constexpr (P16) a.P16[e + c] = 0;
+        else a.P[e + c] = 0;
+      }
+  };
+  const int jo = j0 + c0;
+  if (r == 0 && own) {
+    // row 0 of P: zero
+    int Vs[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) { Vs[c] = V[c]; V[c] = 0; }
+    store((int64_t)(x0 + dx + 1) * k + jo);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) V[c] = Vs[c];
+    if (s == 0 && dx == 0) store_zero(jo);
+  }
+  // counts left of the tile in the row (exclusive prefix over tiles), one row ahead
+  auto left_of = [&](int y, int (&L)[8]) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) L[c] = (c0 + c < ck) ? a.rsh[((int64_t)y * S + s) * k + jo + c] : 0;
+  };
+  int Lc[8], Ln[8];
+  left_of(y0, Lc);
+  const unsigned long long below = (2ull << dx) - 1ull;   // columns x0 .. x0 + dx
+  for (int dy = 0; dy < th; ++dy) {
+    const int y = y0 + dy, buf = dy & 1;
+    if (dy + 1 < th) left_of(y + 1, Ln);
+    const int l = (lane < tw) ? (int)a.labels[(int64_t)y * W + x0 + lane] - j0 : -1;
+#pragma unroll
+    for (int i = 0; i < kCK / 4; ++i) {
+      const int c = wave * (kCK / 4) + i;
+      const unsigned long long m = __ballot(l == c);
+      if (lane == 0) masks[buf][c] = m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 8; ++c) V[c] += Lc[c] + __popcll(masks[buf][c0 + c] & below);
+    if (own) store((int64_t)(y + 1) * rowlen + (int64_t)(x0 + dx + 1) * k + jo);
+    if (s == 0 && dx == 0) store_zero((int64_t)(y + 1) * rowlen + jo);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) Lc[c] = Ln[c];
   }
 }
 
 namespace {
-template <int VPT>
+template <bool P16>
 hipError_t go_main(const IntegralArgs& a, int R, int S, hipStream_t st) {
-  size_t lds = (size_t)T * a.k * 4 + 2 * (size_t)a.k * 8 + 2 * (size_t)a.k * 4;
-  auto kern = integral_main_kernel<VPT>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
   timing_begin(K_INT_MAIN);
-  hipLaunchKernelGGL(kern, dim3(S, R), dim3(256), lds, st, a, R, S);
+  const dim3 grid((unsigned)S, (unsigned)R, (unsigned)((a.k + kCK - 1) / kCK));
+  hipLaunchKernelGGL((integral_main_kernel<P16>), grid, dim3(256), 0, st, a, R, S);
   timing_end(K_INT_MAIN);
   return hipGetLastError();
 }
@@ -213,14 +243,7 @@ hipError_t launch_integral(const IntegralArgs& a, hipStream_t st) {
                      a, R, S);
   timing_end(K_INT_PREFIX);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int vpt = (T * a.k + 255) / 256;
-  if (vpt <= 1) return go_main<1>(a, R, S, st);
-  if (vpt <= 2) return go_main<2>(a, R, S, st);
-  if (vpt <= 4) return go_main<4>(a, R, S, st);
-  if (vpt <= 8) return go_main<8>(a, R, S, st);
-  if (vpt <= 16) return go_main<16>(a, R, S, st);
-  if (vpt <= 32) return go_main<32>(a, R, S, st);
-  return go_main<64>(a, R, S, st);
+  return a.P16 ? go_main<true>(a, R, S, st) : go_main<false>(a, R, S, st);
 }
 
 }  // namespace vqnnf
