@@ -430,9 +430,9 @@ def main():
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the hot path shards "
-              "into independent (template, map) pairs and row bands, but multi-GPU runs are not "
-              "part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path would shard "
+              "into independent (template, map) pairs and row bands of a map, but no multi-GPU "
+              "launch is implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
