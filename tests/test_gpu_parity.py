@@ -81,6 +81,9 @@ ASSIGN_CASES = [
     (23, 29, 70, "f32", 200, 8),
     (19, 33, 96, "bf16", 256, 9),
     (1, 1, 8, "f32", 3, 10),
+    # more tiles than compute units: blocks walk several tiles
+    (400, 400, 64, "bf16", 100, 12),
+    (260, 260, 128, "bf16", 256, 13),
 ]
 
 
