@@ -48,12 +48,13 @@ def _template(seed, h, w, D=6, M=10):
     return synth.random_map(h, w, D, "f32", seed=seed, M=M).data
 
 
-def _oracle_rt(tpl, data, bank_o):
-    """R(tau) by the oracle from the template's own codebook and labels (the
-    labels themselves are checked against the oracle's assignment)."""
-    cb = tpl.codebook().astype(np.float64)
-    tl = tpl.labels().astype(np.int64)
-    assert np.array_equal(tl, O.assign_map(data.astype(np.float64), cb))
+def _oracle_rt(tpl, data, bank_o, seed):
+    """R(tau) by the oracle from its own k-means (20 iterations, `seed`); the
+    library's codebook and template labels must equal the oracle's."""
+    cb32 = O.kmeans_codebook(data, tpl.k, 20, seed)
+    assert np.array_equal(tpl.codebook().view(np.uint32), cb32.view(np.uint32))
+    tl = O.assign_map(data.astype(np.float64), cb32.astype(np.float64))
+    assert np.array_equal(tpl.labels().astype(np.int64), tl)
     return O.template_representation(tl, tpl.k, O.expand_bank(bank_o))
 
 
@@ -87,7 +88,7 @@ def test_weighted_template_responses_match_oracle(fs, S):
     bank = B.paper_bank(w, h, fs, S)
     tpl = B.vqnnf_codebook(ctx, data, k, 20, 3, bank)
     bank_o = _to_oracle(bank)           # the library's FP32 coefficients, read exactly
-    rt = _oracle_rt(tpl, data, bank_o)
+    rt = _oracle_rt(tpl, data, bank_o, 3)
     r = tpl.responses().astype(np.float64)
     assert r.shape == rt.shape == (len(bank), k)
     assert np.all(np.abs(r - rt) <= _resp_bound(bank_o, k))
@@ -106,7 +107,7 @@ def test_mixed_bank_responses():
             (4, 1, 20, 24, 4, 3, 0.3, rng.standard_normal((3, 4)))]
     tpl = B.vqnnf_codebook(ctx, data, k, 20, 4, bank)
     bank_o = _to_oracle(bank)
-    rt = _oracle_rt(tpl, data, bank_o)
+    rt = _oracle_rt(tpl, data, bank_o, 4)
     r = tpl.responses().astype(np.float64)
     assert r.shape == (1 + 4 + 25 + 1, k)
     assert np.array_equal(r[:30], rt[:30])

@@ -88,10 +88,14 @@ def crop_case(seed, H, W, D, dtype, tw, th, noise=0.1, M=24):
     return qm, np.ascontiguousarray(t, np.float32), (x0, y0)
 
 
-def oracle_sim(qm, tpl, tdata, bank_o):
-    cb = tpl.codebook().astype(np.float64)
-    tl = tpl.labels().astype(np.int64)
-    assert np.array_equal(tl, O.assign_map(tdata.astype(np.float64), cb))
+def oracle_sim(qm, tpl, tdata, bank_o, seed):
+    """The oracle's heatmap from its own k-means (20 iterations, `seed`); the
+    library's codebook and template labels must equal the oracle's."""
+    cb32 = O.kmeans_codebook(tdata, tpl.k, 20, seed)
+    assert np.array_equal(tpl.codebook().view(np.uint32), cb32.view(np.uint32))
+    cb = cb32.astype(np.float64)
+    tl = O.assign_map(tdata.astype(np.float64), cb)
+    assert np.array_equal(tpl.labels().astype(np.int64), tl)
     ql = O.assign_map(O.decode(qm.dtype, qm.data, qm.scale), cb)
     filters = O.expand_bank(bank_o)
     rt = O.template_representation(tl, tpl.k, filters)
@@ -134,7 +138,7 @@ def test_paper_bank_match(ctx, case):
     heat = torch.full(((H - th + 1) * (W - tw + 1),), float("nan"), device="cuda")
     best = B.vqnnf_match(ctx, tpl, B.device_fmap(dq, qm.dtype), REFINED, heat)
     # the oracle builds the bank from the paper on its own (FP64 coefficients)
-    sim, filters = oracle_sim(qm, tpl, tdata, O.paper_bank(tw, th, fs, S))
+    sim, filters = oracle_sim(qm, tpl, tdata, O.paper_bank(tw, th, fs, S), seed)
     check(heat, sim, filters, k, best, f"{fs} S={S} k={k}")
 
 
@@ -148,7 +152,7 @@ def test_mixed_bank_and_single_window(ctx):
     dq = to_dev(qm)
     heat = torch.full((36 * 40,), float("nan"), device="cuda")
     best = B.vqnnf_match(ctx, tpl, B.device_fmap(dq, "bf16"), REFINED, heat)
-    sim, filters = oracle_sim(qm, tpl, tdata, to_oracle_bank(bank))
+    sim, filters = oracle_sim(qm, tpl, tdata, to_oracle_bank(bank), 1)
     check(heat, sim, filters, 16, best, "mixed bank")
     # template as large as the map: one window
     qm1 = synth.random_map(30, 34, 24, "bf16", seed=8, M=12)
@@ -157,7 +161,7 @@ def test_mixed_bank_and_single_window(ctx):
     tpl1 = B.vqnnf_codebook(ctx, t1, 12, 20, 2, bank1)
     h1 = torch.full((1,), float("nan"), device="cuda")
     best1 = B.vqnnf_match(ctx, tpl1, B.device_fmap(to_dev(qm1), "bf16"), REFINED, h1)
-    sim1, f1 = oracle_sim(qm1, tpl1, t1, O.paper_bank(34, 30, "23rect", 2))
+    sim1, f1 = oracle_sim(qm1, tpl1, t1, O.paper_bank(34, 30, "23rect", 2), 2)
     check(h1, sim1, f1, 12, best1, "single window")
 
 

@@ -74,7 +74,10 @@ def per_pair(ctx, tpls, fms, heats, prec):
 def check_oracle(wl, tp, mi, ti, bank, heat):
     qm, t = wl.maps[mi], wl.templates[mi][ti]
     h, w, _ = t.data.shape
-    cb = tp.codebook().astype(np.float64)
+    # the oracle's own k-means (make_pairs asks for 20 iterations, seed 0)
+    cb32 = O.kmeans_codebook(t.data, t.k, 20, 0)
+    assert np.array_equal(tp.codebook().view(np.uint32), cb32.view(np.uint32))
+    cb = cb32.astype(np.float64)
     labels = O.assign_map(O.decode(qm.dtype, qm.data, qm.scale), cb)
     filters = O.expand_bank([O.FilterDesc(*b[:6], None, b[6]) for b in bank])
     rt = O.template_representation(O.assign_map(t.data.astype(np.float64), cb), t.k, filters)

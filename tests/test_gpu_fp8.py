@@ -67,7 +67,9 @@ def test_fp8_assign_exact(ctx, H, W, D, k, seed):
     lab = torch.empty(H * W, dtype=torch.uint8, device="cuda")
     log(f"fp8 assign {H}x{W} D={D} k={k}")
     nfl = B.vqnnf_assign(ctx, tpl, fm, B.VQNNF_PREC_BF16_REFINED, lab)
-    ref = O.assign_map(O.decode("fp8", qm.data, qm.scale), tpl.codebook().astype(np.float64))
+    cb32 = O.kmeans_codebook(t, k, 10, seed)
+    assert np.array_equal(tpl.codebook().view(np.uint32), cb32.view(np.uint32))
+    ref = O.assign_map(O.decode("fp8", qm.data, qm.scale), cb32.astype(np.float64))
     got = lab.cpu().numpy().reshape(H, W).astype(np.int64)
     log(f"  flagged {nfl}, mismatches {(got != ref).sum()}")
     assert np.array_equal(got, ref)
@@ -86,7 +88,9 @@ def test_fp8_match_and_two_scales(ctx):
     h, w, _ = t0.data.shape
     tpl = B.vqnnf_codebook(ctx, t0.data, t0.k, 20, 0, B.default_bank(w, h, 3))
     filters = O.expand_bank(O.default_bank(w, h, 3))
-    cb = tpl.codebook().astype(np.float64)
+    cb32 = O.kmeans_codebook(t0.data, t0.k, 20, 0)
+    assert np.array_equal(tpl.codebook().view(np.uint32), cb32.view(np.uint32))
+    cb = cb32.astype(np.float64)
     rt = O.template_representation(O.assign_map(t0.data.astype(np.float64), cb), t0.k, filters)
     for mi, qm in enumerate(wl.maps):
         dev = torch.from_numpy(qm.data).cuda()

@@ -64,7 +64,10 @@ def test_projection_parity(ctx, H, W, D, dt, d):
         x = O.decode(qm.dtype, qm.data, qm.scale)
         fm = B.device_fmap(dev(qm), dt, qm.scale)
         tmpl = x[:30, :30].astype(np.float32)
-    mean, basis, _ = B.vqnnf_pca_fit(tmpl, d)
+    # the oracle's own PCA of the template, rounded to FP32 (the arguments the
+    # projection takes)
+    om, ob, _ = O.pca_fit(tmpl.reshape(-1, D).astype(np.float64), d)
+    mean, basis = om.astype(np.float32), ob.astype(np.float32)
     out = torch.empty((H, W, d), dtype=torch.float32, device="cuda")
     B.vqnnf_pca_project(ctx, fm, mean, basis, out)
     xc = x.reshape(-1, D) - mean.astype(np.float64)
@@ -82,30 +85,32 @@ def test_projection_parity(ctx, H, W, D, dt, d):
 
 @pytest.mark.parametrize("d", [9, 18])
 def test_low_d_match_end_to_end(ctx, d):
-    """Template PCA, template and query projected on the GPU, then the whole
-    matching path at D = d: labels exact against the oracle's assignment of
-    the projected query, heatmap within the parity tolerance, planted crop
-    found."""
+    """The matching path at D = d on PCA-reduced features.  The reduced
+    template and query are the oracle's FP64 projections (its own PCA of the
+    template) rounded to FP32; on them the library's k-means must equal the
+    oracle's bit for bit, the labels must be exact and the heatmap within the
+    parity tolerance.  The GPU projection of the same query stays within the
+    projection bound of the oracle's, and matching on it finds the planted
+    crop."""
     H, W, D, side, k = 256, 288, 256, 48, 32
     qm = synth.random_map(H, W, D, "bf16", seed=31, M=32)
     q64 = O.decode("bf16", qm.data)
     rng = np.random.default_rng(5)
     x0, y0 = int(rng.integers(0, W - side + 1)), int(rng.integers(0, H - side + 1))
     t = (q64[y0:y0 + side, x0:x0 + side] + 0.05 * rng.standard_normal((side, side, D))).astype(np.float32)
-    mean, basis, _ = B.vqnnf_pca_fit(t, d)
-    tp = torch.empty((side, side, d), dtype=torch.float32, device="cuda")
-    B.vqnnf_pca_project(ctx, B.device_fmap(torch.from_numpy(t).cuda(), "f32"), mean, basis, tp)
-    t_low = tp.cpu().numpy()
-    qp = torch.empty((H, W, d), dtype=torch.float32, device="cuda")
-    B.vqnnf_pca_project(ctx, B.device_fmap(dev(qm), "bf16"), mean, basis, qp)
+    om, ob, _ = O.pca_fit(t.reshape(-1, D).astype(np.float64), d)
+    mean, basis = om.astype(np.float32), ob.astype(np.float32)
+    t_low = O.pca_project(t.astype(np.float64), mean, basis).astype(np.float32)
+    q_low = O.pca_project(q64, mean, basis).astype(np.float32)
     bank = B.default_bank(side, side, 3)
     tpl = B.vqnnf_codebook(ctx, t_low, k, 20, 0, bank)
-    cb = tpl.codebook().astype(np.float64)
-    assert np.array_equal(tpl.codebook().view(np.uint32), O.kmeans_codebook(t_low, k, 20, 0).view(np.uint32))
-    fm = B.device_fmap(qp, "f32")
+    cb32 = O.kmeans_codebook(t_low, k, 20, 0)
+    assert np.array_equal(tpl.codebook().view(np.uint32), cb32.view(np.uint32))
+    cb = cb32.astype(np.float64)
+    fm = B.device_fmap(torch.from_numpy(np.ascontiguousarray(q_low)).cuda(), "f32")
     lab = torch.empty(H * W, dtype=torch.uint8, device="cuda")
     nf = B.vqnnf_assign(ctx, tpl, fm, B.VQNNF_PREC_BF16_REFINED, lab)
-    ql = O.assign_map(qp.cpu().numpy().astype(np.float64), cb)
+    ql = O.assign_map(q_low.astype(np.float64), cb)
     assert np.array_equal(lab.cpu().numpy().reshape(H, W), ql.astype(np.uint8))
     heat = torch.full(((H - side + 1) * (W - side + 1),), float("nan"), device="cuda")
     (bx, by), _ = B.vqnnf_match(ctx, tpl, fm, B.VQNNF_PREC_BF16_REFINED, heat)
@@ -116,3 +121,13 @@ def test_low_d_match_end_to_end(ctx, d):
     log(f"low-D d={d}: flagged {nf}, heatmap max err {np.abs(g - sim).max():.3e}, best ({bx},{by}) planted ({x0},{y0})")
     assert (np.abs(g - sim) <= REL * np.abs(sim) + ABS).all()
     assert (bx, by) == (x0, y0)
+    # the same query projected on the GPU, then matched
+    qp = torch.empty((H, W, d), dtype=torch.float32, device="cuda")
+    B.vqnnf_pca_project(ctx, B.device_fmap(dev(qm), "bf16"), mean, basis, qp)
+    exact = O.pca_project(q64, mean, basis).reshape(-1, d)
+    bound = 2 * (3 * D + 4) * U * ((np.abs(q64.reshape(-1, D)) + np.abs(mean.astype(np.float64)))
+                                   @ np.abs(basis.astype(np.float64)).T)
+    assert (np.abs(qp.cpu().numpy().reshape(-1, d).astype(np.float64) - exact) <= bound).all()
+    heat2 = torch.full_like(heat, float("nan"))
+    (bx2, by2), _ = B.vqnnf_match(ctx, tpl, B.device_fmap(qp, "f32"), B.VQNNF_PREC_BF16_REFINED, heat2)
+    assert (bx2, by2) == (x0, y0)
