@@ -15,7 +15,12 @@ codebooks in seconds, so it checks:
   * for every pair, that the reported best is the first maximum of its
     heatmap, and that the graph replay reproduces the captured call.
 Every pair's heatmap must also equal, bit for bit, the one vqnnf_match gives
-for that pair alone (that path is pinned to the oracle at full size)."""
+for that pair alone (that path is pinned to the oracle at full size).
+
+The 32-map FP8 workload (sides 256..2048, 4 templates per map, k = 64,
+full window + 3x3 grid) is checked the same way with its map sides halved
+(128..1024: generating the full set takes minutes of host time); its launch
+configuration is the same (one fused assignment launch over all 32 maps)."""
 import sys
 
 import numpy as np
@@ -36,36 +41,38 @@ def log(*a):
     sys.stdout.flush()
 
 
-def test_c4_batched_full_size():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    log("generating the 64-template 1024x1024 D=256 workload")
-    wl = synth.make_config("c4")
-    qm, row = wl.maps[0], wl.templates[0]
-    H, W, D = qm.H, qm.W, qm.D
+def _to_dev(qm):
+    if qm.dtype == "bf16":
+        return torch.from_numpy(qm.data.view(np.int16)).cuda()
+    return torch.from_numpy(np.ascontiguousarray(qm.data)).cuda()
+
+
+def _check_workload(wl, seed, n_cheap):
     ctx = B.Context(stream=torch.cuda.current_stream())
-    rng = np.random.default_rng(4064)
-    cbs, tpls, heats = [], [], []
-    dev = torch.from_numpy(qm.data.view(np.int16)).cuda()
-    fm = B.device_fmap(dev, "bf16")
-    for t in row:
-        h, w, _ = t.data.shape
-        src = t.data.reshape(-1, D)
-        cb = (src[rng.integers(0, len(src), size=t.k)]
-              + 0.05 * rng.standard_normal((t.k, D))).astype(np.float32)
-        cbs.append(cb)
-        tpls.append(B.vqnnf_template_from_codebook(ctx, t.data, cb, B.default_bank(w, h, t.grid)))
-        heats.append(torch.full(((H - h + 1) * (W - w + 1),), float("nan"), device="cuda"))
+    rng = np.random.default_rng(seed)
+    pairs, cbs, tpls, fms, heats, devs = [], [], [], [], [], []
+    for mi, (qm, row) in enumerate(zip(wl.maps, wl.templates)):
+        devs.append(_to_dev(qm))
+        for t in row:
+            h, w, D = t.data.shape
+            src = t.data.reshape(-1, D)
+            cb = (src[rng.integers(0, len(src), size=t.k)]
+                  + 0.05 * rng.standard_normal((t.k, D))).astype(np.float32)
+            pairs.append((qm, t))
+            cbs.append(cb)
+            tpls.append(B.vqnnf_template_from_codebook(ctx, t.data, cb, B.default_bank(w, h, t.grid)))
+            fms.append(B.device_fmap(devs[mi], qm.dtype, qm.scale))
+            heats.append(torch.full(((qm.H - h + 1) * (qm.W - w + 1),), float("nan"), device="cuda"))
     P = B.VQNNF_PREC_BF16_REFINED
-    n = len(row)
-    log(f"{n} pairs; batched call in graph mode (capture, then replay)")
+    n = len(pairs)
+    log(f"{n} pairs on {len(wl.maps)} map(s); batched call in graph mode (capture, then replay)")
     B.vqnnf_ctx_set_graph(ctx, True)
     try:
-        out = B.vqnnf_match_batched(ctx, tpls, [fm] * n, P, heats)
+        out = B.vqnnf_match_batched(ctx, tpls, fms, P, heats)
         first = [h.clone() for h in heats]
         for h in heats:
             h.fill_(float("nan"))
-        out2 = B.vqnnf_match_batched(ctx, tpls, [fm] * n, P, heats)
+        out2 = B.vqnnf_match_batched(ctx, tpls, fms, P, heats)
         torch.cuda.synchronize()
     finally:
         B.vqnnf_ctx_set_graph(ctx, False)
@@ -75,11 +82,11 @@ def test_c4_batched_full_size():
     del first
     # every pair against the single-pair path, and the best as the first maximum
     found = 0
-    for i, t in enumerate(row):
+    for i, (qm, t) in enumerate(pairs):
         h, w, _ = t.data.shape
-        ow = W - w + 1
+        ow = qm.W - w + 1
         ref = torch.empty_like(heats[i])
-        best = B.vqnnf_match(ctx, tpls[i], fm, P, ref)
+        best = B.vqnnf_match(ctx, tpls[i], fms[i], P, ref)
         assert torch.equal(heats[i], ref), f"pair {i} differs from vqnnf_match"
         assert out[i] == best, (i, out[i], best)
         j = int(torch.argmax(heats[i]).item())
@@ -87,16 +94,17 @@ def test_c4_batched_full_size():
         assert (bx, by) == (j % ow, j // ow) and bs == float(heats[i][j].item()), i
         found += (bx, by) == (t.x0, t.y0)
     log(f"planted crop is the best window for {found} of {n} pairs")
-    # the oracle on sampled windows
+    # the oracle on sampled windows: the cheapest templates of every codebook
+    # size and the largest template
     picks = []
-    for k in sorted({t.k for t in row}):
-        idx = sorted((i for i, t in enumerate(row) if t.k == k), key=lambda i: row[i].data.shape[0])
-        picks += idx[:3]
-    picks.append(max(range(n), key=lambda i: row[i].data.shape[0]))
+    for k in sorted({t.k for _, t in pairs}):
+        idx = sorted((i for i, (_, t) in enumerate(pairs) if t.k == k), key=lambda i: pairs[i][1].data.shape[0])
+        picks += idx[:n_cheap]
+    picks.append(max(range(n), key=lambda i: pairs[i][1].data.shape[0]))
     for i in picks:
-        t = row[i]
+        qm, t = pairs[i]
         h, w, _ = t.data.shape
-        oh, ow = H - h + 1, W - w + 1
+        oh, ow = qm.H - h + 1, qm.W - w + 1
         cb64 = cbs[i].astype(np.float64)
         filters = O.expand_bank(O.default_bank(w, h, t.grid))
         tl = O.assign_map(t.data.astype(np.float64), cb64)
@@ -105,7 +113,7 @@ def test_c4_batched_full_size():
         hm = heats[i].cpu().numpy()
         wins = [(t.x0, t.y0), (int(rng.integers(0, ow)), int(rng.integers(0, oh)))]
         for (x, y) in wins:
-            ql = O.assign_map(O.decode("bf16", qm.data[y:y + h, x:x + w]), cb64)
+            ql = O.assign_map(O.decode(qm.dtype, qm.data[y:y + h, x:x + w], qm.scale), cb64)
             sim = O.similarity_map_fast(ql, t.k, w, h, filters, rt)
             assert sim.shape == (1, 1)
             ref, got = float(sim[0, 0]), float(hm[y * ow + x])
@@ -113,3 +121,18 @@ def test_c4_batched_full_size():
             assert abs(got - ref) <= REL * abs(ref) + ABS, (i, x, y, got, ref)
     torch.cuda.synchronize()
     ctx.close()
+
+
+def test_c4_batched_full_size():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    log("generating the 64-template 1024x1024 D=256 BF16 workload")
+    _check_workload(synth.make_config("c4"), 4064, 3)
+
+
+def test_c5_batched_half_sides():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    log("generating the 32-map FP8 D=256 workload, map sides halved")
+    wl = synth.make_config("c5", scale_down=2, progress=lambda i, m: log(f"  map {i} of {m} made"))
+    _check_workload(wl, 4065, 8)
