@@ -63,75 +63,86 @@ __global__ __launch_bounds__(64) void km_draw_kernel(const KmJob* __restrict__ j
   if (ci == 0) {
     idx = uniform_index(u, n);
   } else {
-    // Strictly in point order.  Pass 1: S = the running sum over all points.
-    // Pass 2: the same running sum again, a chunk of 64 at a time (the sum
-    // never decreases, D^2 >= 0) until a chunk ends above u * S; that chunk is
-    // added once more point by point to find the first point above it.  Both
-    // passes perform exactly the additions of one serial running sum.
-    // Buffer loads bounded at n points: lanes past the end read 0; four chunks
-    // are in flight while one is added.
+    // Strictly in point order: S = the running sum over all points, with the
+    // running sum at the end of every chunk of 64 points kept in LDS.  The
+    // first chunk whose end exceeds u * S (the sum never decreases, D^2 >= 0)
+    // is added once more point by point, from the sum before it, to find the
+    // first point above u * S: exactly the additions of one serial running
+    // sum.  Buffer loads bounded at n points: lanes past the end read 0; four
+    // chunks are in flight while one is added.
     const __amdgpu_buffer_rsrc_t d2r = __builtin_amdgcn_make_buffer_rsrc(j.d2, (short)0, n * 8, 0x00020000);
     auto ld = [&](int p) -> double {
       return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(d2r, (uint32_t)p * 8u, 0, 0));
     };
-    // a chunk's values go through LDS so that every addend is read
-    // (broadcast) ahead of the dependent chain of additions
+    // a chunk's values go through LDS and are all read (broadcast) into
+    // registers before the dependent chain of additions
     auto add_chunk = [&](double v, int cnt, double r) -> double {
       chunk_s[lane] = v;
       if (cnt >= 64) {
+        double w[64];
 #pragma unroll
-        for (int i = 0; i < 64; ++i) r = r + chunk_s[i];
+        for (int i = 0; i < 64; ++i) w[i] = chunk_s[i];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < 64; ++i) r = r + w[i];
       } else {
         for (int i = 0; i < cnt; ++i) r = r + chunk_s[i];
       }
       return r;
     };
+    // templates have at most 255 x 255 points: 1017 chunks
+    constexpr int kEnds = 1024;
+    __shared__ double ends_s[kEnds];
+    const int nc = (n + 63) / 64;
+    const bool keep = nc <= kEnds;
     double run = 0.0;
     {
       double q0 = ld(lane), q1 = ld(64 + lane), q2 = ld(128 + lane), q3 = ld(192 + lane);
       for (int base = 0; base < n; base += 256) {
+        const int c = base / 64;
         run = add_chunk(q0, n - base, run);
+        if (keep && lane == 0 && c < nc) ends_s[c] = run;
         q0 = ld(base + 256 + lane);
         run = add_chunk(q1, n - base - 64, run);
+        if (keep && lane == 0 && c + 1 < nc) ends_s[c + 1] = run;
         q1 = ld(base + 320 + lane);
         run = add_chunk(q2, n - base - 128, run);
+        if (keep && lane == 0 && c + 2 < nc) ends_s[c + 2] = run;
         q2 = ld(base + 384 + lane);
         run = add_chunk(q3, n - base - 192, run);
+        if (keep && lane == 0 && c + 3 < nc) ends_s[c + 3] = run;
         q3 = ld(base + 448 + lane);
       }
     }
+    __syncthreads();
     const double total = run;
     if (total == 0.0) {
       idx = uniform_index(u, n);
     } else {
       const double target = u * total;
-      run = 0.0;
-      double q0 = ld(lane), q1 = ld(64 + lane), q2 = ld(128 + lane), q3 = ld(192 + lane);
       int hit = -1;                      // first chunk whose end exceeds the target
       double before = 0.0;               // running sum before that chunk
-      double hv = 0.0;                   // its values
-      for (int base = 0; base < n && hit < 0; base += 256) {
-        double r = add_chunk(q0, n - base, run);
-        if (r > target) { hit = base; before = run; hv = q0; break; }
-        run = r;
-        q0 = ld(base + 256 + lane);
-        r = add_chunk(q1, n - base - 64, run);
-        if (r > target) { hit = base + 64; before = run; hv = q1; break; }
-        run = r;
-        q1 = ld(base + 320 + lane);
-        r = add_chunk(q2, n - base - 128, run);
-        if (r > target) { hit = base + 128; before = run; hv = q2; break; }
-        run = r;
-        q2 = ld(base + 384 + lane);
-        r = add_chunk(q3, n - base - 192, run);
-        if (r > target) { hit = base + 192; before = run; hv = q3; break; }
-        run = r;
-        q3 = ld(base + 448 + lane);
+      if (keep) {
+        for (int c0 = 0; c0 < nc && hit < 0; c0 += 64) {
+          const int c = c0 + lane;
+          const unsigned long long b = __ballot(c < nc && ends_s[c < nc ? c : 0] > target);
+          if (b) hit = c0 + __ffsll((long long)b) - 1;
+        }
+        if (hit > 0) before = ends_s[hit - 1];
+        if (hit >= 0) hit *= 64;
+      } else {
+        // more chunks than kept: the running sum again, chunk by chunk
+        run = 0.0;
+        for (int base = 0; base < n; base += 64) {
+          const double r = add_chunk(ld(base + lane), n - base, run);
+          if (r > target) { hit = base; before = run; break; }
+          run = r;
+        }
       }
       if (hit >= 0) {
         double r = before;
         const int nb = min(64, n - hit);
-        chunk_s[lane] = hv;
+        chunk_s[lane] = ld(hit + lane);
         for (int i = 0; i < nb; ++i) {
           r = r + chunk_s[i];
           if (r > target) { idx = hit + i; break; }
