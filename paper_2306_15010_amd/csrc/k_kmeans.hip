@@ -190,39 +190,64 @@ __global__ __launch_bounds__(256) void km_d2_kernel(const KmJob* __restrict__ jo
 
 // Distances of a block of 256 points to one chunk of kKmCK centres (FP64
 // centres, or the FP32 codebook when from_f32 is set); writes the chunk's
-// nearest centre (lowest index on ties) and its distance.
+// nearest centre (lowest index on ties) and its distance.  The centres are
+// staged dimension-major (one dimension's kKmCK values contiguous, read as
+// broadcast 16-byte words); each thread requests its point's values 16
+// dimensions ahead of the ones it is accumulating.
 __global__ __launch_bounds__(256) void km_assign_kernel(const KmJob* __restrict__ jobs, int from_f32) {
   const KmJob& j = jobs[blockIdx.z];
   const int n = j.l, D = j.D, k = j.k;
   const int c0 = blockIdx.y * kKmCK;
   if (c0 >= k || (int64_t)blockIdx.x * 256 >= n) return;   // uniform per block
   const int nc = min(kKmCK, k - c0);
-  __shared__ double cs[kKmCK][kKmTD];
+  __shared__ double cs[kKmTD][kKmCK];
   const int p = blockIdx.x * 256 + threadIdx.x;
   const float* xtp = j.xt + min(p, n - 1);       // dimension-major: coalesced across the wave
   double acc[kKmCK];
 #pragma unroll
   for (int i = 0; i < kKmCK; ++i) acc[i] = 0.0;
+  constexpr int PF = 16;                         // dimensions per prefetch group
   for (int t0 = 0; t0 < D; t0 += kKmTD) {
     const int tn = min(kKmTD, D - t0);
     __syncthreads();
     for (int e = threadIdx.x; e < kKmCK * kKmTD; e += 256) {
-      const int ci = e / kKmTD, t = e % kKmTD;
+      const int t = e / kKmCK, ci = e % kKmCK;
       double v = 0.0;
       if (ci < nc && t < tn)
         v = from_f32 ? (double)j.c32[(size_t)(c0 + ci) * D + t0 + t] : j.c[(size_t)(c0 + ci) * D + t0 + t];
-      cs[ci][t] = v;
+      cs[t][ci] = v;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int t = 0; t < tn; ++t) {
-      const double xv = (double)xtp[(int64_t)(t0 + t) * n];
+    // a global-address-space pointer: the point values are read with global
+    // loads (only the vector-memory counter), so the waits for them leave
+    // the LDS reads of the centres alone
+    typedef __attribute__((address_space(1))) const float gfloat;
+    gfloat* xq = (gfloat*)(xtp + (int64_t)t0 * n);
+    float xa[PF], xb[PF];
+    auto ldx = [&](float (&dst)[PF], int g) {
 #pragma unroll
-      for (int i = 0; i < kKmCK; ++i) {
-        const double diff = xv - cs[i][t];
-        const double sq = diff * diff;
-        acc[i] = acc[i] + sq;
+      for (int u = 0; u < PF; ++u) dst[u] = xq[(int64_t)min(g + u, tn - 1) * n];   // past tn: unused
+    };
+    // dimensions t0 + g .. t0 + g + PF - 1, in order
+    auto comp = [&](const float (&src)[PF], int g) {
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        if (g + u >= tn) break;
+        const double xv = (double)src[u];
+#pragma unroll
+        for (int i = 0; i < kKmCK; ++i) {
+          const double diff = xv - cs[g + u][i];
+          const double sq = diff * diff;
+          acc[i] = acc[i] + sq;
+        }
       }
+    };
+    ldx(xa, 0);
+    for (int g = 0; g < tn; g += 2 * PF) {
+      ldx(xb, g + PF);
+      comp(xa, g);
+      ldx(xa, g + 2 * PF);
+      comp(xb, g + PF);
     }
   }
   if (p < n) {
