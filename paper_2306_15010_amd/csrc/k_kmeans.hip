@@ -325,24 +325,44 @@ __global__ __launch_bounds__(1024) void km_sort_kernel(const KmJob* __restrict__
 }
 
 // New centres: thread per (cluster, dimension), sequential sum of the
-// cluster's points in point order, divided by the count.
+// cluster's points in point order, divided by the count.  Groups of G points:
+// the point indices are requested one group ahead of their values and the
+// values one group ahead of their additions (global loads: only the
+// vector-memory counter), so each group waits for one memory round trip.
 __global__ __launch_bounds__(256) void km_update_kernel(const KmJob* __restrict__ jobs) {
   const KmJob& j = jobs[blockIdx.y];
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)j.k * j.D) return;
-  const int c = (int)(e / j.D), t = (int)(e % j.D);
+  const int D = j.D;
+  const int c = (int)(e / D), t = (int)(e % D);
   const int b = j.start[c], nb = j.start[c + 1] - b;
   if (nb == 0) return;                     // empty cluster keeps its centre
+  typedef __attribute__((address_space(1))) const int gint;
+  typedef __attribute__((address_space(1))) const float gfloat;
+  gint* ip = (gint*)(j.idx + b);
+  gfloat* xp = (gfloat*)(j.x + t);
+  constexpr int G = 32;
+  int ia[G];                               // indices of the next group
+  float va[G], vb[G];                      // values of this group and the next
+  // past the cluster's end: its last point again (read, never added)
+#pragma unroll
+  for (int q = 0; q < G; ++q) ia[q] = ip[min(q, nb - 1)];
+#pragma unroll
+  for (int q = 0; q < G; ++q) va[q] = xp[(size_t)ia[q] * D];
+#pragma unroll
+  for (int q = 0; q < G; ++q) ia[q] = ip[min(G + q, nb - 1)];
   double s = 0.0;
-  int m = 0;
-  for (; m + 8 <= nb; m += 8) {           // loads of 8 points ahead of their adds
-    float v[8];
+  for (int m = 0; m < nb; m += G) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = j.x[(size_t)j.idx[b + m + q] * j.D + t];
+    for (int q = 0; q < G; ++q) vb[q] = xp[(size_t)ia[q] * D];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s = s + (double)v[q];
+    for (int q = 0; q < G; ++q) ia[q] = ip[min(m + 2 * G + q, nb - 1)];
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+      if (m + q < nb) s = s + (double)va[q];
+#pragma unroll
+    for (int q = 0; q < G; ++q) va[q] = vb[q];
   }
-  for (; m < nb; ++m) s = s + (double)j.x[(size_t)j.idx[b + m] * j.D + t];
   j.c[e] = s / (double)nb;
 }
 
