@@ -11,6 +11,7 @@
 #include <mutex>
 #include <string>
 #include <map>
+#include <thread>
 #include <vector>
 
 #include "vqnnf_internal.h"
@@ -442,10 +443,8 @@ vqnnf_status upload(vqnnf_ctx* c, T** dst, const std::vector<T>& src) {
 }
 
 void free_device(DeviceTemplate& t) {
-  void* ps[] = {t.d_codebook, t.d_frag_bf16, t.d_frag_f32, t.d_cnorm, t.d_counts, t.d_counts16,
-                t.d_weights, t.d_boxes, t.d_groups, t.d_coef, t.d_resp};
-  for (void* p : ps)
-    if (p) hipFree(p);
+  if (t.d_blob) hipFree(t.d_blob);
+  t.d_blob = nullptr;
   t.d_codebook = nullptr; t.d_frag_bf16 = nullptr; t.d_frag_f32 = nullptr; t.d_cnorm = nullptr;
   t.d_counts = nullptr; t.d_counts16 = nullptr; t.d_weights = nullptr; t.d_boxes = nullptr;
   t.d_groups = nullptr; t.d_coef = nullptr; t.d_resp = nullptr;
@@ -500,20 +499,34 @@ vqnnf_status finish_template(vqnnf_ctx* ctx, vqnnf_template* tp, const vqnnf_fma
   HostTables ht;
   build_tables(t, ht);
   if (!ctx->has_device) return ok();
-  vqnnf_status s;
-  if ((s = upload(ctx, &t.d_codebook, t.codebook))) return s;
-  std::vector<uint4> fb(ht.frag_bf16.size() / 8);
-  std::memcpy(fb.data(), ht.frag_bf16.data(), ht.frag_bf16.size() * 2);
-  if ((s = upload(ctx, &t.d_frag_bf16, fb))) return s;
-  if ((s = upload(ctx, &t.d_frag_f32, ht.frag_f32))) return s;
-  if ((s = upload(ctx, &t.d_cnorm, ht.cnorm))) return s;
-  if ((s = upload(ctx, &t.d_counts, ht.counts))) return s;
-  if ((s = upload(ctx, &t.d_counts16, ht.counts16))) return s;
-  if ((s = upload(ctx, &t.d_weights, t.weights))) return s;
-  if ((s = upload(ctx, &t.d_boxes, t.boxes))) return s;
-  if ((s = upload(ctx, &t.d_groups, t.groups))) return s;
-  if ((s = upload(ctx, &t.d_coef, t.coef))) return s;
-  if ((s = upload(ctx, &t.d_resp, ht.resp))) return s;
+  // every table in one device allocation, filled by one copy from a host
+  // image (256-byte aligned parts; an empty table keeps a null pointer)
+  struct Part { void** dst; const void* src; size_t bytes; size_t off; };
+  auto part = [](auto** dst, const auto& v) {
+    return Part{(void**)dst, (const void*)v.data(), v.size() * sizeof(v[0]), 0};
+  };
+  Part parts[] = {part(&t.d_codebook, t.codebook),   part(&t.d_frag_bf16, ht.frag_bf16),
+                  part(&t.d_frag_f32, ht.frag_f32),  part(&t.d_cnorm, ht.cnorm),
+                  part(&t.d_counts, ht.counts),      part(&t.d_counts16, ht.counts16),
+                  part(&t.d_weights, t.weights),     part(&t.d_boxes, t.boxes),
+                  part(&t.d_groups, t.groups),       part(&t.d_coef, t.coef),
+                  part(&t.d_resp, ht.resp)};
+  size_t total = 0;
+  for (Part& q : parts) {
+    q.off = total;
+    total += (q.bytes + 255) & ~(size_t)255;
+  }
+  for (Part& q : parts) *q.dst = nullptr;
+  if (total == 0) return ok();
+  std::vector<char> image(total, 0);
+  for (const Part& q : parts)
+    if (q.bytes) std::memcpy(image.data() + q.off, q.src, q.bytes);
+  char* blob = nullptr;
+  HIP_TRY(hipMalloc((void**)&blob, total));
+  t.d_blob = blob;
+  HIP_TRY(hipMemcpy(blob, image.data(), total, hipMemcpyHostToDevice));
+  for (const Part& q : parts)
+    if (q.bytes) *q.dst = blob + q.off;
   return ok();
 }
 
@@ -525,11 +538,40 @@ vqnnf_status check_template_map(const vqnnf_fmap* tmpl) {
   if (tmpl->H > 255 || tmpl->W > 255)
     return fail(VQNNF_EINVAL, "template: sides must be <= 255 (window histograms are 16-bit)");
   if (tmpl->dtype == VQNNF_RGB8) return ok();
-  for (int64_t p = 0; p < (int64_t)tmpl->H * tmpl->W; ++p) {
-    const float* v = (const float*)tmpl->data + p * (tmpl->pixel_stride ? tmpl->pixel_stride : tmpl->D);
-    for (int d = 0; d < tmpl->D; ++d)
-      if (!std::isfinite(v[d])) return fail(VQNNF_EINVAL, "template: non-finite value at pixel %lld", (long long)p);
+  const int64_t np = (int64_t)tmpl->H * tmpl->W, st = tmpl->pixel_stride ? tmpl->pixel_stride : tmpl->D;
+  const int D = tmpl->D;
+  const float* base = (const float*)tmpl->data;
+  // first pixel in [p0, p1) with an infinite or NaN value (all exponent bits
+  // set), or -1
+  auto scan = [&](int64_t p0, int64_t p1) -> int64_t {
+    for (int64_t p = p0; p < p1; ++p) {
+      const float* v = base + p * st;
+      uint32_t bad = 0u;
+      for (int d = 0; d < D; ++d) {
+        uint32_t b;
+        std::memcpy(&b, v + d, 4);
+        bad |= (uint32_t)((b & 0x7f800000u) == 0x7f800000u);
+      }
+      if (bad) return p;
+    }
+    return -1;
+  };
+  int64_t first = -1;
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int nt = np * D >= (int64_t)1 << 22 ? (int)std::min<unsigned>(8u, std::max(1u, hw)) : 1;
+  if (nt == 1) {
+    first = scan(0, np);
+  } else {
+    // large templates: contiguous pixel ranges on nt threads, the lowest hit wins
+    std::vector<int64_t> hit(nt, -1);
+    std::vector<std::thread> th;
+    const int64_t per = (np + nt - 1) / nt;
+    for (int i = 0; i < nt; ++i)
+      th.emplace_back([&, i]() { hit[i] = scan(std::min(np, i * per), std::min(np, (i + 1) * per)); });
+    for (std::thread& x : th) x.join();
+    for (int i = 0; i < nt && first < 0; ++i) first = hit[i];
   }
+  if (first >= 0) return fail(VQNNF_EINVAL, "template: non-finite value at pixel %lld", (long long)first);
   return ok();
 }
 

@@ -100,6 +100,7 @@ struct DeviceTemplate {
   std::vector<float> cnorm32;        // [k] ||c||^2 rounded to FP32
   std::vector<ScaledSet> scaled;     // FP8 tables, one per distinct scale vector
   // device copies
+  void* d_blob = nullptr;            // one allocation holding every table below
   float* d_codebook = nullptr;       // [k][D] FP32
   uint4* d_frag_bf16 = nullptr;      // A fragments, BF16 hi/lo, scaled by -2
   float* d_frag_f32 = nullptr;       // A fragments, FP32, scaled by -2

@@ -183,3 +183,19 @@ def test_batched_codebooks_on_host_context():
     with pytest.raises(B.VqnnfError) as ei:
         B.vqnnf_codebook_batched(ctx, ts, [4, 0, 5], 20, seeds, banks)
     assert ei.value.status == B.VQNNF_EINVAL and "template 1" in str(ei.value)
+
+
+def test_large_template_non_finite_names_first_pixel():
+    """A large template is scanned for non-finite values on several threads;
+    the error still names the first such pixel in row-major order."""
+    ctx = B.Context(host=True)
+    t = np.ones((255, 255, 80), np.float32)
+    t[200, 17, 3] = np.inf
+    t[120, 250, 79] = np.nan
+    t[254, 254, 0] = -np.inf
+    assert _status_of(lambda: B.vqnnf_codebook(ctx, t, 4, 1, 0, B.default_bank(255, 255, 1))) == B.VQNNF_EINVAL
+    assert f"pixel {120 * 255 + 250}" in B.last_error(), B.last_error()
+    t[120, 250, 79] = 1.0
+    t[200, 17, 3] = 1.0
+    assert _status_of(lambda: B.vqnnf_codebook(ctx, t, 4, 1, 0, B.default_bank(255, 255, 1))) == B.VQNNF_EINVAL
+    assert f"pixel {254 * 255 + 254}" in B.last_error(), B.last_error()
