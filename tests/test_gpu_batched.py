@@ -252,3 +252,65 @@ def test_batched_many_maps_one_launch(ctx):
     check_oracle(wa, tpls[0], *pa[3][0], heats[0])
     n_a = len(pa[0])
     check_oracle(wb, tpls[n_a + 1], *pb[3][1], heats[n_a + 1])
+
+
+def test_batched_mixed_storage(ctx):
+    """One batch over an FP32 map (D = 64), a low-dimensional FP32 map
+    (D = 18), a BF16 map (D = 128) and an RGB image (colour features,
+    D = 27): maps that share the fused assignment launch and maps that take
+    their own assignment kernels.  Every pair equals its single-pair
+    vqnnf_match bit for bit; the FP32, low-D and RGB pairs are checked
+    against the oracle (its own k-means and colour features)."""
+    P = B.VQNNF_PREC_BF16_REFINED
+    rng = np.random.default_rng(75)
+    pairs = []   # (template handle, fmap, heatmap, oracle query features, oracle template features, k, w, h, seed)
+    devs = []
+
+    def add_float_map(qm, sides, k):
+        q64 = O.decode(qm.dtype, qm.data, qm.scale)
+        dev = to_dev(qm)
+        devs.append(dev)
+        for side in sides:
+            x0, y0 = int(rng.integers(0, qm.W - side + 1)), int(rng.integers(0, qm.H - side + 1))
+            t = (q64[y0:y0 + side, x0:x0 + side]
+                 + 0.05 * rng.standard_normal((side, side, qm.D))).astype(np.float32)
+            seed = len(pairs) + 1
+            tp = B.vqnnf_codebook(ctx, t, k, 20, seed, B.default_bank(side, side, 3))
+            heat = torch.full(((qm.H - side + 1) * (qm.W - side + 1),), float("nan"), device="cuda")
+            pairs.append((tp, B.device_fmap(dev, qm.dtype), heat, q64, t.astype(np.float64), k, side, side, seed))
+
+    add_float_map(synth.random_map(70, 90, 64, "f32", seed=71, M=20), (14, 20), 16)
+    add_float_map(synth.random_map(60, 75, 18, "f32", seed=72, M=16), (12,), 32)
+    add_float_map(synth.random_map(64, 80, 128, "bf16", seed=73, M=20), (16, 24), 32)
+    img = synth.rgb_image(72, 96, seed=74)
+    dimg = torch.from_numpy(np.ascontiguousarray(img)).cuda()
+    devs.append(dimg)
+    qf = O.rgb_patch_features(img)
+    for tw, th in ((18, 16), (24, 24)):
+        x0, y0 = int(rng.integers(0, 96 - tw + 1)), int(rng.integers(0, 72 - th + 1))
+        crop = np.ascontiguousarray(img[y0:y0 + th, x0:x0 + tw])
+        seed = len(pairs) + 1
+        tp = B.vqnnf_codebook(ctx, crop, 24, 20, seed, B.default_bank(tw, th, 3))
+        heat = torch.full(((72 - th + 1) * (96 - tw + 1),), float("nan"), device="cuda")
+        pairs.append((tp, B.device_fmap(dimg, "rgb8"), heat, qf, O.rgb_patch_features(crop), 24, tw, th, seed))
+    tpls = [p[0] for p in pairs]
+    fms = [p[1] for p in pairs]
+    heats = [p[2] for p in pairs]
+    log(f"mixed batch: {len(pairs)} pairs over FP32, low-D FP32, BF16 and RGB maps")
+    out = B.vqnnf_match_batched(ctx, tpls, fms, P, heats)
+    refs, bests = per_pair(ctx, tpls, fms, heats, P)
+    for i in range(len(pairs)):
+        assert torch.equal(heats[i], refs[i]), f"pair {i}"
+        assert out[i] == bests[i], f"pair {i}: {out[i]} vs {bests[i]}"
+    for i in (0, 2, len(pairs) - 1):
+        tp, _, heat, qx, tx, k, w, h, seed = pairs[i]
+        cb32 = O.kmeans_codebook(tx.astype(np.float32), k, 20, seed)
+        assert np.array_equal(tp.codebook().view(np.uint32), cb32.view(np.uint32)), f"pair {i} codebook"
+        cb = cb32.astype(np.float64)
+        filters = O.expand_bank(O.default_bank(w, h, 3))
+        rt = O.template_representation(O.assign_map(tx, cb), k, filters)
+        sim = O.similarity_map_fast(O.assign_map(qx, cb), k, w, h, filters, rt)
+        gpu = heat.cpu().numpy().reshape(sim.shape).astype(np.float64)
+        err = np.abs(gpu - sim)
+        log(f"pair {i} vs oracle: max abs err {err.max():.3e}")
+        assert (err <= REL * np.abs(sim) + ABS).all(), f"pair {i}"
