@@ -71,7 +71,12 @@ typedef enum {
    * inside the bound.  Labels equal the FP64 nearest neighbour computed in
    * the fixed order d = sum_t (q_t - c_t)^2 (sequential in t, no FMA),
    * lowest index on ties. */
-  VQNNF_PREC_BF16_REFINED = 1
+  VQNNF_PREC_BF16_REFINED = 1,
+  /* For VQNNF_FP8_E4M3 maps only (else VQNNF_EINVAL): the same refined
+   * search as VQNNF_PREC_BF16_REFINED, which FP8 maps take anyway (the E4M3
+   * codes are exact in BF16, the channel scale is folded into a copy of the
+   * codebook); the FP64 re-score uses code x scale, the oracle's value. */
+  VQNNF_PREC_FP8_REFINED = 2
 } vqnnf_prec;
 
 /* A feature map (query or template). */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvqnnf.so")
 
 VQNNF_OK, VQNNF_EINVAL, VQNNF_ENOMEM, VQNNF_EHIP, VQNNF_ENOTSUP, VQNNF_EHANDLE = range(6)
 VQNNF_F32, VQNNF_BF16, VQNNF_FP8_E4M3, VQNNF_RGB8 = 0, 1, 2, 3
-VQNNF_PREC_FP32_PLAIN, VQNNF_PREC_BF16_REFINED = 0, 1
+VQNNF_PREC_FP32_PLAIN, VQNNF_PREC_BF16_REFINED, VQNNF_PREC_FP8_REFINED = 0, 1, 2
 
 EXPORTED = [
     "vqnnf_ctx_create", "vqnnf_ctx_create_host", "vqnnf_ctx_destroy", "vqnnf_codebook",

@@ -580,10 +580,17 @@ vqnnf_status check_query(const vqnnf_ctx* c, const vqnnf_template* t, const vqnn
   vqnnf_status s = check_map(q, "query");
   if (s) return s;
   if (q->D != t->t.D) return fail(VQNNF_EINVAL, "query D=%d differs from template D=%d", q->D, t->t.D);
-  if (prec != VQNNF_PREC_FP32_PLAIN && prec != VQNNF_PREC_BF16_REFINED)
+  if (prec != VQNNF_PREC_FP32_PLAIN && prec != VQNNF_PREC_BF16_REFINED && prec != VQNNF_PREC_FP8_REFINED)
     return fail(VQNNF_EINVAL, "unknown precision %d", prec);
+  if (prec == VQNNF_PREC_FP8_REFINED && q->dtype != VQNNF_FP8_E4M3)
+    return fail(VQNNF_EINVAL, "VQNNF_PREC_FP8_REFINED needs an FP8 E4M3 query map (got dtype %d)", q->dtype);
   (void)c;
   return ok();
+}
+
+// FP8 maps take the refined BF16 search (their codes are exact in BF16).
+int32_t search_prec(int32_t prec) {
+  return prec == VQNNF_PREC_FP8_REFINED ? VQNNF_PREC_BF16_REFINED : prec;
 }
 
 vqnnf_status need_device(const vqnnf_ctx* c) {
@@ -1341,6 +1348,7 @@ vqnnf_status vqnnf_assign(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fma
                           uint8_t* labels, int64_t* n_flagged) {
   vqnnf_status s;
   if ((s = check_ctx(c)) || (s = check_tpl(c, t)) || (s = check_query(c, t, q, prec))) return s;
+  prec = search_prec(prec);
   if (!labels) return fail(VQNNF_EINVAL, "null labels");
   int64_t n = (int64_t)q->H * q->W;
   if ((s = assign_scratch(c, t, n, prec, false))) return s;
@@ -1432,6 +1440,7 @@ vqnnf_status vqnnf_match(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap
                          float* heatmap, int32_t* best_xy, float* best_score) {
   vqnnf_status s;
   if ((s = check_ctx(c)) || (s = check_tpl(c, t)) || (s = check_query(c, t, q, prec))) return s;
+  prec = search_prec(prec);
   if (!heatmap) return fail(VQNNF_EINVAL, "null heatmap");
   if ((s = check_score_dims(t, q->H, q->W))) return s;
   if ((s = pair_scratch(c, &t, &q, 1, prec, 64))) return s;
@@ -1720,6 +1729,7 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     }
     if (!heatmaps[i]) return fail(VQNNF_EINVAL, "pair %d: null heatmap", i);
   }
+  prec = search_prec(prec);
   if ((s = pair_scratch(c, t, q, n, prec, 64))) return s;
   std::vector<const ScaledSet*> sets((size_t)n);
   for (int i = 0; i < n; ++i)

@@ -115,6 +115,12 @@ def test_argument_errors_on_host_context():
     q_stride = B.FMap(0x1000, B.VQNNF_BF16, 32, 32, 4, 3, None)
     assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q_stride, 1, lab)) == B.VQNNF_EINVAL
     assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q, 9, lab)) == B.VQNNF_EINVAL
+    # the FP8 precision is for FP8 maps only
+    assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q, B.VQNNF_PREC_FP8_REFINED, lab)) == B.VQNNF_EINVAL
+    assert "FP8" in B.last_error()
+    sc8 = np.ones(4, np.float32)
+    q8ok = B.FMap(0x1000, B.VQNNF_FP8_E4M3, 32, 32, 4, 4, sc8.ctypes.data)
+    assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q8ok, B.VQNNF_PREC_FP8_REFINED, lab)) == B.VQNNF_ENOTSUP
     q_null = B.FMap(None, B.VQNNF_BF16, 32, 32, 4, 4, None)
     assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q_null, 1, lab)) == B.VQNNF_EINVAL
     # template larger than the map

@@ -140,3 +140,33 @@ def test_fp8_batched_graph_scale_change(ctx):
         r = torch.empty_like(heats[i])
         assert B.vqnnf_match(ctx, tpls[i], fms[i], P, r) == out2[i]
         assert torch.equal(r, heats[i]), i
+
+
+def test_fp8_precision_enum_same_results(ctx):
+    """VQNNF_PREC_FP8_REFINED on an FP8 map runs the refined search: the same
+    labels, heatmap and best window as VQNNF_PREC_BF16_REFINED, in single and
+    batched calls; the labels are the oracle's."""
+    qm = fp8_map(64, 72, 64, 9)
+    q = qm.decoded_f32()
+    t = np.ascontiguousarray(q[10:26, 20:36].astype(np.float32))
+    tpl = B.vqnnf_codebook(ctx, t, 16, 20, 2, B.default_bank(16, 16, 2))
+    dev = torch.from_numpy(qm.data).cuda()
+    fm = B.device_fmap(dev, "fp8", qm.scale)
+    la = torch.empty(64 * 72, dtype=torch.uint8, device="cuda")
+    lb = torch.empty_like(la)
+    B.vqnnf_assign(ctx, tpl, fm, B.VQNNF_PREC_BF16_REFINED, la)
+    B.vqnnf_assign(ctx, tpl, fm, B.VQNNF_PREC_FP8_REFINED, lb)
+    assert torch.equal(la, lb)
+    cb32 = O.kmeans_codebook(t, 16, 20, 2)
+    assert np.array_equal(tpl.codebook().view(np.uint32), cb32.view(np.uint32))
+    ref = O.assign_map(O.decode("fp8", qm.data, qm.scale), cb32.astype(np.float64))
+    assert np.array_equal(lb.cpu().numpy().reshape(64, 72).astype(np.int64), ref)
+    ha = torch.full((49 * 57,), float("nan"), device="cuda")
+    hb = torch.full_like(ha, float("nan"))
+    ba = B.vqnnf_match(ctx, tpl, fm, B.VQNNF_PREC_BF16_REFINED, ha)
+    bb = B.vqnnf_match(ctx, tpl, fm, B.VQNNF_PREC_FP8_REFINED, hb)
+    assert ba == bb and torch.equal(ha, hb)
+    hc = torch.full_like(ha, float("nan"))
+    out = B.vqnnf_match_batched(ctx, [tpl], [fm], B.VQNNF_PREC_FP8_REFINED, [hc])
+    assert out[0] == ba and torch.equal(ha, hc)
+    log(f"FP8 precision enum: best {bb}")
