@@ -232,7 +232,9 @@ vqnnf_status vqnnf_template_responses(const vqnnf_template* t, float* out);
 
 /* NNF of a query map (Alg. 1): labels[y*W + x] = index of the nearest
  * codeword of pixel (y, x) (squared L2, lowest index on ties).
- *  query: DEVICE map, dtype F32 or BF16, query->D == template D.
+ *  query: DEVICE map, dtype F32, BF16, FP8_E4M3 (with its host channel
+ *  scales) or RGB8 (D = 27 colour features), query->D == template D.
+ *  prec: a vqnnf_prec (VQNNF_PREC_FP8_REFINED with FP8 maps only).
  *  labels: DEVICE uint8[H*W].
  *  n_flagged: HOST, may be NULL; receives the number of pixels re-scored in
  *  FP64 (0 for VQNNF_PREC_FP32_PLAIN).  Non-NULL synchronises. */
