@@ -73,7 +73,7 @@ __device__ __forceinline__ void block_max_to(unsigned long long key, unsigned lo
 }
 
 // ================================================================ fused
-// One block owns a tile of up to kTXW x tyw windows and one group of kKG
+// One block owns a tile of up to kTXW x tyw windows and one group of KG
 // channels.  LDS holds, per grid row-band b and per column c of the
 // txw + w - 1 columns the tile touches:
 //   Q[b][c]  the band's column histogram (channel pairs as packed u16,
@@ -98,10 +98,12 @@ constexpr int kSL = 7;                 // columns per prefix segment (odd: a wav
 constexpr int kNSeg = 53;              // segments per row (<= 64 lanes)
 constexpr int kHS = kSL * kNSeg;       // LDS row length in 16-byte entries
 constexpr int kColsMax = kHS - kSL;    // nseg = cols / kSL + 1 segments cover [0, cols]
-constexpr int kKG = 16;                // channels per block
-constexpr int kPQ = kKG / 8;           // 16-byte entries (four pairs) per column per band
+// Channels per block (KG, a template parameter): 32 (four pair groups, 1024
+// threads) where the grid has at most 3 x 3 bins and k pads to a multiple of
+// 32, else 16 (two pair groups, 512 threads); KG / 8 16-byte entries (four
+// pairs each) per column per band.  Wider blocks re-prime their histograms
+// and rebuild their prefixes for more channels at once.
 constexpr int kTXW = 256;              // windows per tile row
-constexpr int kST = 512;               // threads per block: kTXW windows x kPQ pair groups
 constexpr int kMaxCls = 4;             // bin weight classes (distinct bin weights)
 constexpr int kMaxAcc = 1 + kMaxCls;   // stored sums per window: full window + classes
 
@@ -167,22 +169,25 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
 // UNI: every bin has the same weight, so the bins share one accumulator
 // (accumulator 0: full window, 1: bins); otherwise one per filter while
 // scoring, merged into the stored sums at the end of each row.
-template <int G, bool UNI>
+template <int G, bool UNI, int KG>
 __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int by, int grp) {
+  constexpr int kPQ = KG / 8;                        // pair groups
+  constexpr int kST = kTXW * kPQ;                    // threads
   constexpr int NF = 1 + G * G;
   constexpr int NACC = UNI ? 2 : NF;                 // accumulators while scoring
   constexpr int NOUT = UNI ? 2 : 1 + kMaxCls;        // sums after merging bins of equal weight
   constexpr int NR = G * kPQ;                        // (band, pair group) rows
   static_assert(NR <= kST / 64, "one wave per prefix row");
+  static_assert(kColsMax + 1 <= kST, "one column per thread");
   __shared__ uint4 Qs[NR][kHS];
   __shared__ uint4 Hs[NR][kHS];
-  __shared__ uint16_t red[NOUT][kTXW];               // pair group 1's sums (<= w*h < 2^16)
+  __shared__ uint16_t red[kPQ - 1][NOUT][kTXW];      // pair groups 1..kPQ-1: sums (<= w*h < 2^16)
   const auto labs = gbl(p.labels);
   const auto t16 = gbl(p.t16);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int x0 = bx * p.txw, y0 = by * p.tyw;
-  const int j0 = grp * kKG;
+  const int j0 = grp * KG;
   const int txv = min(p.txw, p.ow - x0), tyv = min(p.tyw, p.oh - y0);
   const int cols = txv + p.w - 1;
   const int nseg = cols / kSL + 1;                   // segments cover [0, cols]
@@ -208,13 +213,13 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
     for (int r = 0; r < 8; ++r) {
       if (r0 + r >= p.h) break;
       while (r0 + r >= p.ye[b + 1]) ++b;
-      if ((unsigned)l8[r] < (unsigned)kKG) atomicAdd(qword(b, l8[r], c), 1u << (16 * (l8[r] & 1)));
+      if ((unsigned)l8[r] < (unsigned)KG) atomicAdd(qword(b, l8[r], c), 1u << (16 * (l8[r] & 1)));
     }
   }
 
   // scoring role: window xl of the tile, pair group pq (uniform per wave)
-  const int pq = wv & 1;
-  const int xl = (wv >> 1) * 64 + lane;
+  const int pq = wv & (kPQ - 1);
+  const int xl = (wv / kPQ) * 64 + lane;
   uint32_t T[NF][4];
 #pragma unroll
   for (int f = 0; f < NF; ++f)
@@ -250,13 +255,15 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
       }
     }
   };
-  // pair group 0 adds group 1's sums and stores them, or with one channel
-  // group forms the score itself
+  // pair group 0 adds the other pair groups' sums and stores them, or with
+  // one channel group forms the score itself
   auto store_row = [&](int yy) {
     uint32_t v[NOUT];
     merge(v);
 #pragma unroll
-    for (int a = 0; a < NOUT; ++a) v[a] += red[a][xl];
+    for (int g2 = 0; g2 < kPQ - 1; ++g2)
+#pragma unroll
+      for (int a = 0; a < NOUT; ++a) v[a] += red[g2][a][xl];
     const int64_t win = (int64_t)yy * p.ow + x0 + xl;
     float s = 0.f;
 #pragma unroll
@@ -325,11 +332,11 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s) acc[0] = min_dot(full[s], T[0][s], acc[0]);
-      if (pq == 1) {
+      if (pq >= 1) {
         uint32_t o[NOUT];
         merge(o);
 #pragma unroll
-        for (int a = 0; a < NOUT; ++a) red[a][xl] = (uint16_t)o[a];
+        for (int a = 0; a < NOUT; ++a) red[pq - 1][a][xl] = (uint16_t)o[a];
       }
     }
     // ---- vertical update of Q to row y + 1, then prefetch for row y + 2
@@ -338,8 +345,8 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
 #pragma unroll
       for (int b = 0; b < G; ++b) {
         if (lo[b] == li[b]) continue;
-        if ((unsigned)lo[b] < (unsigned)kKG) atomicSub(qword(b, lo[b], c), 1u << (16 * (lo[b] & 1)));
-        if ((unsigned)li[b] < (unsigned)kKG) atomicAdd(qword(b, li[b], c), 1u << (16 * (li[b] & 1)));
+        if ((unsigned)lo[b] < (unsigned)KG) atomicSub(qword(b, lo[b], c), 1u << (16 * (lo[b] & 1)));
+        if ((unsigned)li[b] < (unsigned)KG) atomicAdd(qword(b, li[b], c), 1u << (16 * (li[b] & 1)));
       }
       if (dy + 2 < tyv) fetch(y + 2, c);
     }
@@ -349,20 +356,20 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
   if (p.ng == 1) block_max_n<kST / 64>(key, p.best);
 }
 
-template <int G, bool UNI>
-__global__ __launch_bounds__(kST) void score_tile_kernel(TileParams p) {
-  score_tile_body<G, UNI>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+template <int G, bool UNI, int KG>
+__global__ __launch_bounds__(kTXW * (KG / 8)) void score_tile_kernel(TileParams p) {
+  score_tile_body<G, UNI, KG>(p, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Batched: block -> pair from a table, then (group, tile column, tile row)
 // with the channel group fastest.
-template <int G, bool UNI>
-__global__ __launch_bounds__(kST) void score_tile_batch_kernel(const TileParams* __restrict__ tab,
-                                                               const uint32_t* __restrict__ blk) {
+template <int G, bool UNI, int KG>
+__global__ __launch_bounds__(kTXW * (KG / 8)) void score_tile_batch_kernel(const TileParams* __restrict__ tab,
+                                                                           const uint32_t* __restrict__ blk) {
   const TileParams& p = tab[blk[blockIdx.x]];
   const int b = (int)(blockIdx.x - p.b0);
   const int grp = b % p.ng, t = b / p.ng;
-  score_tile_body<G, UNI>(p, t % p.nx, t / p.nx, grp);
+  score_tile_body<G, UNI, KG>(p, t % p.nx, t / p.nx, grp);
 }
 
 typedef unsigned int u32x2_v __attribute__((ext_vector_type(2)));
@@ -496,6 +503,7 @@ namespace {
 struct TilePlan {
   bool ok;
   bool uni;           // every bin has one weight: two sums
+  int kg;             // channels per block (16 or 32)
   int txw;
   int nacc;
   uint32_t cmask[kMaxCls];
@@ -504,12 +512,19 @@ struct TilePlan {
 };
 
 // Tiles are as wide as the LDS rows allow (at most kTXW windows, at least 32).
-TilePlan plan_tile(const DeviceTemplate& t) {
+// wide: 32-channel blocks where they are allowed (single-pair launches with
+// a 3 x 3 grid: on the 1024 x 1024, k = 128 match they score 15% faster; in
+// batches of small tiles, and with 2 x 2 grids whose 32-channel blocks hold
+// one block per compute unit, the 16-channel blocks measured faster).
+TilePlan plan_tile(const DeviceTemplate& t, bool wide = false) {
   TilePlan pl{};
   if (!t.grid.valid) return pl;
   const int G = t.grid.g;
   const int NF = 1 + G * G;
-  if (G < 1 || G > 4 || t.geom.kpad % kKG || t.n_filters != NF) return pl;
+  if (G < 1 || G > 4 || t.geom.kpad % 16 || t.n_filters != NF) return pl;
+  // 32-channel blocks hold 4 G rows of LDS histograms and prefixes (142 KB
+  // at G = 3)
+  pl.kg = (wide && G == 3 && t.geom.kpad % 32 == 0) ? 32 : 16;
   int maxband = 0;
   for (int b = 0; b < G; ++b) maxband = std::max(maxband, t.grid.ye[b + 1] - t.grid.ye[b]);
   pl.txw = std::min(kTXW, kColsMax + 1 - t.w);
@@ -546,6 +561,7 @@ struct PairTables {
   CombineParams cp;
   int G;
   bool uni;
+  int kg;
   int ny;
   int64_t ncblk;   // combine blocks (0: the tile kernel forms the scores)
 };
@@ -577,7 +593,7 @@ void make_pair(const DeviceTemplate& t, const TilePlan& pl, const uint8_t* label
   tp.nacc = pl.nacc;
   for (int c = 0; c < kMaxCls; ++c) tp.cmask[c] = pl.cmask[c];
   tp.nx = nx;
-  tp.ng = t.geom.kpad / kKG;
+  tp.ng = t.geom.kpad / pl.kg;
   for (int a = 0; a < kMaxAcc; ++a) {
     tp.wt[a] = pl.wt[a];
     tp.area2[a] = pl.area2[a];
@@ -587,6 +603,7 @@ void make_pair(const DeviceTemplate& t, const TilePlan& pl, const uint8_t* label
   tp.part = tp.ng > 1 ? part : nullptr;
   o->G = G;
   o->uni = pl.uni;
+  o->kg = pl.kg;
   o->ny = (oh + tp.tyw - 1) / tp.tyw;
   CombineParams& cp = o->cp;
   cp = CombineParams{};
@@ -605,41 +622,67 @@ void make_pair(const DeviceTemplate& t, const TilePlan& pl, const uint8_t* label
 }
 
 size_t partial_bytes(const DeviceTemplate& t, const TilePlan& pl, int H, int W) {
-  const int ng = t.geom.kpad / kKG;
+  const int ng = t.geom.kpad / pl.kg;
   if (ng <= 1) return 0;
   const int64_t nwin = (int64_t)(H - t.h + 1) * (W - t.w + 1);
   return (size_t)ng * pl.nacc * ((nwin + 3) / 4 * 4) * 2;
 }
 
-template <int G, bool UNI>
+template <int G, bool UNI, int KG>
 hipError_t go_tile(const TileParams& tp, int ny, hipStream_t s) {
   const dim3 grid((unsigned)tp.nx, (unsigned)ny, (unsigned)tp.ng);
-  hipLaunchKernelGGL((score_tile_kernel<G, UNI>), grid, dim3(kST), 0, s, tp);
+  hipLaunchKernelGGL((score_tile_kernel<G, UNI, KG>), grid, dim3(kTXW * (KG / 8)), 0, s, tp);
   return hipGetLastError();
 }
 
-template <int G, bool UNI>
+template <int G, bool UNI, int KG>
 hipError_t go_tile_b(const TileParams* tab, const uint32_t* blk, uint32_t nblk, hipStream_t s) {
-  hipLaunchKernelGGL((score_tile_batch_kernel<G, UNI>), dim3(nblk), dim3(kST), 0, s, tab, blk);
+  hipLaunchKernelGGL((score_tile_batch_kernel<G, UNI, KG>), dim3(nblk), dim3(kTXW * (KG / 8)), 0, s, tab, blk);
   return hipGetLastError();
 }
 
-// One pair (tab == nullptr) or a batch.
-hipError_t go_tile_any(int G, bool uni, const TileParams& tp, int ny, const TileParams* tab,
+// One pair (tab == nullptr) or a batch.  32-channel blocks for G <= 3 only.
+hipError_t go_tile_any(int G, bool uni, int kg, const TileParams& tp, int ny, const TileParams* tab,
                        const uint32_t* blk, uint32_t nblk, hipStream_t s) {
-#define VQ_TILE(g, u) return tab ? go_tile_b<g, u>(tab, blk, nblk, s) : go_tile<g, u>(tp, ny, s)
+#define VQ_TILE(g, u, k) return tab ? go_tile_b<g, u, k>(tab, blk, nblk, s) : go_tile<g, u, k>(tp, ny, s)
+  if (kg == 32) {
+    switch (G * 2 + (uni ? 1 : 0)) {
+      case 2: VQ_TILE(1, false, 32);
+      case 3: VQ_TILE(1, true, 32);
+      case 4: VQ_TILE(2, false, 32);
+      case 5: VQ_TILE(2, true, 32);
+      case 6: VQ_TILE(3, false, 32);
+      case 7: VQ_TILE(3, true, 32);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (kg != 16) return hipErrorInvalidValue;
   switch (G * 2 + (uni ? 1 : 0)) {
-    case 2: VQ_TILE(1, false);
-    case 3: VQ_TILE(1, true);
-    case 4: VQ_TILE(2, false);
-    case 5: VQ_TILE(2, true);
-    case 6: VQ_TILE(3, false);
-    case 7: VQ_TILE(3, true);
-    case 8: VQ_TILE(4, false);
-    case 9: VQ_TILE(4, true);
+    case 2: VQ_TILE(1, false, 16);
+    case 3: VQ_TILE(1, true, 16);
+    case 4: VQ_TILE(2, false, 16);
+    case 5: VQ_TILE(2, true, 16);
+    case 6: VQ_TILE(3, false, 16);
+    case 7: VQ_TILE(3, true, 16);
+    case 8: VQ_TILE(4, false, 16);
+    case 9: VQ_TILE(4, true, 16);
     default: return hipErrorInvalidValue;
   }
 #undef VQ_TILE
+}
+
+// Static LDS of a tile block: histograms and prefixes of G * KG / 8 rows,
+// plus the pair groups' hand-over sums.
+size_t tile_lds_bytes(int G, bool uni, int kg) {
+  const int pq = kg / 8;
+  return (size_t)2 * G * pq * kHS * 16 + (size_t)(pq - 1) * (uni ? 2 : kMaxAcc) * kTXW * 2;
+}
+
+// Tile blocks resident per compute unit (160 KB of LDS, 2048 threads).
+int tile_blocks_per_cu(int G, bool uni, int kg) {
+  const int by_threads = 2048 / (kTXW * (kg / 8));
+  const int by_lds = (int)(163840 / std::max<size_t>(tile_lds_bytes(G, uni, kg), 1));
+  return std::max(1, std::min(by_threads, by_lds));
 }
 
 template <int NACC>
@@ -677,19 +720,16 @@ size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W) {
 
 hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out) {
   const DeviceTemplate& t = *a.t;
-  TilePlan pl = plan_tile(t);
+  TilePlan pl = plan_tile(t, true);
   if (!pl.ok) return hipErrorInvalidConfiguration;
   if (partial_bytes(t, pl, a.H, a.W) > 0 && !a.partials) return hipErrorInvalidValue;
   // tile height from the caller (autotuned) or the default
   const int tyw = a.tyw > 0 ? a.tyw : fused_default_tyw(t, a.H, a.W, a.n_cu);
   PairTables pt;
   make_pair(t, pl, a.labels, a.H, a.W, tyw, (uint16_t*)a.partials, a.heatmap, a.best, &pt);
-  if (lds_bytes_out) {
-    const int NR = pt.G * kPQ;
-    *lds_bytes_out = (size_t)2 * NR * kHS * 16 + (size_t)(pl.uni ? 2 : kMaxAcc) * kTXW * 2;
-  }
+  if (lds_bytes_out) *lds_bytes_out = tile_lds_bytes(pt.G, pt.uni, pt.kg);
   timing_begin(K_SCORE_FUSED);
-  hipError_t e = go_tile_any(pt.G, pt.uni, pt.tp, pt.ny, nullptr, nullptr, 0, s);
+  hipError_t e = go_tile_any(pt.G, pt.uni, pt.kg, pt.tp, pt.ny, nullptr, nullptr, 0, s);
   timing_end(K_SCORE_FUSED);
   if (e != hipSuccess || pt.ncblk == 0) return e;
   timing_begin(K_SCORE_COMBINE);
@@ -713,8 +753,8 @@ bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, Scor
     make_pair(*it.t, pls[i], it.labels, it.H, it.W, it.tyw, pp, it.heatmap, it.best, &pts[i]);
     out->part_bytes += align_up(pb, 256);
   }
-  // tile launches per (G, uniform bins); pairs with the largest templates
-  // (the costliest tile set-up) first
+  // tile launches per (G, uniform bins, channels per block); pairs with the
+  // largest templates (the costliest tile set-up) first
   std::vector<size_t> order(items.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
@@ -726,13 +766,14 @@ bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, Scor
     std::memcpy(out->blob.data() + off, src, bytes);
     return off;
   };
+  for (int kg : {32, 16})
   for (int G = 1; G <= 4; ++G)
     for (int u = 0; u < 2; ++u) {
       std::vector<TileParams> tab;
       std::vector<uint32_t> blk;
       for (size_t i : order) {
         PairTables& pt = pts[i];
-        if (pt.G != G || pt.uni != (u == 1)) continue;
+        if (pt.G != G || pt.uni != (u == 1) || pt.kg != kg) continue;
         pt.tp.b0 = (uint32_t)blk.size();
         const int64_t nb = (int64_t)pt.tp.nx * pt.ny * pt.tp.ng;
         if ((int64_t)blk.size() + nb > 0x7FFFFFFF) return false;
@@ -744,6 +785,7 @@ bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, Scor
       l.kind = 0;
       l.G = G;
       l.uni = u;
+      l.kg = kg;
       l.tab_off = put(tab.data(), tab.size() * sizeof(TileParams));
       l.blk_off = put(blk.data(), blk.size() * 4);
       l.nblk = (uint32_t)blk.size();
@@ -778,7 +820,8 @@ hipError_t launch_score_batch(const ScoreBatchPlan& pl, const uint8_t* d_blob, h
     hipError_t e;
     if (l.kind == 0) {
       timing_begin(K_SCORE_FUSED);
-      e = go_tile_any(l.G, l.uni != 0, TileParams{}, 0, (const TileParams*)(d_blob + l.tab_off), blk, l.nblk, s);
+      e = go_tile_any(l.G, l.uni != 0, l.kg, TileParams{}, 0, (const TileParams*)(d_blob + l.tab_off), blk,
+                      l.nblk, s);
       timing_end(K_SCORE_FUSED);
     } else {
       timing_begin(K_SCORE_COMBINE);
@@ -793,13 +836,20 @@ hipError_t launch_score_batch(const ScoreBatchPlan& pl, const uint8_t* d_blob, h
 
 bool fused_supported(const DeviceTemplate& t) { return plan_tile(t).ok; }
 
-// Tiles fill whole rounds of two blocks per compute unit (at least 8 rows).
+int fused_groups(const DeviceTemplate& t) {
+  const TilePlan pl = plan_tile(t);
+  return pl.ok ? t.geom.kpad / pl.kg : t.geom.kpad / 16;
+}
+
+// Tiles fill whole rounds of the blocks resident per compute unit (at least
+// 8 rows).
 int fused_default_tyw(const DeviceTemplate& t, int H, int W, int n_cu) {
-  TilePlan pl = plan_tile(t);
+  TilePlan pl = plan_tile(t, true);
+  if (!pl.ok) return 8;
   const int ow = W - t.w + 1, oh = H - t.h + 1;
   const int nx = (ow + pl.txw - 1) / std::max(pl.txw, 1);
-  const int per_row = nx * (t.geom.kpad / kKG);
-  const int slots = 2 * std::max(n_cu, 1);
+  const int per_row = nx * (t.geom.kpad / pl.kg);
+  const int slots = tile_blocks_per_cu(t.grid.g, pl.uni, pl.kg) * std::max(n_cu, 1);
   const int ny = std::max(1, (slots + per_row - 1) / per_row);
   return std::min(std::max(8, (oh + ny - 1) / ny), std::max(oh, 1));
 }

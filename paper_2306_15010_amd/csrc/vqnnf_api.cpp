@@ -1676,7 +1676,7 @@ int batch_default_tyw(const std::vector<ScoreBatchItem>& items, int n_cu) {
     for (const ScoreBatchItem& it : items) {
       const int ow = it.W - it.t->w + 1, oh = it.H - it.t->h + 1;
       const int64_t nx = (ow + 255) / 256;
-      blocks += nx * ((oh + std::min(cap, oh) - 1) / std::min(cap, oh)) * (it.t->geom.kpad / 16);
+      blocks += nx * ((oh + std::min(cap, oh) - 1) / std::min(cap, oh)) * fused_groups(*it.t);
     }
     if (blocks >= 8LL * n_cu) return cap;
   }

@@ -281,7 +281,7 @@ struct ScoreBatchItem {
 };
 struct ScoreBatchLaunch {
   int kind;                    // 0 tile, 1 combine
-  int G, uni, nacc;
+  int G, uni, kg, nacc;        // kg: channels per tile block
   size_t tab_off, blk_off;     // byte offsets into the table blob
   uint32_t nblk;
 };
@@ -297,6 +297,7 @@ bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, Scor
 hipError_t launch_score_batch(const ScoreBatchPlan& plan, const uint8_t* d_blob, hipStream_t s);
 // True when the on-chip score kernel can take this template's bank.
 bool fused_supported(const DeviceTemplate& t);
+int fused_groups(const DeviceTemplate& t);   // channel groups of the tile score
 // Scratch bytes of the on-chip path's per-channel-group partial sums.
 size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W);
 // Default window rows per tile of the on-chip score for this shape.
