@@ -180,6 +180,9 @@ SCORE_CASES = [
     (40, 40, 40, 40, 2, 5),
     (129, 300, 30, 30, 1, 64),
     (96, 96, 96, 31, 3, 200),
+    # 32-channel blocks: unequal bins with three channel groups, and a wide template
+    (120, 160, 40, 37, 3, 96),
+    (240, 300, 250, 180, 3, 64),
 ]
 
 
