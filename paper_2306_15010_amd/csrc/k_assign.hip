@@ -327,8 +327,6 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
   // epilogue of a finished tile: s_j = ||c_j||^2 + (-2 q.c_j), the norm
   // added once after the products were accumulated from zero
   const __amdgpu_buffer_rsrc_t lab_rs = raw_rsrc(p.labels);
-  const __amdgpu_buffer_rsrc_t wlp_rs = raw_rsrc(p.wl_pix);
-  const __amdgpu_buffer_rsrc_t wlm_rs = raw_rsrc(p.wl_mask);
   auto finish = [&](int64_t tile) {
 #pragma unroll
     for (int mb = 0; mb < KB; ++mb) {
@@ -388,13 +386,16 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
         }
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(p.wl_count, (uint32_t)__popcll(bal));
-        base = __shfl(base, 0);
+        base = __builtin_amdgcn_readfirstlane(__shfl(base, 0));
         if (fl) {
-          const uint32_t slot = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-          __builtin_amdgcn_raw_buffer_store_b32((uint32_t)pix, wlp_rs, (int)(slot * 4), 0, 0);
+          // resources based at the wave's first slot (64-bit pointer
+          // arithmetic), so the 32-bit offsets stay below 64 entries
+          const uint32_t r = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+          __builtin_amdgcn_raw_buffer_store_b32((uint32_t)pix, raw_rsrc(p.wl_pix + base), (int)(r * 4), 0, 0);
+          const __amdgpu_buffer_rsrc_t wlm_rs = raw_rsrc(p.wl_mask + (size_t)base * MW);
 #pragma unroll
           for (int w = 0; w < MW; ++w)
-            __builtin_amdgcn_raw_buffer_store_b32(mw[w], wlm_rs, (int)((slot * MW + w) * 4), 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(mw[w], wlm_rs, (int)((r * MW + w) * 4), 0, 0);
         }
       }
     }

@@ -208,13 +208,15 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
           }
           uint32_t base = 0;
           if (lane == 0) base = atomicAdd(o.wl_count, (uint32_t)__popcll(bal));
-          base = __shfl(base, 0);
+          base = __builtin_amdgcn_readfirstlane(__shfl(base, 0));
           if (fl) {
-            const uint32_t slot = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)pix, raw_rsrc(o.wl_pix), (int)(slot * 4), 0, 0);
+            // resources based at the wave's first slot, offsets below 64 entries
+            const uint32_t r = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)pix, raw_rsrc(o.wl_pix + base), (int)(r * 4), 0, 0);
+            const __amdgpu_buffer_rsrc_t wlm_rs = raw_rsrc(o.wl_mask + (size_t)base * MW);
 #pragma unroll
             for (int w = 0; w < MW; ++w)
-              __builtin_amdgcn_raw_buffer_store_b32(mw[w], raw_rsrc(o.wl_mask), (int)((slot * MW + w) * 4), 0, 0);
+              __builtin_amdgcn_raw_buffer_store_b32(mw[w], wlm_rs, (int)((r * MW + w) * 4), 0, 0);
           }
         }
       }

@@ -3,6 +3,7 @@
 #pragma clang fp contract(off)
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -110,9 +111,14 @@ struct vqnnf_ctx {
   double total_ms[K_COUNT] = {};
 };
 
+// Every template gets an id that is never reused, so plans and graphs keyed
+// on it cannot match a later template that happens to get the same address.
+std::atomic<uint64_t> g_next_template_uid{1};
+
 struct vqnnf_template {
   int magic = kTplMagic;
   vqnnf_ctx* ctx = nullptr;
+  uint64_t uid = g_next_template_uid.fetch_add(1);
   DeviceTemplate t;
 };
 
@@ -1510,7 +1516,7 @@ vqnnf_status build_multi_plan(vqnnf_ctx* c, vqnnf_ctx::MultiPlan& mp, const std:
                                (uint64_t)slot0,
                                (uint64_t)(uintptr_t)c->m_labels.p, (uint64_t)(uintptr_t)c->m_count.p,
                                (uint64_t)(uintptr_t)c->m_wl_pix.p, (uint64_t)(uintptr_t)c->m_wl_mask.p};
-  for (int i : gr) sig.insert(sig.end(), {(uint64_t)(uintptr_t)t[i], (uint64_t)(uintptr_t)sets[i]});
+  for (int i : gr) sig.insert(sig.end(), {t[i]->uid, (uint64_t)(uintptr_t)sets[i]});
   if (sig == mp.sig) return ok();
   // order: largest blocks first, stable within a size
   std::vector<int> order(gr.size());
@@ -1982,7 +1988,7 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     }
     for (int i = 0; i < n; ++i) {
       const vqnnf_fmap& m = *q[i];
-      sig.insert(sig.end(), {(uint64_t)(uintptr_t)t[i], (uint64_t)(uintptr_t)m.data, (uint64_t)m.dtype,
+      sig.insert(sig.end(), {t[i]->uid, (uint64_t)(uintptr_t)m.data, (uint64_t)m.dtype,
                              (uint64_t)m.H, (uint64_t)m.W, (uint64_t)m.D, (uint64_t)m.pixel_stride,
                              (uint64_t)(uintptr_t)sets[i], (uint64_t)(uintptr_t)heatmaps[i]});
     }

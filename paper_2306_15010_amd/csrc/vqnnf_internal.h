@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -98,7 +99,9 @@ struct DeviceTemplate {
   BoundCoef bound_bf16q{};           // BF16-stored query, codebook hi+lo
   BoundCoef bound_f32q{};            // FP32-stored query, both split hi+lo
   std::vector<float> cnorm32;        // [k] ||c||^2 rounded to FP32
-  std::vector<ScaledSet> scaled;     // FP8 tables, one per distinct scale vector
+  // FP8 tables, one per distinct scale vector; a deque keeps every set at a
+  // fixed address while more are added (callers hold pointers to them)
+  std::deque<ScaledSet> scaled;
   // device copies
   void* d_blob = nullptr;            // one allocation holding every table below
   float* d_codebook = nullptr;       // [k][D] FP32
