@@ -286,6 +286,33 @@ vqnnf_status vqnnf_score_integral(vqnnf_ctx* ctx, const vqnnf_template* t,
 vqnnf_status vqnnf_match(vqnnf_ctx* ctx, const vqnnf_template* t, const vqnnf_fmap* query,
                          int32_t prec, float* heatmap, int32_t* best_xy, float* best_score);
 
+/* vqnnf_match for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments and the same results as vqnnf_match, bit for bit, with
+ * every intermediate (label map, re-score worklist and candidate masks,
+ * score partial sums, best-location key) placed in one fixed device array
+ * of VQNNF_NOALLOC_SCRATCH_BYTES that the library holds on each device it
+ * runs on until the process ends.  The call allocates nothing (no hipMalloc,
+ * hipFree or event creation) and does not autotune (it uses a tile height
+ * tuned by an earlier vqnnf_match on the same shape, else the default) or
+ * record kernel timings.
+ *  - VQNNF_ENOMEM when the pair needs more than the array holds: about
+ *    H*W*(1 + 4 + 4*ceil(k/32)) bytes on the refined path (H*W on the plain
+ *    path) plus the score's partial sums, e.g. a 1024 x 1024 map with k = 128
+ *    and a 96 x 96 template takes 35 MB.
+ *  - VQNNF_ENOTSUP for banks the on-chip score does not take (see
+ *    vqnnf_score).
+ *  - FP8 maps: EINVAL unless the template already holds the codebook tables
+ *    of the map's channel scales (built by any vqnnf_assign, vqnnf_match or
+ *    vqnnf_match_batched call with a map of the same scales).
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents (each call clears what must start at zero): calls whose
+ * work overlaps on one device (different streams or contexts, host threads)
+ * race and give wrong results; serialise them. */
+#define VQNNF_NOALLOC_SCRATCH_BYTES ((uint64_t)64 << 20)
+vqnnf_status vqnnf_match_noalloc(vqnnf_ctx* ctx, const vqnnf_template* t, const vqnnf_fmap* query,
+                                 int32_t prec, float* heatmap, int32_t* best_xy, float* best_score);
+
 /* A batch of independent (template, query map) pairs, the whole path for
  * each: t[i] is matched against q[i] into heatmaps[i] (device,
  * (H_i - h_i + 1) x (W_i - w_i + 1) FP32, caller owned), with the same

@@ -26,7 +26,8 @@ EXPORTED = [
     "vqnnf_template_from_codebook", "vqnnf_template_free", "vqnnf_template_info",
     "vqnnf_template_codebook", "vqnnf_template_labels", "vqnnf_template_counts",
     "vqnnf_template_weights", "vqnnf_template_responses", "vqnnf_paper_bank", "vqnnf_assign", "vqnnf_filter", "vqnnf_score",
-    "vqnnf_score_integral", "vqnnf_match", "vqnnf_match_batched", "vqnnf_ctx_set_graph",
+    "vqnnf_score_integral", "vqnnf_match", "vqnnf_match_noalloc", "vqnnf_match_batched",
+    "vqnnf_ctx_set_graph",
     "vqnnf_ctx_set_autotune",
     "vqnnf_ctx_set_timing", "vqnnf_ctx_kernel_times",
     "vqnnf_ctx_reset_times", "vqnnf_last_error", "vqnnf_version",
@@ -86,6 +87,7 @@ def lib() -> C.CDLL:
         "vqnnf_score": (st, [vp, vp, vp, i32, i32, vp, P(i32), P(C.c_float)]),
         "vqnnf_score_integral": (st, [vp, vp, vp, i32, i32, vp, P(i32), P(C.c_float)]),
         "vqnnf_match": (st, [vp, vp, P(FMap), i32, vp, P(i32), P(C.c_float)]),
+        "vqnnf_match_noalloc": (st, [vp, vp, P(FMap), i32, vp, P(i32), P(C.c_float)]),
         "vqnnf_match_batched": (st, [vp, i32, P(vp), P(P(FMap)), i32, P(vp), P(i32), P(C.c_float)]),
         "vqnnf_ctx_set_graph": (st, [vp, i32]),
         "vqnnf_ctx_set_autotune": (st, [vp, i32]),
@@ -385,6 +387,23 @@ def vqnnf_match(ctx: Context, tpl: Template, query: FMap, prec: int, heatmap, wa
     st = lib().vqnnf_match(ctx.h, tpl.h, C.byref(query), prec, C.c_void_p(heatmap.data_ptr()),
                            xy, C.byref(sc))
     return _best_out(st, xy, sc)
+
+
+def vqnnf_match_noalloc(ctx: Context, tpl: Template, query: FMap, prec: int, heatmap, want_best=True):
+    """vqnnf_match with every intermediate in the library's fixed device
+    array (no device allocation); same results."""
+    if not want_best:
+        _check(lib().vqnnf_match_noalloc(ctx.h, tpl.h, C.byref(query), prec,
+                                         C.c_void_p(heatmap.data_ptr()), None, None))
+        return None
+    xy = (C.c_int32 * 2)()
+    sc = C.c_float()
+    st = lib().vqnnf_match_noalloc(ctx.h, tpl.h, C.byref(query), prec, C.c_void_p(heatmap.data_ptr()),
+                                   xy, C.byref(sc))
+    return _best_out(st, xy, sc)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def vqnnf_match_batched(ctx: Context, templates: Sequence[Template], queries: Sequence[FMap],

@@ -12,7 +12,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvqnnf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-DEVICE_SOURCES = ["k_assign.hip", "k_assign_multi.hip", "k_bank.hip", "k_integral.hip", "k_kmeans.hip", "k_lowd.hip", "k_pca.hip", "k_score.hip"]
+DEVICE_SOURCES = ["k_assign.hip", "k_assign_multi.hip", "k_bank.hip", "k_integral.hip", "k_kmeans.hip", "k_lowd.hip", "k_pca.hip", "k_score.hip", "noalloc_scratch.hip"]
 HOST_SOURCES = ["vqnnf_api.cpp", "vqnnf_template.cpp"]
 
 COMMON = ["-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wno-unused-command-line-argument"]

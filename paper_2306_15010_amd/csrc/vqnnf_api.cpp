@@ -629,8 +629,22 @@ vqnnf_status read_best(vqnnf_ctx* c, int ow, int32_t* best_xy, float* best_score
 
 size_t mask_words(const DeviceTemplate& t) { return (size_t)(t.geom.kpad + 31) / 32; }
 
+// Device scratch of one pair's path: by default the context's buffers;
+// vqnnf_match_noalloc points them into its fixed array.
+struct PairBufs {
+  char* control;         // [0]: u64 best key, [8]: u32 worklist counter
+  uint8_t* labels;       // [n_pix]
+  uint32_t* wl_pix;      // [n_pix] re-score worklist
+  uint32_t* wl_mask;     // [n_pix][mask_words] candidate masks
+  void* partials;        // on-chip score partial sums
+};
+PairBufs ctx_bufs(const vqnnf_ctx* c) {
+  return PairBufs{(char*)c->control.p, (uint8_t*)c->labels.p, (uint32_t*)c->wl_pix.p,
+                  (uint32_t*)c->wl_mask.p, c->partials.p};
+}
+
 vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap* q, int prec,
-                        uint8_t* labels, bool counter_zeroed) {
+                        uint8_t* labels, bool counter_zeroed, const PairBufs& b) {
   const DeviceTemplate& t = tp->t;
   AssignArgs a{};
   a.q = q->data;
@@ -657,9 +671,9 @@ vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap
     else HIP_TRY(launch_assign_plain(a, c->stream, c->n_cu));
     return ok();
   }
-  a.wl_count = (uint32_t*)((char*)c->control.p + 8);
-  a.wl_pix = (uint32_t*)c->wl_pix.p;
-  a.wl_mask = (uint32_t*)c->wl_mask.p;
+  a.wl_count = (uint32_t*)(b.control + 8);
+  a.wl_pix = b.wl_pix;
+  a.wl_mask = b.wl_mask;
   a.bound = ss ? ss->bound : (q->dtype == VQNNF_F32) ? t.bound_f32q : t.bound_bf16q;
   if (!counter_zeroed) HIP_TRY(launch_fill_u32(a.wl_count, 0u, 1, c->stream));
   if (lowd) HIP_TRY(launch_assign_lowd(a, true, c->stream));
@@ -701,10 +715,14 @@ vqnnf_status check_score_dims(const vqnnf_template* tp, int H, int W) {
   return ok();
 }
 
+// partials: the on-chip score's partial sums (null: the context's buffer).
+// tune: the first call on a new shape may time tile heights (allocates
+// events); false uses the tuned height if known, else the default sizing.
 vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t* labels,
                                   const int32_t* P, int32_t H, int32_t W, float* heatmap,
                                   unsigned long long* best, bool zeroed,
-                                  const uint16_t* P16 = nullptr) {
+                                  const uint16_t* P16 = nullptr, void* partials = nullptr,
+                                  bool tune = true) {
   ScoreArgs a{};
   a.t = &t->t;
   a.labels = labels;
@@ -714,7 +732,7 @@ vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t*
   a.W = W;
   a.heatmap = heatmap;
   a.best = best;
-  a.partials = c->partials.p;
+  a.partials = partials ? partials : c->partials.p;
   a.n_cu = c->n_cu;
   if (!zeroed) HIP_TRY(launch_zero_u64(a.best, c->stream));
   if (labels) {
@@ -726,7 +744,7 @@ vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t*
     auto it = c->tyw_cache.find(key);
     if (it != c->tyw_cache.end()) {
       a.tyw = it->second;
-    } else if (c->autotune && !c->capturing) {
+    } else if (tune && c->autotune && !c->capturing) {
       // time each candidate tile height twice on this very call (every run
       // writes the same heatmap and key), keep the fastest for the shape
       const int oh = H - d.h + 1;
@@ -838,9 +856,28 @@ vqnnf_status pair_scratch(vqnnf_ctx* c, const vqnnf_template* const* t, const vq
 vqnnf_status enqueue_pair(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap* q, int prec,
                           float* heatmap, unsigned long long* key, bool counter_zeroed) {
   uint8_t* lab = (uint8_t*)c->labels.p;
-  vqnnf_status s = run_assign(c, t, q, prec, lab, counter_zeroed);
+  vqnnf_status s = run_assign(c, t, q, prec, lab, counter_zeroed, ctx_bufs(c));
   if (s) return s;
   return enqueue_score_labels(c, t, lab, q->H, q->W, heatmap, key);
+}
+
+// Byte layout of vqnnf_match_noalloc's fixed scratch for one pair: the
+// control block, the label map, the worklist and masks (refined path) and
+// the score partials, each part 256-byte aligned.
+struct NoAllocLayout {
+  size_t labels, wl_pix, wl_mask, partials, total;
+};
+NoAllocLayout noalloc_layout(const DeviceTemplate& t, int H, int W, int prec) {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t np = (size_t)H * W;
+  const bool refined = prec == VQNNF_PREC_BF16_REFINED;
+  NoAllocLayout l{};
+  l.labels = 256;
+  l.wl_pix = l.labels + al(np);
+  l.wl_mask = l.wl_pix + (refined ? al(np * 4) : 0);
+  l.partials = l.wl_mask + (refined ? al(np * 4 * mask_words(t)) : 0);
+  l.total = l.partials + al(fused_partial_bytes(t, H, W));
+  return l;
 }
 
 }  // namespace
@@ -860,6 +897,8 @@ vqnnf_status vqnnf_ctx_create(void* hip_stream, uint64_t scratch_cap_bytes, vqnn
   HIP_TRY(hipGetDeviceProperties(&prop, dev));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(VQNNF_ENOTSUP, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+  // the fixed scratch of vqnnf_match_noalloc, resolved once per device
+  HIP_TRY(noalloc_scratch_init(dev));
   auto* c = new vqnnf_ctx();
   c->has_device = true;
   c->device = dev;
@@ -1361,7 +1400,7 @@ vqnnf_status vqnnf_assign(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fma
   const ScaledSet* ss;
   if ((s = prepare_scaled(c, t, q, &ss))) return s;
   HookScope hs(c);
-  if ((s = run_assign(c, t, q, prec, labels, false))) return s;
+  if ((s = run_assign(c, t, q, prec, labels, false, ctx_bufs(c)))) return s;
   if (n_flagged) {
     uint32_t cnt = 0;
     if (prec == VQNNF_PREC_BF16_REFINED) {
@@ -1457,6 +1496,56 @@ vqnnf_status vqnnf_match(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap
   HIP_TRY(launch_fill_u32((uint32_t*)c->control.p, 0u, 4, c->stream));
   if ((s = enqueue_pair(c, t, q, prec, heatmap, (unsigned long long*)c->control.p, true))) return s;
   return read_best(c, q->W - t->t.w + 1, best_xy, best_score);
+}
+
+vqnnf_status vqnnf_match_noalloc(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fmap* q,
+                                 int32_t prec, float* heatmap, int32_t* best_xy, float* best_score) {
+  vqnnf_status s;
+  if ((s = check_ctx(c)) || (s = check_tpl(c, t)) || (s = check_query(c, t, q, prec))) return s;
+  prec = search_prec(prec);
+  if (!heatmap) return fail(VQNNF_EINVAL, "null heatmap");
+  if ((s = check_score_dims(t, q->H, q->W))) return s;
+  if (!fused_supported(t->t))
+    return fail(VQNNF_ENOTSUP, "vqnnf_match_noalloc needs a bank the on-chip score takes (full window + "
+                "g x g grid, g <= 4, at most four distinct bin weights)");
+  const NoAllocLayout l = noalloc_layout(t->t, q->H, q->W, prec);
+  if (l.total > kNoAllocScratchBytes)
+    return fail(VQNNF_ENOMEM, "vqnnf_match_noalloc: a %dx%d map with k = %d needs %zu bytes of scratch; "
+                "the fixed scratch holds %zu", q->W, q->H, t->t.k, l.total, kNoAllocScratchBytes);
+  if ((s = need_device(c))) return s;
+  // FP8 maps use the codebook tables of their channel scales, which only an
+  // allocating call can build
+  const ScaledSet* ss = nullptr;
+  if (q->dtype == VQNNF_FP8_E4M3) {
+    for (const ScaledSet& x : t->t.scaled)
+      if (std::memcmp(x.scale.data(), q->channel_scale, sizeof(float) * t->t.D) == 0) ss = &x;
+    if (!ss)
+      return fail(VQNNF_EINVAL, "vqnnf_match_noalloc: the template has no tables for this FP8 map's channel "
+                  "scales; one vqnnf_assign or vqnnf_match call with a map of these scales builds them");
+  }
+  char* base = (char*)noalloc_scratch(c->device);
+  if (!base) return fail(VQNNF_EHIP, "the fixed scratch of device %d was not resolved", c->device);
+  const PairBufs b{base, (uint8_t*)(base + l.labels), (uint32_t*)(base + l.wl_pix),
+                   (uint32_t*)(base + l.wl_mask), base + l.partials};
+  unsigned long long* key = (unsigned long long*)b.control;
+  // the array keeps the previous call's contents: clear the best key and the
+  // worklist counter with a kernel (graph-capturable, no memset node)
+  HIP_TRY(launch_fill_u32((uint32_t*)b.control, 0u, 4, c->stream));
+  if ((s = run_assign(c, t, q, prec, b.labels, true, b))) return s;
+  if ((s = enqueue_score(c, t, b.labels, nullptr, q->H, q->W, heatmap, key, true, nullptr, b.partials, false)))
+    return s;
+  if (!best_xy && !best_score) return ok();
+  unsigned long long hk = 0;
+  HIP_TRY(hipMemcpyAsync(&hk, key, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const uint32_t ow = (uint32_t)(q->W - t->t.w + 1);
+  const uint32_t idx = 0xFFFFFFFFu - (uint32_t)(hk & 0xFFFFFFFFu);
+  if (best_xy) {
+    best_xy[0] = (int32_t)(idx % ow);
+    best_xy[1] = (int32_t)(idx / ow);
+  }
+  if (best_score) *best_score = unpack_score(hk);
+  return ok();
 }
 
 }  // extern "C"

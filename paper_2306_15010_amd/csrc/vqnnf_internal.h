@@ -325,6 +325,13 @@ struct KmJob {
 };
 hipError_t launch_kmeans(const KmJob* d_jobs, const std::vector<KmJob>& jobs, int iters, hipStream_t s);
 
+// Fixed scratch of vqnnf_match_noalloc: a static device array of this size
+// per device.  noalloc_scratch_init (device current) resolves its address
+// once per device; noalloc_scratch returns it (null before the init).
+constexpr size_t kNoAllocScratchBytes = (size_t)VQNNF_NOALLOC_SCRATCH_BYTES;
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch(int device);
+
 // Kernel-name registry for timing.
 enum KernelId {
   K_FILL = 0, K_ASSIGN_PLAIN, K_ASSIGN_REFINED, K_RESCORE, K_INT_EDGE, K_INT_PREFIX,
