@@ -273,13 +273,27 @@ def colour_leg(ctx, B, synth, steps, torch):
     return out
 
 
-def batched_bench(args, ctx, B, synth, torch):
+def stored_label_hashes(workload):
+    """Per-pair SHA-256 of the oracle's full-size label maps (written by
+    tests/golden/make_fullsize_golden.py from the oracle alone), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "fullsize_labels.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f).get(workload)
+    if not g:
+        return None
+    return [p["labels_sha256"] for m in g["maps"] for p in m["pairs"]]
+
+
+def batched_leg(workload, scale_down, steps, warmup, ctx, B, synth, torch, with_cpu=False):
     """Batched workloads: every (template, map) pair in one vqnnf_match_batched
     call, replayed as one captured HIP graph, against the same pairs as
     sequential vqnnf_match calls."""
-    log(f"generating workload {args.workload} (map sides / {args.scale_down})")
+    import hashlib
+    log(f"generating workload {workload} (map sides / {scale_down})")
     t0 = time.perf_counter()
-    wl = synth.make_config(args.workload, scale_down=args.scale_down,
+    wl = synth.make_config(workload, scale_down=scale_down,
                            progress=lambda i, n: log(f"  map {i} of {n} made"))
     log(f"  {time.perf_counter() - t0:.1f} s")
     tpls, fms, heats, devs = [], [], [], []
@@ -287,7 +301,8 @@ def batched_bench(args, ctx, B, synth, torch):
     torch.cuda.synchronize()
     tp0 = time.perf_counter()
     # every template's k-means (and NNF) in one batched call on the GPU
-    tpls = B.vqnnf_codebook_batched(ctx, [t.data for t in flat], [t.k for t in flat], 20, [0] * len(flat),
+    tpls = B.vqnnf_codebook_batched(ctx, [t.data for t in flat], [t.k for t in flat], 20,
+                                    list(range(len(flat))),
                                     [B.default_bank(t.data.shape[1], t.data.shape[0], t.grid) for t in flat])
     prep_s = time.perf_counter() - tp0
     for qm, row in zip(wl.maps, wl.templates):
@@ -326,13 +341,26 @@ def batched_bench(args, ctx, B, synth, torch):
 
     log("timing: graph-captured batch")
     B.vqnnf_ctx_set_graph(ctx, True)
-    ms_graph = timed(bat, args.steps, args.warmup)
+    ms_graph = timed(bat, steps, warmup)
     out = B.vqnnf_match_batched(ctx, tpls, fms, P, heats)
     B.vqnnf_ctx_set_graph(ctx, False)
+    # the batch's label maps against the oracle's (stored hashes, full size only)
+    stored = stored_label_hashes(workload) if scale_down == 1 else None
+    labels_ok = None
+    if stored is not None and len(stored) == len(tpls):
+        labels_ok = 0
+        pi = 0
+        for qm, row in zip(wl.maps, wl.templates):
+            lab = torch.empty(qm.H * qm.W, dtype=torch.uint8, device="cuda")
+            for _ in row:
+                B.vqnnf_batched_labels(ctx, pi, lab)
+                torch.cuda.synchronize()
+                labels_ok += hashlib.sha256(lab.cpu().numpy().tobytes()).hexdigest() == stored[pi]
+                pi += 1
     log("timing: eager batch")
-    ms_eager = timed(bat, args.steps, args.warmup)
+    ms_eager = timed(bat, steps, warmup)
     log("timing: sequential vqnnf_match calls")
-    ms_seq = timed(seq, args.steps, args.warmup)
+    ms_seq = timed(seq, steps, warmup)
     ctx.reset_times()
     ctx.set_timing(True)
     bat()
@@ -346,9 +374,9 @@ def batched_bench(args, ctx, B, synth, torch):
             found += int(out[i][0] == (t.x0, t.y0))
             i += 1
     cpu = None
-    if not args.no_cpu_baseline:
+    if with_cpu:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(wl)
+        cpu = cpu_baseline_sample(wl)
     # dominant kernel of the batch: the fused multi-template assignment, a
     # dense contraction of 2*k*D flop per (pixel, template); the refined path
     # executes it twice (high and low BF16 terms of the codebook)
@@ -362,28 +390,33 @@ def batched_bench(args, ctx, B, synth, torch):
                 "executed_tflops": 2.0 * ach, "kernel_ms_per_batch": ms_am}
     value = pair_px / (ms_graph / 1e3)
     res = {
-        "metric": METRIC, "value": value, "unit": "px/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": value, "unit": "px/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp8" if wl.maps[0].dtype == "fp8" else "bf16",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {len(wl.maps)} map(s), {len(tpls)} (template, map) "
-                               f"pairs, D={wl.maps[0].D} {wl.maps[0].dtype}, map sides / {args.scale_down}",
+        "config": {"workload": f"{workload}: {len(wl.maps)} map(s), {len(tpls)} (template, map) "
+                               f"pairs, D={wl.maps[0].D} {wl.maps[0].dtype}, map sides / {scale_down}",
                    "global_batch": len(tpls), "pair_pixels": pair_px, "map_pixels": map_px,
                    "prec": "bf16_refined"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "map_px_per_s": map_px / (ms_graph / 1e3),
         "graph_batch_ms": ms_graph, "eager_batch_ms": ms_eager, "sequential_ms": ms_seq,
+        "sequential_value": pair_px / (ms_seq / 1e3),
         "speedup_vs_sequential": ms_seq / ms_graph,
+        "labels_equal_to_oracle": (f"{labels_ok} of {len(tpls)} pairs (stored oracle hashes)"
+                                   if labels_ok is not None else None),
         "planted_found": f"{found} of {len(tpls)}",
         "kernels_total_ms": {k: round(v[1], 4) for k, v in kt.items()},
         "kernel_launches": {k: v[0] for k, v in kt.items()},
         "template_prep_s": prep_s,
     }
-    print(json.dumps(res), flush=True)
+    for tp in tpls:
+        tp.free()
+    return res
 
 
-def cpu_baseline(wl, budget_px=256 * 256):
+def cpu_baseline_sample(wl, budget_px=256 * 256):
     """The oracle as it stands on a bounded sample of the same workload: the
     top-left 256x256 pixels of the query (assign, integral image, filter bank,
     scores of every window inside the sample, argmax).  Batched workloads use
@@ -413,6 +446,60 @@ def cpu_baseline(wl, budget_px=256 * 256):
     return {"value": n / dt, "unit": "px/s", "cores": 1, "kind": "oracle",
             "sample": f"top-left {side}x{side} pixels of the query map ({n} px, "
                       f"{sim.size} windows), FP64 numpy, single thread, {dt:.1f} s"}
+
+
+def oracle_heatmap_bands(O, labels, k, w, h, filters, rt, n_threads, band=64):
+    """The oracle's eq. 2 for every window from row bands of the label map (a
+    window depends only on the labels inside it), bands on n_threads threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    H, W = labels.shape
+    oh = H - h + 1
+    out = np.empty((oh, W - w + 1))
+
+    def one(y0):
+        y1 = min(oh, y0 + band)
+        out[y0:y1] = O.similarity_map_fast(labels[y0:y1 + h - 1], k, w, h, filters, rt)
+
+    with ThreadPoolExecutor(max_workers=n_threads) as ex:
+        list(ex.map(one, range(0, oh, band)))
+    return out
+
+
+def cpu_baseline_full(qm, t, gpu_labels, gpu_heat):
+    """The oracle on the whole workload, on every host core the process may
+    use: FP64 assignment of every pixel (the oracle's C variant, bit-identical
+    to the Python oracle), integral images, filter bank, eq. 2 for every
+    window and the argmax (the Python oracle over row bands).  Template prep
+    (k-means, template NNF and counts) is not timed, as on the GPU.  Also
+    reports the GPU's label mismatches and heatmap error against it."""
+    from oracle import vqnnf_oracle as O
+    from oracle import vqnnf_oracle_c as OC
+    cores = len(os.sched_getaffinity(0))
+    h, w, D = t.data.shape
+    cb64 = OC.kmeans_codebook(t.data, t.k, 20, seed=0).astype(np.float64)
+    filters = O.expand_bank(O.default_bank(w, h, t.grid))
+    tl = O.assign_map(t.data.astype(np.float64), cb64)
+    rt = O.template_representation(tl, t.k, filters)
+    t0 = time.perf_counter()
+    ql = OC.assign_map(qm.dtype, qm.data, qm.scale, cb64, n_threads=cores)
+    t1 = time.perf_counter()
+    sim = oracle_heatmap_bands(O, ql.astype(np.int64), t.k, w, h, filters, rt, cores)
+    bx, by, _ = O.localise(sim)
+    t2 = time.perf_counter()
+    n = qm.H * qm.W
+    err = np.abs(gpu_heat.reshape(sim.shape).astype(np.float64) - sim)
+    rel = err / np.maximum(np.abs(sim), 2.0 ** -24)
+    return {"value": n / (t2 - t0), "unit": "px/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole workload: all {n} query pixels and {sim.size} windows; FP64 "
+                      f"assignment (oracle C variant, {cores} threads) {t1 - t0:.1f} s, integral "
+                      f"images + filter bank + eq. 2 + argmax (Python oracle, {cores} threads over "
+                      f"row bands) {t2 - t1:.1f} s",
+            "seconds": t2 - t0,
+            "label_mismatches_vs_gpu": int((ql.reshape(-1) != gpu_labels.reshape(-1)).sum()),
+            "similarity_abs_err_max": float(err.max()),
+            "similarity_abs_err_p999": float(np.quantile(err, 0.999)),
+            "similarity_rel_err_max": float(rel.max()),
+            "oracle_best": [int(bx), int(by)]}
 
 
 def main():
@@ -447,8 +534,10 @@ def main():
     if args.workload in ("c4", "c5"):
         # the full batches need more scratch than the default cap (re-score
         # worklists and partial sums of every pair at once)
-        batched_bench(args, B.Context(stream=torch.cuda.current_stream(), scratch_cap=64 << 30), B, synth,
-                      torch)
+        res = batched_leg(args.workload, args.scale_down, args.steps, args.warmup,
+                          B.Context(stream=torch.cuda.current_stream(), scratch_cap=64 << 30), B, synth,
+                          torch, with_cpu=not args.no_cpu_baseline)
+        print(json.dumps(res), flush=True)
         return
     log(f"generating workload {args.workload}")
     wl = synth.make_config(args.workload)
@@ -495,6 +584,9 @@ def main():
     best, bscore = B.vqnnf_match(ctx, tpl, fm, P, heat)
     lab = torch.empty(n_pix, dtype=torch.uint8, device="cuda")
     n_flag = B.vqnnf_assign(ctx, tpl, fm, P, lab)
+    # the refined path's results, kept for the oracle comparison (later legs
+    # reuse the heatmap buffer)
+    gpu_heat, gpu_lab = heat.cpu().numpy(), lab.cpu().numpy()
     value = n_pix / (ms / 1e3)
 
     kernels = {k: {"launches": v[0], "avg_ms": v[1] / max(1, v[0])} for k, v in kt.items()}
@@ -504,6 +596,9 @@ def main():
     roof = kernel_roofline(dom, kernels[dom]["avg_ms"], n_pix, D, qbytes, t.k, 2, oh * ow, n_f)
     roof = dict(roof) if roof else {}
     roof["kernel"] = dom
+    roof["duration_source"] = (f"HIP events on the context stream around each launch, mean of "
+                               f"{kernels[dom]['launches']} launches")
+    roof["avg_ms"] = kernels[dom]["avg_ms"]
     roof["traffic"] = measured_traffic(dom, args.workload)
     others = {}
     for k2 in kernels:
@@ -533,11 +628,15 @@ def main():
         log("timing the low-dimensional (PCA) and colour-feature workloads")
         sec["low_d"] = low_d_leg(ctx, B, t, qd, qm, max(5, args.steps // 2), torch)
         sec["colour"] = colour_leg(ctx, B, synth, max(5, args.steps // 2), torch)
+        log("timing the 64-template batch (c4): graph, eager, sequential")
+        bctx = B.Context(stream=stream, scratch_cap=64 << 30)
+        sec["c4_batched"] = batched_leg("c4", 1, max(5, args.steps // 2), 2, bctx, B, synth, torch)
+        bctx.close()
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(wl)
+        log("timing the CPU oracle on the whole workload (all host cores)")
+        cpu = cpu_baseline_full(qm, t, gpu_lab, gpu_heat)
 
     out = {
         "metric": METRIC, "value": value, "unit": "px/s", "n_gpus": 1, "steps": args.steps,

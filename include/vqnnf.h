@@ -336,6 +336,37 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* ctx, int32_t n_pairs, const vqnnf_te
                                  const vqnnf_fmap* const* q, int32_t prec, float* const* heatmaps,
                                  int32_t* best_xy, float* best_score);
 
+/* The NNF label map (Alg. 1) that the last vqnnf_match_batched call on this
+ * context computed for pair `pair`, copied into `labels` (DEVICE uint8
+ * [H*W] of that pair's map) on the context stream, after that call's work.
+ * Kept for pairs whose assignment ran in a fused multi-template launch
+ * (refined search, BF16 or FP8 maps with D a multiple of 64 and aligned
+ * rows, maps shared by at least two pairs); other pairs return
+ * VQNNF_ENOTSUP (their label map is scratch reused pair by pair).  EINVAL
+ * when `pair` is outside the last call.  Valid until the next batched call
+ * on the context. */
+vqnnf_status vqnnf_batched_labels(vqnnf_ctx* ctx, int32_t pair, uint8_t* labels);
+
+/* Test support for the error bound of the refined search.  With a buffer
+ * set, every refined matrix-core assignment on this context (BF16, FP32 and
+ * FP8 maps; not the direct-distance path of D <= 32 or RGB maps) also writes
+ * each pixel's FP32 scores s~_j = ||c_j||^2 - 2 q.c_j, the values the
+ * error bound is applied to, to scores[pix * kpad + j] (DEVICE float,
+ * kpad = k rounded up to a multiple of 16; entries j >= k are padding).  A
+ * call whose map needs more than `capacity` floats returns EINVAL.  NULL
+ * turns it off. */
+vqnnf_status vqnnf_ctx_set_debug_scores(vqnnf_ctx* ctx, float* scores, int64_t capacity);
+
+/* The error bound of the refined search for maps of storage `dtype`
+ * (VQNNF_BF16, VQNNF_F32, or VQNNF_FP8_E4M3 with its HOST channel_scale[D]):
+ * out[0..2] = a0, a1, a2 of the flag threshold
+ * T(n) = a0 + n * (a1 + n * a2), n an upper bound of the pixel's norm (of
+ * the stored values: the E4M3 codes' values for FP8 maps); out[3..4] = A0, A1
+ * of the per-codeword score bound |s~_j - s_j| <= A0 + A1 * n that T is
+ * built from (T also covers the FP64 rule's own rounding).  Host only. */
+vqnnf_status vqnnf_template_score_bound(const vqnnf_template* t, int32_t dtype, const float* channel_scale,
+                                        double* out);
+
 /* Autotuning of the on-chip score's tile height (1 = on, the default): the
  * first call for a shape (template size, grid, codebook size, map size; for
  * a batched score launch, the shapes of all its pairs) times a few tile

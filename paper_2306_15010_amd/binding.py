@@ -27,7 +27,8 @@ EXPORTED = [
     "vqnnf_template_codebook", "vqnnf_template_labels", "vqnnf_template_counts",
     "vqnnf_template_weights", "vqnnf_template_responses", "vqnnf_paper_bank", "vqnnf_assign", "vqnnf_filter", "vqnnf_score",
     "vqnnf_score_integral", "vqnnf_match", "vqnnf_match_noalloc", "vqnnf_match_batched",
-    "vqnnf_ctx_set_graph",
+    "vqnnf_ctx_set_graph", "vqnnf_batched_labels", "vqnnf_ctx_set_debug_scores",
+    "vqnnf_template_score_bound",
     "vqnnf_ctx_set_autotune",
     "vqnnf_ctx_set_timing", "vqnnf_ctx_kernel_times",
     "vqnnf_ctx_reset_times", "vqnnf_last_error", "vqnnf_version",
@@ -90,6 +91,9 @@ def lib() -> C.CDLL:
         "vqnnf_match_noalloc": (st, [vp, vp, P(FMap), i32, vp, P(i32), P(C.c_float)]),
         "vqnnf_match_batched": (st, [vp, i32, P(vp), P(P(FMap)), i32, P(vp), P(i32), P(C.c_float)]),
         "vqnnf_ctx_set_graph": (st, [vp, i32]),
+        "vqnnf_batched_labels": (st, [vp, i32, vp]),
+        "vqnnf_ctx_set_debug_scores": (st, [vp, vp, i64]),
+        "vqnnf_template_score_bound": (st, [vp, i32, vp, vp]),
         "vqnnf_ctx_set_autotune": (st, [vp, i32]),
         "vqnnf_ctx_set_timing": (st, [vp, i32]),
         "vqnnf_ctx_kernel_times": (st, [vp, i32, P(C.c_char_p), P(i64), P(C.c_double), P(i32)]),
@@ -404,6 +408,30 @@ def vqnnf_match_noalloc(ctx: Context, tpl: Template, query: FMap, prec: int, hea
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def vqnnf_ctx_set_debug_scores(ctx: Context, scores=None):
+    """Test support: refined assignments on ctx also write their FP32 scores
+    into the float32 device tensor `scores` ([n_pix][kpad]); None turns it off."""
+    if scores is None:
+        _check(lib().vqnnf_ctx_set_debug_scores(ctx.h, None, 0))
+    else:
+        _check(lib().vqnnf_ctx_set_debug_scores(ctx.h, C.c_void_p(scores.data_ptr()), scores.numel()))
+
+
+def vqnnf_template_score_bound(tpl: Template, dtype: str, channel_scale=None):
+    """(a0, a1, a2, A0, A1) of the refined search's bound for maps of `dtype`."""
+    out = np.zeros(5, dtype=np.float64)
+    sc = None if channel_scale is None else np.ascontiguousarray(channel_scale, dtype=np.float32)
+    _check(lib().vqnnf_template_score_bound(tpl.h, _DT[dtype], sc.ctypes.data if sc is not None else None,
+                                            out.ctypes.data))
+    return tuple(float(v) for v in out)
+
+
+def vqnnf_batched_labels(ctx: Context, pair: int, labels):
+    """Copies pair `pair`'s label map of the last batched call into the
+    device tensor `labels` (uint8, H*W), on the context stream."""
+    _check(lib().vqnnf_batched_labels(ctx.h, pair, C.c_void_p(labels.data_ptr())))
 
 
 def vqnnf_match_batched(ctx: Context, templates: Sequence[Template], queries: Sequence[FMap],

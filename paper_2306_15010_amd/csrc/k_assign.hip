@@ -78,6 +78,8 @@ struct KParams {
   uint32_t* wl_pix;
   uint32_t* wl_mask;
   float a0, a1, a2;
+  float* dump;             // refined path, test support: s~_j to dump[pix * dump_stride + j]
+  int dump_stride;
 };
 
 // Loads NE consecutive query elements of one pixel starting at element d0,
@@ -335,6 +337,16 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[mb][nb][i] = c0[i] + acc[mb][nb][i];
+    }
+    if (p.dump) {   // test support: the scores the bound is applied to
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int64_t pix = tile * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
+        if (pix < p.n_pix)
+#pragma unroll
+          for (int mb = 0; mb < KB; ++mb)
+            *(f32x4_t*)(p.dump + pix * p.dump_stride + 16 * mb + 4 * g) = acc[mb][nb];
+      }
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
@@ -957,6 +969,8 @@ hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu) {
   kp.a0 = a.bound.a0;
   kp.a1 = a.bound.a1;
   kp.a2 = a.bound.a2;
+  kp.dump = a.dump;
+  kp.dump_stride = g.kpad;
   const int qt = qtype(a.dtype);
   // full load groups: D a multiple of two K-steps of 32, rows aligned to the
   // query load width (16 bytes; 8 for FP8 codes)

@@ -88,6 +88,9 @@ struct vqnnf_ctx {
     std::vector<int> slot_pair;        // output slot -> index in the map group
   };
   std::vector<MultiPlan> mplans;       // one per map group of the last batch
+  // label map (and its size) of every pair of the last batch whose
+  // assignment ran fused; null for the others
+  std::vector<std::pair<const uint8_t*, int64_t>> batch_labels;
   // batched re-score and score of the fused groups' pairs
   Buffer b_part;       // partial sums of every pair's on-chip score
   Buffer b_tab;        // argument tables (re-score, then score)
@@ -103,6 +106,9 @@ struct vqnnf_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<uint64_t> gsig;
+  // test support: scores of the refined matrix-core assignment
+  float* dbg_scores = nullptr;
+  int64_t dbg_cap = 0;
   // timing
   bool timing = false;
   std::vector<TimingRecord> pending;
@@ -676,6 +682,12 @@ vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap
   a.wl_mask = b.wl_mask;
   a.bound = ss ? ss->bound : (q->dtype == VQNNF_F32) ? t.bound_f32q : t.bound_bf16q;
   if (!counter_zeroed) HIP_TRY(launch_fill_u32(a.wl_count, 0u, 1, c->stream));
+  if (c->dbg_scores && !lowd) {
+    if (a.n_pix * (int64_t)t.geom.kpad > c->dbg_cap)
+      return fail(VQNNF_EINVAL, "debug score buffer holds %lld floats; this map needs %lld",
+                  (long long)c->dbg_cap, (long long)(a.n_pix * t.geom.kpad));
+    a.dump = c->dbg_scores;
+  }
   if (lowd) HIP_TRY(launch_assign_lowd(a, true, c->stream));
   else HIP_TRY(launch_assign_refined(a, c->stream, c->n_cu));
   HIP_TRY(launch_rescore(a, c->stream, c->n_cu));
@@ -1740,6 +1752,7 @@ void fused_work(vqnnf_ctx* c, const vqnnf_ctx::MultiPlan& mp, const std::vector<
     const DeviceTemplate& d = t[i]->t;
     const int64_t px0 = lab0 + (int64_t)slot * n_pix;
     uint8_t* lab = (uint8_t*)c->m_labels.p + px0;
+    if ((size_t)i < c->batch_labels.size()) c->batch_labels[i] = {lab, n_pix};
     AssignArgs a{};
     a.q = q0->data;
     a.stride = map_stride(q0);
@@ -1825,6 +1838,7 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     if (!heatmaps[i]) return fail(VQNNF_EINVAL, "pair %d: null heatmap", i);
   }
   prec = search_prec(prec);
+  c->batch_labels.assign((size_t)n, {nullptr, 0});
   if ((s = pair_scratch(c, t, q, n, prec, 64))) return s;
   std::vector<const ScaledSet*> sets((size_t)n);
   for (int i = 0; i < n; ++i)
@@ -2122,6 +2136,58 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     }
     if (best_score) best_score[i] = unpack_score(hk[i]);
   }
+  return ok();
+}
+
+vqnnf_status vqnnf_batched_labels(vqnnf_ctx* c, int32_t pair, uint8_t* labels) {
+  vqnnf_status s;
+  if ((s = check_ctx(c))) return s;
+  if (!labels) return fail(VQNNF_EINVAL, "null labels");
+  if (pair < 0 || (size_t)pair >= c->batch_labels.size())
+    return fail(VQNNF_EINVAL, "pair %d is outside the last batched call (%zu pairs)", pair, c->batch_labels.size());
+  const auto& e = c->batch_labels[pair];
+  if (!e.first)
+    return fail(VQNNF_ENOTSUP, "pair %d was matched on its own; its label map is not kept", pair);
+  if ((s = need_device(c))) return s;
+  HIP_TRY(hipMemcpyAsync(labels, e.first, (size_t)e.second, hipMemcpyDeviceToDevice, c->stream));
+  return ok();
+}
+
+vqnnf_status vqnnf_ctx_set_debug_scores(vqnnf_ctx* c, float* scores, int64_t capacity) {
+  vqnnf_status s;
+  if ((s = check_ctx(c))) return s;
+  if (scores && capacity < 1) return fail(VQNNF_EINVAL, "capacity must be >= 1");
+  c->dbg_scores = scores;
+  c->dbg_cap = scores ? capacity : 0;
+  return ok();
+}
+
+vqnnf_status vqnnf_template_score_bound(const vqnnf_template* t, int32_t dtype, const float* channel_scale,
+                                        double* out) {
+  vqnnf_status s = check_tpl(nullptr, t);
+  if (s) return s;
+  if (!out) return fail(VQNNF_EINVAL, "null output");
+  BoundCoef b;
+  if (dtype == VQNNF_BF16) {
+    b = t->t.bound_bf16q;
+  } else if (dtype == VQNNF_F32) {
+    b = t->t.bound_f32q;
+  } else if (dtype == VQNNF_FP8_E4M3) {
+    if (!channel_scale) return fail(VQNNF_EINVAL, "FP8 needs channel_scale");
+    for (int d = 0; d < t->t.D; ++d)
+      if (!std::isfinite(channel_scale[d]) || channel_scale[d] < 0.0f)
+        return fail(VQNNF_EINVAL, "channel_scale[%d] must be finite and >= 0", d);
+    std::vector<uint16_t> fb;
+    std::vector<float> ff;
+    build_scaled_tables(t->t, channel_scale, fb, ff, b);
+  } else {
+    return fail(VQNNF_EINVAL, "dtype %d has no matrix-core bound", dtype);
+  }
+  out[0] = b.a0;
+  out[1] = b.a1;
+  out[2] = b.a2;
+  out[3] = b.A0;
+  out[4] = b.A1;
   return ok();
 }
 

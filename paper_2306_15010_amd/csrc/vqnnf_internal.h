@@ -38,6 +38,10 @@ AssignGeom make_assign_geom(int k, int D);
 // same threshold.  Constants are rounded up.
 struct BoundCoef {
   float a0, a1, a2;
+  // host only: the per-codeword score bound behind the threshold,
+  // |s~_j - s_j| <= A0 + A1 * ||q|| for every codeword j (before the FP64
+  // rule's own rounding and the safety factors are added)
+  double A0, A1;
 };
 
 // Filter geometry for the on-chip score kernel: the bank must be the full
@@ -167,6 +171,7 @@ struct AssignArgs {
   uint32_t* wl_mask;     // [n_pix][mask_words]
   int mask_words;        // 0: ceil(kpad / 32); the fused multi-template kernel writes its own count
   BoundCoef bound;
+  float* dump;           // refined matrix-core path, test support: s~ [n_pix][kpad] or null
 };
 
 // Fused assignment of several templates against one map (batched matching).

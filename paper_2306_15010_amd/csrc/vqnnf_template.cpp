@@ -269,6 +269,8 @@ BoundCoef make_bound(const DeviceTemplate& t, const std::vector<double>& cmul,
   // absolute floor far above any such effect for finite inputs
   A0 += 1e-30;
   BoundCoef b;
+  b.A0 = A0;
+  b.A1 = A1;
   const double s = 1.0 + 0x1.0p-10;
   // 2*E64 with ||q|| <= smax*||e||: 2*gam64*(smax*||e|| + ||c||)^2
   b.a0 = round_up_f32(s * (2.0 * A0 + 2.0 * gam64 * cmax * cmax));

@@ -128,9 +128,33 @@ _E4M3_POS = _E4M3[:0x7F]  # codes 0x00..0x7E, increasing, 0 .. 448
 
 def f32_to_e4m3fn(x: np.ndarray) -> np.ndarray:
     """Encode finite values to OCP E4M3FN codes: round to nearest even,
-    saturating at +-448.  |x| = m * 2^e with m in [1, 2): normal codes
-    (e >= -6) keep rint(8m) in [8, 16] (16 carries into the exponent),
-    subnormals rint(|x| * 2^9) on the 2^-9 grid."""
+    saturating at +-448.  |x| >= 2^-6 (normal codes): the binary64 pattern
+    rounded to 3 mantissa bits, ties to even, by integer addition (a carry
+    out of the mantissa moves into the exponent), exponent rebiased from 1023
+    to 7; |x| < 2^-6: rint(|x| * 2^9) on the subnormal 2^-9 grid.  Returns
+    the same codes as the frexp form below, several times faster."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    np.minimum(a, 448.0, out=a)
+    b = a.view(np.int64)
+    r = b >> 49
+    r &= 1
+    r += b
+    r += (1 << 48) - 1
+    r >>= 49
+    r -= (1023 - 7) << 3
+    small = a < 2.0 ** -6
+    if small.any():
+        r[small] = np.rint(a[small] * 512.0).astype(np.int64)
+    code = r.astype(np.uint8)            # every code is in 0..0x7E here
+    code[(x < 0) & (code != 0)] |= np.uint8(0x80)
+    return code
+
+
+def f32_to_e4m3fn_frexp(x: np.ndarray) -> np.ndarray:
+    """The same encoding written with frexp: |x| = m * 2^e with m in [1, 2):
+    normal codes (e >= -6) keep rint(8m) in [8, 16] (16 carries into the
+    exponent), subnormals rint(|x| * 2^9) on the 2^-9 grid."""
     x = np.asarray(x, dtype=np.float64)
     a = np.minimum(np.abs(x), 448.0)
     m, e = np.frexp(a)                          # a = m * 2^e, m in [0.5, 1)
@@ -262,7 +286,8 @@ def make_single(name: str, seed: int, H: int, W: int, D: int, M: int, sigma: flo
 CONFIGS = ("c1", "c2", "c3", "c4", "c5")
 
 
-def make_config(name: str, seed: Optional[int] = None, scale_down: int = 1, progress=None) -> Workload:
+def make_config(name: str, seed: Optional[int] = None, scale_down: int = 1, progress=None,
+                maps: Optional[List[int]] = None) -> Workload:
     """Workloads shaped like the five benchmark configurations.
 
     c1: 64x64, D=27, FP32, 32 components, 16x16 template, k=8, full + 2x2 grid.
@@ -276,7 +301,9 @@ def make_config(name: str, seed: Optional[int] = None, scale_down: int = 1, prog
         per-channel scales, 128 components; 4 templates per map, sides
         U{32..128}, k=64, full + 3x3 grid.
     `scale_down` divides map sides (tests use it for reduced-size variants);
-    `progress(done, total)`, if given, is called as the maps of c5 are made.
+    `progress(done, total)`, if given, is called as the maps of c5 are made;
+    `maps` (c5 only) makes just those maps (each map has its own streams, so a
+    subset is the same bytes as in the whole set).
     """
     idx = CONFIGS.index(name)
     if seed is None:
@@ -295,7 +322,7 @@ def make_config(name: str, seed: Optional[int] = None, scale_down: int = 1, prog
                                    (24, 160), (16, 32, 64, 128), 2)
     if name == "c5":
         return make_multi_map(seed, 32, (256 // s, 2048 // s), 256, 128, 0.3, "fp8", 4,
-                              (32, 128), 64, 3, progress=progress)
+                              (32, 128), 64, 3, progress=progress, only=maps)
     raise ValueError(name)
 
 
@@ -341,7 +368,7 @@ def _multi_map_one(job):
 
 
 def make_multi_map(seed, n_maps, side_rng, D, M, sigma, dtype, t_per_map, tside_rng, k, grid,
-                   noise=0.1, progress=None) -> Workload:
+                   noise=0.1, progress=None, only=None) -> Workload:
     r_means, r_sizes, *r_maps = _streams(seed, 2 + n_maps)
     means = r_means.standard_normal(size=(M, D))
     lo, hi = side_rng
@@ -352,6 +379,9 @@ def make_multi_map(seed, n_maps, side_rng, D, M, sigma, dtype, t_per_map, tside_
         W = int(r_sizes.choice(sides))
         jobs.append((int(r_maps[i].integers(0, 2**62)), H, W, D, M, sigma, dtype, means, t_per_map,
                      tside_rng, k, grid, noise))
+    if only is not None:
+        jobs = [jobs[i] for i in only]
+        n_maps = len(jobs)
     # every map has its own streams, so maps can be made in any order; large
     # workloads use a pool of fresh interpreters
     total = sum(j[1] * j[2] for j in jobs) * D
