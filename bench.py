@@ -105,6 +105,17 @@ def copy_probe(n_bytes=1 << 30, reps=3):
     print(json.dumps({"copy_probe_bytes": n_bytes, "reps": reps}), flush=True)
 
 
+def read_probe(n_bytes=1 << 30, reps=3):
+    """A read-only pass over a buffer of known size (a sum over 1 GiB): the
+    reference for the HBM read counters of read-mostly kernels."""
+    import torch
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    for _ in range(reps):
+        a.sum()
+    torch.cuda.synchronize()
+    print(json.dumps({"read_probe_bytes": n_bytes, "reps": reps}), flush=True)
+
+
 def secondary(name, ctx, B, synth, steps):
     """Both paths on another workload (device-resident, same timing as the main line)."""
     import torch
@@ -515,6 +526,8 @@ def main():
                     help="batched workloads: divide map sides by this factor")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--read-probe", action="store_true",
+                    help="only run a read-only pass over 1 GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path would shard "
@@ -530,6 +543,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.read_probe:
+        read_probe()
         return
     if args.workload in ("c4", "c5"):
         # the full batches need more scratch than the default cap (re-score

@@ -367,14 +367,26 @@ vqnnf_status vqnnf_ctx_set_debug_scores(vqnnf_ctx* ctx, float* scores, int64_t c
 vqnnf_status vqnnf_template_score_bound(const vqnnf_template* t, int32_t dtype, const float* channel_scale,
                                         double* out);
 
-/* Autotuning of the on-chip score's tile height (1 = on, the default): the
- * first call for a shape (template size, grid, codebook size, map size; for
- * a batched score launch, the shapes of all its pairs) times a few tile
- * heights on that call's own data (each run writes the same result) and
- * keeps the fastest; calls made while a graph is captured use the tuned
- * value if there is one, else the default sizing.  0 turns it off and
+/* Autotuning (1 = on, the default) of schedules that never change a result:
+ *  - the refined assignment kernel's schedule, per shape class (D, padded
+ *    codebook size, storage, map size to a power of two): the first refined
+ *    call of a class times each schedule on its own data;
+ *  - the on-chip score's tile height, per shape (template size, grid,
+ *    codebook size, map size; for a batched score launch, the shapes of all
+ *    its pairs): the first call times a few heights on its own data.
+ * Each candidate run writes the same labels / heatmap; the fastest is kept.
+ * Calls made while a graph is captured (and vqnnf_match_noalloc) use tuned
+ * values if there are any, else the defaults.  0 turns tuning off and
  * forgets tuned values. */
 vqnnf_status vqnnf_ctx_set_autotune(vqnnf_ctx* ctx, int32_t enable);
+
+/* Persists the context's tuning results in a text file (HOST path): entries
+ * already in the file for this device's compute-unit count are loaded now,
+ * and the file is rewritten (atomically, by rename) whenever tuning adds an
+ * entry, so later processes skip the tuning runs.  NULL stops persisting;
+ * results stay in memory.  A missing file is not an error; EINVAL when the
+ * file cannot be written. */
+vqnnf_status vqnnf_ctx_set_tune_file(vqnnf_ctx* ctx, const char* path);
 
 /* Graph mode for vqnnf_match_batched (0 = off, the default: kernels are
  * launched one by one).  Turning it off releases the captured graph. */

@@ -28,7 +28,7 @@ EXPORTED = [
     "vqnnf_template_weights", "vqnnf_template_responses", "vqnnf_paper_bank", "vqnnf_assign", "vqnnf_filter", "vqnnf_score",
     "vqnnf_score_integral", "vqnnf_match", "vqnnf_match_noalloc", "vqnnf_match_batched",
     "vqnnf_ctx_set_graph", "vqnnf_batched_labels", "vqnnf_ctx_set_debug_scores",
-    "vqnnf_template_score_bound",
+    "vqnnf_template_score_bound", "vqnnf_ctx_set_tune_file",
     "vqnnf_ctx_set_autotune",
     "vqnnf_ctx_set_timing", "vqnnf_ctx_kernel_times",
     "vqnnf_ctx_reset_times", "vqnnf_last_error", "vqnnf_version",
@@ -95,6 +95,7 @@ def lib() -> C.CDLL:
         "vqnnf_ctx_set_debug_scores": (st, [vp, vp, i64]),
         "vqnnf_template_score_bound": (st, [vp, i32, vp, vp]),
         "vqnnf_ctx_set_autotune": (st, [vp, i32]),
+        "vqnnf_ctx_set_tune_file": (st, [vp, C.c_char_p]),
         "vqnnf_ctx_set_timing": (st, [vp, i32]),
         "vqnnf_ctx_kernel_times": (st, [vp, i32, P(C.c_char_p), P(i64), P(C.c_double), P(i32)]),
         "vqnnf_ctx_reset_times": (st, [vp]),
@@ -426,6 +427,11 @@ def vqnnf_template_score_bound(tpl: Template, dtype: str, channel_scale=None):
     _check(lib().vqnnf_template_score_bound(tpl.h, _DT[dtype], sc.ctypes.data if sc is not None else None,
                                             out.ctypes.data))
     return tuple(float(v) for v in out)
+
+
+def vqnnf_ctx_set_tune_file(ctx: Context, path):
+    """Persist (and load) the context's tuning results in a text file."""
+    _check(lib().vqnnf_ctx_set_tune_file(ctx.h, None if path is None else str(path).encode()))
 
 
 def vqnnf_batched_labels(ctx: Context, pair: int, labels):

@@ -137,27 +137,33 @@ __device__ __forceinline__ void load_query(const void* q, int64_t off, int d0, i
 // of 32 elements (one K-step); the group count is even.  Work is a flat
 // stream of (tile, group) steps.  Step s:
 //   wait for the codebook group of step s to land in LDS, barrier;
-//   start the direct global->LDS copy of group s+1 into the other stage;
+//   start the direct global->LDS copy of group s+1 into the other stage (the
+//   two stages are separate arrays, so the compiler can tell the stage being
+//   filled from the one being read and adds no wait of its own);
 //   multiply group s (codebook from LDS, query from registers);
 //   at the end of a tile: epilogue (argmin, bound, worklist);
 //   request the query elements of step s+2 into the register buffer just
 //   consumed (two buffers: even and odd groups).
 // Memory counters drain in issue order, so the wait for the codebook copy of
-// step s leaves exactly the query loads of step s+1 outstanding.
+// step s leaves exactly the query loads of step s+1 outstanding.  With SG the
+// codebook fragments of block mb+1 are read from LDS while the matrix cores
+// work on block mb (the compiler otherwise reads each block just before its
+// use and the LDS latency sits between the matrix-core groups).
 struct StepCursor {
   int64_t tile;
   int gi;
 };
 
-template <int KB, int NB, int QT, bool FAST>
+template <int KB, int NB, int QT, bool FAST, bool SG>
 __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
   constexpr bool QF32 = QT == kQF32, QF8 = QT == kQFP8;
+  static_assert(!SG || !QF32, "fragments ahead: one query term");
   constexpr int NT = kWPB * 64;
   constexpr int GF = 2 * KB * 64;                  // uint4 per load group (hi + lo)
   constexpr int CPT = (GF + NT - 1) / NT;          // copies per thread per group
-  constexpr int NEL = 8;                           // elements per lane per group
+  constexpr int NEL = 8;                           // elements per lane per K-step
   constexpr int EB = QF32 ? 4 : QF8 ? 1 : 2;       // bytes per query element
-  constexpr int QW = NEL * EB / 4;                 // 32-bit words per lane per group
+  constexpr int QW = NEL * EB / 4;                 // 32-bit words per lane per K-step
   constexpr int QN = FAST ? NB * (QF32 ? 2 : 1) : 0;  // vector loads per query request
   constexpr int MW = (KB + 1) / 2;                 // candidate mask words
   // stages padded to whole copies (the padding receives duplicate data)
@@ -207,7 +213,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
     return (const char*)p.q + first * p.stride * EB;
   };
   uint32_t qa[NB][QW], qb[NB][QW];
-  // query elements of group gi for the tile whose base set_tile returned
+  // query elements of K-step gi for the tile whose base set_tile returned
   auto load_q = [&](const char* tb, int gi, uint32_t (&dst)[NB][QW]) {
     if constexpr (FAST) {
       const __amdgpu_buffer_rsrc_t rs = raw_rsrc(tb);
@@ -313,15 +319,37 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
         }
       }
     }
+    if constexpr (SG) {
+      // codebook fragments one block ahead: the LDS reads of block mb + 1
+      // are in flight while the matrix cores work on block mb (the
+      // scheduling barriers keep this order and both register sets live)
+      uint4 ah[2], al[2];
+      ah[0] = stage[lane];
+      al[0] = stage[KB * 64 + lane];
 #pragma unroll
-    for (int mb = 0; mb < KB; ++mb) {
-      const uint4 ahi = stage[mb * 64 + lane];
-      const uint4 alo = stage[(KB + mb) * 64 + lane];
+      for (int mb = 0; mb < KB; ++mb) {
+        if (mb + 1 < KB) {
+          ah[(mb + 1) & 1] = stage[(mb + 1) * 64 + lane];
+          al[(mb + 1) & 1] = stage[(KB + mb + 1) * 64 + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        acc[mb][nb] = mfma_bf16(ahi, bhi[nb], acc[mb][nb]);
-        acc[mb][nb] = mfma_bf16(alo, bhi[nb], acc[mb][nb]);
-        if constexpr (QF32) acc[mb][nb] = mfma_bf16(ahi, blo[nb], acc[mb][nb]);
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma_bf16(ah[mb & 1], bhi[nb], acc[mb][nb]);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma_bf16(al[mb & 1], bhi[nb], acc[mb][nb]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int mb = 0; mb < KB; ++mb) {
+        const uint4 ahi = stage[mb * 64 + lane];
+        const uint4 alo = stage[(KB + mb) * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          acc[mb][nb] = mfma_bf16(ahi, bhi[nb], acc[mb][nb]);
+          acc[mb][nb] = mfma_bf16(alo, bhi[nb], acc[mb][nb]);
+          if constexpr (QF32) acc[mb][nb] = mfma_bf16(ahi, blo[nb], acc[mb][nb]);
+        }
       }
     }
   };
@@ -414,6 +442,15 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
   };
 
   for (int i = threadIdx.x; i < 16 * KB; i += NT) cn_s[i] = p.cnorm[i];
+  // one step: wait for its codebook group, barrier, start the copy of
+  // group `fg` into `fill`, multiply group `cur` with `qbuf`
+  auto step = [&](uint4* cur, uint4* fill, int fg, uint32_t (&qbuf)[NB][QW]) {
+    wait_stage();
+    __syncthreads();
+    dma_cb(fg, fill);
+    __builtin_amdgcn_sched_barrier(0);  // the copy stays ahead of later loads
+    compute(cur, qbuf);
+  };
   // prologue: group 0 of the first tile in stage st0, its query elements in
   // qa and those of group 1 in qb
   const char* tb = set_tile(blockIdx.x);
@@ -428,24 +465,14 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
     const char* tb_next = tb;
     for (int gi = 0; gi < ngr; gi += 2) {
       const bool last = gi + 2 == ngr;
-      {  // even group gi; requests group gi + 2 (or group 0 of the next tile)
-        wait_stage();
-        __syncthreads();
-        dma_cb(gi + 1, st1);
-        __builtin_amdgcn_sched_barrier(0);  // the copy stays ahead of later loads
-        compute(st0, qa);
-        if (last) tb_next = set_tile(tile + gridDim.x);
-        load_q(last ? tb_next : tb, last ? 0 : gi + 2, qa);
-      }
-      {  // odd group gi + 1; requests group gi + 3 (or group 1 of the next tile)
-        wait_stage();
-        __syncthreads();
-        dma_cb(last ? 0 : gi + 2, st0);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(st1, qb);
-        if (last) finish(tile);
-        load_q(last ? tb_next : tb, last ? 1 : gi + 3, qb);
-      }
+      // even group gi; requests group gi + 2 (or group 0 of the next tile)
+      step(st0, st1, gi + 1, qa);
+      if (last) tb_next = set_tile(tile + gridDim.x);
+      load_q(last ? tb_next : tb, last ? 0 : gi + 2, qa);
+      // odd group gi + 1; requests group gi + 3 (or group 1 of the next tile)
+      step(st1, st0, last ? 0 : gi + 2, qb);
+      if (last) finish(tile);
+      load_q(last ? tb_next : tb, last ? 1 : gi + 3, qb);
     }
     tb = tb_next;
   }
@@ -862,22 +889,25 @@ bool rows_aligned(const AssignArgs& a, int elem_bytes, int align) {
 int qtype(int dtype) { return dtype == VQNNF_F32 ? kQF32 : dtype == VQNNF_FP8_E4M3 ? kQFP8 : kQBF16; }
 int qbytes(int qt) { return qt == kQF32 ? 4 : qt == kQFP8 ? 1 : 2; }
 
-template <int KB, int NB, int QT, bool FAST>
+template <int KB, int NB, int QT, bool FAST, bool SG>
 hipError_t go_refined(const KParams& kp, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((assign_refined_kernel<KB, NB, QT, FAST>), dim3(grid), dim3(kWPB * 64), 0, s, kp);
+  hipLaunchKernelGGL((assign_refined_kernel<KB, NB, QT, FAST, SG>), dim3(grid), dim3(kWPB * 64), 0, s, kp);
   return hipGetLastError();
 }
 
 template <int KB, int NB, int QT>
-hipError_t go_refined_f(const KParams& kp, int grid, bool fast, hipStream_t s) {
-  return fast ? go_refined<KB, NB, QT, true>(kp, grid, s) : go_refined<KB, NB, QT, false>(kp, grid, s);
+hipError_t go_refined_f(const KParams& kp, int grid, bool fast, int var, hipStream_t s) {
+  if (!fast) return go_refined<KB, NB, QT, false, false>(kp, grid, s);
+  if constexpr (QT != kQF32 && KB <= 8)
+    if (var == 2) return go_refined<KB, NB, QT, true, true>(kp, grid, s);
+  return go_refined<KB, NB, QT, true, false>(kp, grid, s);
 }
 
 template <int KB, int NB>
-hipError_t go_refined_q(const KParams& kp, int grid, int qt, bool fast, hipStream_t s) {
-  if (qt == kQF32) return go_refined_f<KB, NB, kQF32>(kp, grid, fast, s);
-  if (qt == kQFP8) return go_refined_f<KB, NB, kQFP8>(kp, grid, fast, s);
-  return go_refined_f<KB, NB, kQBF16>(kp, grid, fast, s);
+hipError_t go_refined_q(const KParams& kp, int grid, int qt, bool fast, int var, hipStream_t s) {
+  if (qt == kQF32) return go_refined_f<KB, NB, kQF32>(kp, grid, fast, var, s);
+  if (qt == kQFP8) return go_refined_f<KB, NB, kQFP8>(kp, grid, fast, var, s);
+  return go_refined_f<KB, NB, kQBF16>(kp, grid, fast, var, s);
 }
 
 template <int KB, int NB, int E, int QT, bool VEC>
@@ -951,6 +981,22 @@ bool rescore_vec(const AssignArgs& a) {
 // Pixel blocks per wave: KB*NB*4 accumulators stay <= 128 registers.
 static int pick_nb(int kb) { return kb <= 8 ? 4 : 2; }
 
+// Schedule of the refined kernel: 1 the compiler's, 2 codebook fragments
+// read one block ahead of the matrix cores.  Variant 2 exists for aligned
+// BF16 / FP8 rows with at most 128 codewords and is their default
+// (a.variant 0); other maps always take variant 1.
+int refined_variants(const AssignArgs& a) {
+  const AssignGeom& g = a.t->geom;
+  const int qt = qtype(a.dtype);
+  const bool fast = rows_aligned(a, qbytes(qt), qt == kQFP8 ? 8 : 16) && (a.D % 64 == 0) && g.s_bf16 == 1;
+  return (fast && qt != kQF32 && g.kb <= 8) ? 2 : 1;
+}
+static int refined_variant(const AssignArgs& a) {
+  const int n = refined_variants(a);
+  if (a.variant >= 1 && a.variant <= n) return a.variant;
+  return n;
+}
+
 hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu) {
   const DeviceTemplate& t = *a.t;
   const AssignGeom& g = t.geom;
@@ -981,15 +1027,16 @@ hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu) {
   kp.n_tiles = (a.n_pix + tile_px - 1) / tile_px;
   const int grid = (int)std::min<int64_t>(kp.n_tiles, (int64_t)n_cu);
   if (g.s_bf16 != 1 || kp.n_groups % 2 != 0) return hipErrorInvalidValue;
+  const int var = refined_variant(a);
   timing_begin(K_ASSIGN_REFINED);
   hipError_t e;
   switch (g.kb) {
-    case 1: e = go_refined_q<1, 4>(kp, grid, qt, fast, s); break;
-    case 2: e = go_refined_q<2, 4>(kp, grid, qt, fast, s); break;
-    case 3: e = go_refined_q<3, 4>(kp, grid, qt, fast, s); break;
-    case 4: e = go_refined_q<4, 4>(kp, grid, qt, fast, s); break;
-    case 8: e = go_refined_q<8, 4>(kp, grid, qt, fast, s); break;
-    case 16: e = go_refined_q<16, 2>(kp, grid, qt, fast, s); break;
+    case 1: e = go_refined_q<1, 4>(kp, grid, qt, fast, var, s); break;
+    case 2: e = go_refined_q<2, 4>(kp, grid, qt, fast, var, s); break;
+    case 3: e = go_refined_q<3, 4>(kp, grid, qt, fast, var, s); break;
+    case 4: e = go_refined_q<4, 4>(kp, grid, qt, fast, var, s); break;
+    case 8: e = go_refined_q<8, 4>(kp, grid, qt, fast, var, s); break;
+    case 16: e = go_refined_q<16, 2>(kp, grid, qt, fast, var, s); break;
     default: e = hipErrorInvalidValue; break;
   }
   timing_end(K_ASSIGN_REFINED);

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -106,6 +107,11 @@ struct vqnnf_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<uint64_t> gsig;
+  // refined assignment schedule: 0 = tuned per shape class (default when
+  // tuning is off); VQNNF_ASSIGN_VARIANT forces one when the context is made
+  int assign_variant = 0;
+  std::map<std::vector<int>, int> avar_cache;   // shape class -> schedule
+  std::string tune_file;                        // persisted tuning results, "" = none
   // test support: scores of the refined matrix-core assignment
   float* dbg_scores = nullptr;
   int64_t dbg_cap = 0;
@@ -649,8 +655,18 @@ PairBufs ctx_bufs(const vqnnf_ctx* c) {
                   (uint32_t*)c->wl_mask.p, c->partials.p};
 }
 
+vqnnf_status save_tune_file(vqnnf_ctx* c);
+
+// Shape class of a refined assignment for the schedule tuner: D, padded
+// codebook size, storage, row alignment and the map size to a power of two.
+std::vector<int> assign_key(const AssignArgs& a, int n_variants) {
+  int lg = 0;
+  while (lg < 40 && ((int64_t)1 << lg) < a.n_pix) ++lg;
+  return {a.D, a.t->geom.kpad, a.dtype, n_variants, lg};
+}
+
 vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap* q, int prec,
-                        uint8_t* labels, bool counter_zeroed, const PairBufs& b) {
+                        uint8_t* labels, bool counter_zeroed, const PairBufs& b, bool allow_tune = true) {
   const DeviceTemplate& t = tp->t;
   AssignArgs a{};
   a.q = q->data;
@@ -671,6 +687,7 @@ vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap
   a.frag_bf16 = ss ? ss->d_frag_bf16 : t.d_frag_bf16;
   a.frag_f32 = ss ? ss->d_frag_f32 : t.d_frag_f32;
   a.scale = ss ? ss->d_scale : nullptr;
+  a.variant = c->assign_variant;
   const bool lowd = lowd_supported(q->dtype, q->D);
   if (prec == VQNNF_PREC_FP32_PLAIN) {
     if (lowd) HIP_TRY(launch_assign_lowd(a, false, c->stream));
@@ -681,15 +698,58 @@ vqnnf_status run_assign(vqnnf_ctx* c, const vqnnf_template* tp, const vqnnf_fmap
   a.wl_pix = b.wl_pix;
   a.wl_mask = b.wl_mask;
   a.bound = ss ? ss->bound : (q->dtype == VQNNF_F32) ? t.bound_f32q : t.bound_bf16q;
-  if (!counter_zeroed) HIP_TRY(launch_fill_u32(a.wl_count, 0u, 1, c->stream));
   if (c->dbg_scores && !lowd) {
     if (a.n_pix * (int64_t)t.geom.kpad > c->dbg_cap)
       return fail(VQNNF_EINVAL, "debug score buffer holds %lld floats; this map needs %lld",
                   (long long)c->dbg_cap, (long long)(a.n_pix * t.geom.kpad));
     a.dump = c->dbg_scores;
   }
-  if (lowd) HIP_TRY(launch_assign_lowd(a, true, c->stream));
-  else HIP_TRY(launch_assign_refined(a, c->stream, c->n_cu));
+  bool launched = false;
+  if (!lowd && !a.variant) {
+    const int nv = refined_variants(a);
+    const std::vector<int> key = assign_key(a, nv);
+    auto it = c->avar_cache.find(key);
+    if (it != c->avar_cache.end()) {
+      a.variant = it->second;
+    } else if (nv > 1 && c->autotune && !c->capturing && allow_tune) {
+      // time every schedule twice on this very call (each run clears the
+      // worklist counter and writes the same labels and worklist), keep the
+      // fastest for the shape class; the last run's results stand
+      set_timing_hook(nullptr);
+      std::vector<hipEvent_t> ev(2 * nv);
+      for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+      for (int rep = 0; rep < 2; ++rep)
+        for (int v = 1; v <= nv; ++v) {
+          a.variant = v;
+          HIP_TRY(launch_fill_u32(a.wl_count, 0u, 1, c->stream));
+          if (rep == 1) HIP_TRY(hipEventRecord(ev[2 * (v - 1)], c->stream));
+          HIP_TRY(launch_assign_refined(a, c->stream, c->n_cu));
+          if (rep == 1) HIP_TRY(hipEventRecord(ev[2 * (v - 1) + 1], c->stream));
+        }
+      HIP_TRY(hipEventSynchronize(ev.back()));
+      float best_ms = 1e30f;
+      int best = nv;
+      for (int v = 1; v <= nv; ++v) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[2 * (v - 1)], ev[2 * (v - 1) + 1]));
+        if (ms < best_ms) { best_ms = ms; best = v; }
+      }
+      for (auto& e : ev) hipEventDestroy(e);
+      if (c->timing) {
+        TimingHook h{hook_begin, hook_end, c};
+        set_timing_hook(&h);
+      }
+      c->avar_cache[key] = best;
+      vqnnf_status st = save_tune_file(c);
+      if (st) return st;
+      launched = true;
+    }
+  }
+  if (!launched) {
+    if (!counter_zeroed) HIP_TRY(launch_fill_u32(a.wl_count, 0u, 1, c->stream));
+    if (lowd) HIP_TRY(launch_assign_lowd(a, true, c->stream));
+    else HIP_TRY(launch_assign_refined(a, c->stream, c->n_cu));
+  }
   HIP_TRY(launch_rescore(a, c->stream, c->n_cu));
   return ok();
 }
@@ -788,6 +848,8 @@ vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t*
         set_timing_hook(&h);
       }
       c->tyw_cache[key] = best;
+      vqnnf_status st = save_tune_file(c);
+      if (st) return st;
       return ok();   // the last candidate's run already produced the result
     }
     HIP_TRY(launch_score_fused(a, c->stream, &lds));
@@ -873,6 +935,31 @@ vqnnf_status enqueue_pair(vqnnf_ctx* c, const vqnnf_template* t, const vqnnf_fma
   return enqueue_score_labels(c, t, lab, q->H, q->W, heatmap, key);
 }
 
+// Writes every tuning result of the context to its tune file (if any):
+// written to a temporary file and renamed, so a reader never sees half a file.
+vqnnf_status save_tune_file(vqnnf_ctx* c) {
+  if (c->tune_file.empty()) return ok();
+  const std::string tmp = c->tune_file + ".tmp" + std::to_string((long long)(uintptr_t)c);
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return fail(VQNNF_EINVAL, "cannot write the tune file %s", tmp.c_str());
+  auto put = [&](char kind, const std::map<std::vector<int>, int>& m) {
+    for (const auto& e : m) {
+      std::fprintf(f, "%c %d", kind, c->n_cu);
+      for (int x : e.first) std::fprintf(f, " %d", x);
+      std::fprintf(f, " %d\n", e.second);
+    }
+  };
+  put('a', c->avar_cache);
+  put('s', c->tyw_cache);
+  put('b', c->btyw_cache);
+  const bool bad = std::fclose(f) != 0;
+  if (bad || std::rename(tmp.c_str(), c->tune_file.c_str()) != 0) {
+    std::remove(tmp.c_str());
+    return fail(VQNNF_EINVAL, "cannot write the tune file %s", c->tune_file.c_str());
+  }
+  return ok();
+}
+
 // Byte layout of vqnnf_match_noalloc's fixed scratch for one pair: the
 // control block, the label map, the worklist and masks (refined path) and
 // the score partials, each part 256-byte aligned.
@@ -917,6 +1004,7 @@ vqnnf_status vqnnf_ctx_create(void* hip_stream, uint64_t scratch_cap_bytes, vqnn
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   c->stream = (hipStream_t)hip_stream;
   c->cap = scratch_cap_bytes ? scratch_cap_bytes : (16ull << 30);
+  if (const char* v = std::getenv("VQNNF_ASSIGN_VARIANT")) c->assign_variant = std::atoi(v);
   *out = c;
   return ok();
 }
@@ -1543,7 +1631,7 @@ vqnnf_status vqnnf_match_noalloc(vqnnf_ctx* c, const vqnnf_template* t, const vq
   // the array keeps the previous call's contents: clear the best key and the
   // worklist counter with a kernel (graph-capturable, no memset node)
   HIP_TRY(launch_fill_u32((uint32_t*)b.control, 0u, 4, c->stream));
-  if ((s = run_assign(c, t, q, prec, b.labels, true, b))) return s;
+  if ((s = run_assign(c, t, q, prec, b.labels, true, b, false))) return s;
   if ((s = enqueue_score(c, t, b.labels, nullptr, q->H, q->W, heatmap, key, true, nullptr, b.partials, false)))
     return s;
   if (!best_xy && !best_score) return ok();
@@ -2017,7 +2105,7 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
       }
     }
     c->btyw_cache[bkey] = best;
-    return ok();   // the last candidate's run already produced the result
+    return save_tune_file(c);   // the last candidate's run already produced the result
   };
   auto enqueue_all = [&]() -> vqnnf_status {
     HIP_TRY(launch_fill_u32((uint32_t*)keys, 0u, 2 * (int64_t)n, c->stream));
@@ -2139,6 +2227,42 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
   return ok();
 }
 
+vqnnf_status vqnnf_ctx_set_tune_file(vqnnf_ctx* c, const char* path) {
+  vqnnf_status s;
+  if ((s = check_ctx(c))) return s;
+  c->tune_file = path ? path : "";
+  if (!path) return ok();
+  // lines "<kind> <compute units> <key ints ...> <value>"; kinds a (assignment
+  // schedule), s (tile height of a single score), b (of a batched score);
+  // entries of other compute-unit counts and malformed lines are skipped
+  FILE* f = std::fopen(path, "r");
+  if (!f) return ok();   // nothing tuned yet
+  char line[4096];
+  while (std::fgets(line, sizeof(line), f)) {
+    char kind = 0;
+    int off = 0;
+    if (std::sscanf(line, " %c%n", &kind, &off) != 1 || (kind != 'a' && kind != 's' && kind != 'b')) continue;
+    std::vector<long long> v;
+    const char* p = line + off;
+    for (;;) {
+      long long x;
+      int n = 0;
+      if (std::sscanf(p, " %lld%n", &x, &n) != 1) break;
+      v.push_back(x);
+      p += n;
+    }
+    if (v.size() < 3 || v[0] != c->n_cu) continue;
+    std::vector<int> key(v.begin() + 1, v.end() - 1);
+    const int val = (int)v.back();
+    if (val < 1) continue;
+    if (kind == 'a') c->avar_cache[key] = val;
+    else if (kind == 's') c->tyw_cache[key] = val;
+    else c->btyw_cache[key] = val;
+  }
+  std::fclose(f);
+  return ok();
+}
+
 vqnnf_status vqnnf_batched_labels(vqnnf_ctx* c, int32_t pair, uint8_t* labels) {
   vqnnf_status s;
   if ((s = check_ctx(c))) return s;
@@ -2198,6 +2322,7 @@ vqnnf_status vqnnf_ctx_set_autotune(vqnnf_ctx* c, int32_t enable) {
   if (!c->autotune) {
     c->tyw_cache.clear();
     c->btyw_cache.clear();
+    c->avar_cache.clear();
   }
   return ok();
 }

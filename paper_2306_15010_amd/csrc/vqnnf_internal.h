@@ -172,6 +172,7 @@ struct AssignArgs {
   int mask_words;        // 0: ceil(kpad / 32); the fused multi-template kernel writes its own count
   BoundCoef bound;
   float* dump;           // refined matrix-core path, test support: s~ [n_pix][kpad] or null
+  int variant;           // refined matrix-core path: schedule 1..refined_variants(), 0 = default
 };
 
 // Fused assignment of several templates against one map (batched matching).
@@ -217,6 +218,9 @@ hipError_t launch_assign_multi(const MultiArgs& a, hipStream_t s, int n_cu);
 
 hipError_t launch_assign_plain(const AssignArgs& a, hipStream_t s, int n_cu);
 hipError_t launch_assign_refined(const AssignArgs& a, hipStream_t s, int n_cu);
+// Schedules of the refined kernel available for these arguments (1 or 2);
+// the highest is the default.
+int refined_variants(const AssignArgs& a);
 hipError_t launch_rescore(const AssignArgs& a, hipStream_t s, int n_cu);
 // Batched re-score of many pairs: one launch per (query type, vector path)
 // class, each pair's arguments read from a device table.
