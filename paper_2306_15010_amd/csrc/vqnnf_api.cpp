@@ -1817,6 +1817,7 @@ hipError_t enqueue_multi_launch(vqnnf_ctx* c, const MultiLaunch& l, const uint8_
   ma.kp.n_groups = l.n_groups;
   ma.kp.n_tiles = l.n_tiles;
   ma.fp8 = l.fp8;
+  ma.variant = c->assign_variant;
   return launch_assign_multi(ma, c->stream, c->n_cu);
 }
 

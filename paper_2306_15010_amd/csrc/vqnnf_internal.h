@@ -208,6 +208,7 @@ struct MultiParams {
 struct MultiArgs {
   MultiParams kp;
   bool fp8;
+  int variant;                       // 0/1 the compiler's schedule, 2 fragments one block ahead
 };
 // Pixels per tile of the fused launch and the tiles of one map.
 constexpr int kMultiTilePx = 512;
