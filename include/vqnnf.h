@@ -293,9 +293,9 @@ vqnnf_status vqnnf_match(vqnnf_ctx* ctx, const vqnnf_template* t, const vqnnf_fm
  * score partial sums, best-location key) placed in one fixed device array
  * of VQNNF_NOALLOC_SCRATCH_BYTES that the library holds on each device it
  * runs on until the process ends.  The call allocates nothing (no hipMalloc,
- * hipFree or event creation) and does not autotune (it uses a tile height
- * tuned by an earlier vqnnf_match on the same shape, else the default) or
- * record kernel timings.
+ * hipFree or event creation) and does not autotune (it uses the score tile
+ * choice tuned by an earlier vqnnf_match on the same shape, else the
+ * default) or record kernel timings.
  *  - VQNNF_ENOMEM when the pair needs more than the array holds: about
  *    H*W*(1 + 4 + 4*ceil(k/32)) bytes on the refined path (H*W on the plain
  *    path) plus the score's partial sums, e.g. a 1024 x 1024 map with k = 128
@@ -371,9 +371,10 @@ vqnnf_status vqnnf_template_score_bound(const vqnnf_template* t, int32_t dtype, 
  *  - the refined assignment kernel's schedule, per shape class (D, padded
  *    codebook size, storage, map size to a power of two): the first refined
  *    call of a class times each schedule on its own data;
- *  - the on-chip score's tile height, per shape (template size, grid,
- *    codebook size, map size; for a batched score launch, the shapes of all
- *    its pairs): the first call times a few heights on its own data.
+ *  - the on-chip score's tile block width (16 or 32 channels) and tile
+ *    height, per shape (template size, grid, codebook size, map size; for a
+ *    batched score launch, the shapes of all its pairs): the first call
+ *    times both widths at a few heights on its own data.
  * Each candidate run writes the same labels / heatmap; the fastest is kept.
  * Calls made while a graph is captured (and vqnnf_match_noalloc) use tuned
  * values if there are any, else the defaults.  0 turns tuning off and
@@ -385,7 +386,10 @@ vqnnf_status vqnnf_ctx_set_autotune(vqnnf_ctx* ctx, int32_t enable);
  * and the file is rewritten (atomically, by rename) whenever tuning adds an
  * entry, so later processes skip the tuning runs.  NULL stops persisting;
  * results stay in memory.  A missing file is not an error; EINVAL when the
- * file cannot be written. */
+ * file cannot be written.  Lines are "<kind> <compute units> <shape key...>
+ * <value>": kind a = assignment schedule, s = single-pair score tile, b =
+ * batched score tile; a score tile value is the window rows per tile, plus
+ * 65536 for 32-channel tile blocks. */
 vqnnf_status vqnnf_ctx_set_tune_file(vqnnf_ctx* ctx, const char* path);
 
 /* Graph mode for vqnnf_match_batched (0 = off, the default: kernels are

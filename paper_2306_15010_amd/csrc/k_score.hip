@@ -124,7 +124,11 @@ struct TileParams {
   uint32_t b0;          // batched launches: first block of the pair
   // one channel group: eq. 2 per sum a, the heatmap and the best key
   float wt[kMaxAcc];
-  int area2[kMaxAcc];   // twice the summed areas of the filters in sum a
+  // sum a's L1 term sum_j |T_j - C_j| = area2[a] + cmul[a] * (stored sum):
+  // (0, 1) for sums of |T_j - C_j|, (twice the filters' area, -2) for sums
+  // of min(T_j, C_j)
+  int area2[kMaxAcc];
+  int cmul[kMaxAcc];
   float* heatmap;
   unsigned long long* best;
 };
@@ -169,7 +173,11 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
 // UNI: every bin has the same weight, so the bins share one accumulator
 // (accumulator 0: full window, 1: bins); otherwise one per filter while
 // scoring, merged into the stored sums at the end of each row.
-template <int G, bool UNI, int KG>
+// SAD: the accumulators sum |T_j - C_j| (v_sad_u16: two channels per
+// instruction, one instruction per channel pair and bin); otherwise
+// min(T_j, C_j) (v_pk_min_u16 + v_dot2_u32_u16), whose sums stay below the
+// window area where twice the area overflows 16 bits.
+template <int G, bool UNI, int KG, bool SAD>
 __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int by, int grp) {
   constexpr int kPQ = KG / 8;                        // pair groups
   constexpr int kST = kTXW * kPQ;                    // threads
@@ -200,20 +208,33 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
   for (int i = tid; i < NR * kHS; i += kST) (&Qs[0][0])[i] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
   // band histograms at the tile's first row: items of 8 rows of one column,
-  // the 8 label loads issued together
+  // four items per thread at a time with their 32 label loads issued together
   const int nrc = (p.h + 7) / 8;
-  for (int i = tid; i < nrc * cols; i += kST) {
-    const int c = i % cols, r0 = (i / cols) * 8;
-    int l8[8];
+  const int nit = nrc * cols;
+  constexpr int kPI = 4;
+  for (int i0 = tid; i0 < nit; i0 += kPI * kST) {
+    int l8[kPI][8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
-      l8[r] = (r0 + r < p.h) ? (int)labs[(int64_t)(y0 + r0 + r) * p.W + x0 + c] - j0 : -1;
-    int b = 0;
+    for (int u = 0; u < kPI; ++u) {
+      const int i = i0 + u * kST;
+      const int c = i % cols, r0 = (i / cols) * 8;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      if (r0 + r >= p.h) break;
-      while (r0 + r >= p.ye[b + 1]) ++b;
-      if ((unsigned)l8[r] < (unsigned)KG) atomicAdd(qword(b, l8[r], c), 1u << (16 * (l8[r] & 1)));
+      for (int r = 0; r < 8; ++r)
+        l8[u][r] = (i < nit && r0 + r < p.h) ? (int)labs[(int64_t)(y0 + r0 + r) * p.W + x0 + c] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kPI; ++u) {
+      const int i = i0 + u * kST;
+      if (i >= nit) break;
+      const int c = i % cols, r0 = (i / cols) * 8;
+      int b = 0;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        if (r0 + r >= p.h) break;
+        while (r0 + r >= p.ye[b + 1]) ++b;
+        const int l = l8[u][r] - j0;
+        if ((unsigned)l < (unsigned)KG) atomicAdd(qword(b, l, c), 1u << (16 * (l & 1)));
+      }
     }
   }
 
@@ -225,19 +246,26 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
   for (int f = 0; f < NF; ++f)
 #pragma unroll
     for (int s = 0; s < 4; ++s) T[f][s] = t16[f * (p.kpad / 2) + j0 / 2 + pq * 4 + s];
-  // labels leaving / entering each band at the next row step, prefetched
+  // labels leaving / entering each band at the next row step, prefetched a
+  // step ahead; kept as loaded (the group offset is taken at use), so the
+  // loads stay in flight across the barriers until the next step needs them
   int lo[G], li[G];
   auto fetch = [&](int ynext, int c) {
 #pragma unroll
     for (int b = 0; b < G; ++b) {
-      lo[b] = (int)labs[(int64_t)(ynext - 1 + p.ye[b]) * p.W + x0 + c] - j0;
-      li[b] = (int)labs[(int64_t)(ynext - 1 + p.ye[b + 1]) * p.W + x0 + c] - j0;
+      lo[b] = (int)labs[(int64_t)(ynext - 1 + p.ye[b]) * p.W + x0 + c];
+      li[b] = (int)labs[(int64_t)(ynext - 1 + p.ye[b + 1]) * p.W + x0 + c];
     }
   };
   if (tyv > 1 && tid < cols) fetch(y0 + 1, tid);
 
   uint32_t acc[NACC];
   unsigned long long key = 0ull;
+  // one channel pair's term of a bin (packed counts c, template counts t)
+  auto term = [](uint32_t c, uint32_t t, uint32_t a) -> uint32_t {
+    if constexpr (SAD) return __builtin_amdgcn_sad_u16(c, t, a);
+    else return min_dot(c, t, a);
+  };
   // the stored sums: full window, then the bins of each weight class
   auto merge = [&](uint32_t (&o)[NOUT]) {
     if constexpr (UNI) {
@@ -271,7 +299,7 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
       if (a >= p.nacc) break;
       const uint32_t o = v[a];
       if (p.ng == 1) {
-        s = fmaf(p.wt[a], (float)(p.area2[a] - 2 * (int)o), s);
+        s = fmaf(p.wt[a], (float)(p.area2[a] + p.cmul[a] * (int)o), s);
       } else {
         gbl(p.part)[((int64_t)grp * p.nacc + a) * p.pstride + win] = (uint16_t)o;
       }
@@ -325,13 +353,13 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
           for (int a = 0; a < G; ++a) {
             const uint32_t bin = comp(hv[a + 1], s) - comp(hv[a], s);
             const int ai = UNI ? 1 : 1 + b * G + a;
-            acc[ai] = min_dot(bin, T[1 + b * G + a][s], acc[ai]);
+            acc[ai] = term(bin, T[1 + b * G + a][s], acc[ai]);
           }
           full[s] += comp(hv[G], s) - comp(hv[0], s);
         }
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc[0] = min_dot(full[s], T[0][s], acc[0]);
+      for (int s = 0; s < 4; ++s) acc[0] = term(full[s], T[0][s], acc[0]);
       if (pq >= 1) {
         uint32_t o[NOUT];
         merge(o);
@@ -345,8 +373,9 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
 #pragma unroll
       for (int b = 0; b < G; ++b) {
         if (lo[b] == li[b]) continue;
-        if ((unsigned)lo[b] < (unsigned)KG) atomicSub(qword(b, lo[b], c), 1u << (16 * (lo[b] & 1)));
-        if ((unsigned)li[b] < (unsigned)KG) atomicAdd(qword(b, li[b], c), 1u << (16 * (li[b] & 1)));
+        const int o = lo[b] - j0, e = li[b] - j0;
+        if ((unsigned)o < (unsigned)KG) atomicSub(qword(b, o, c), 1u << (16 * (o & 1)));
+        if ((unsigned)e < (unsigned)KG) atomicAdd(qword(b, e, c), 1u << (16 * (e & 1)));
       }
       if (dy + 2 < tyv) fetch(y + 2, c);
     }
@@ -356,20 +385,20 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
   if (p.ng == 1) block_max_n<kST / 64>(key, p.best);
 }
 
-template <int G, bool UNI, int KG>
+template <int G, bool UNI, int KG, bool SAD>
 __global__ __launch_bounds__(kTXW * (KG / 8)) void score_tile_kernel(TileParams p) {
-  score_tile_body<G, UNI, KG>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+  score_tile_body<G, UNI, KG, SAD>(p, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Batched: block -> pair from a table, then (group, tile column, tile row)
 // with the channel group fastest.
-template <int G, bool UNI, int KG>
+template <int G, bool UNI, int KG, bool SAD>
 __global__ __launch_bounds__(kTXW * (KG / 8)) void score_tile_batch_kernel(const TileParams* __restrict__ tab,
                                                                            const uint32_t* __restrict__ blk) {
   const TileParams& p = tab[blk[blockIdx.x]];
   const int b = (int)(blockIdx.x - p.b0);
   const int grp = b % p.ng, t = b / p.ng;
-  score_tile_body<G, UNI, KG>(p, t % p.nx, t / p.nx, grp);
+  score_tile_body<G, UNI, KG, SAD>(p, t % p.nx, t / p.nx, grp);
 }
 
 typedef unsigned int u32x2_v __attribute__((ext_vector_type(2)));
@@ -384,53 +413,78 @@ struct CombineParams {
   int ngroups;
   uint32_t b0;        // batched launches: first block of the pair
   float wt[kMaxAcc];  // per stored sum
-  int area2[kMaxAcc]; // per stored sum: twice the summed filter areas
+  int area2[kMaxAcc]; // per stored sum: L1 term = area2 + cmul * (sum over groups)
+  int cmul[kMaxAcc];
   float* heatmap;
   unsigned long long* best;
 };
 
-// Four consecutive windows per thread: 8-byte loads of every partial row
-// (rows are padded to a multiple of four windows).
+// Two quads of four consecutive windows per thread (a block covers
+// kCombineWin windows): 8-byte loads of every partial row (rows are padded
+// to a multiple of four windows), issued for several channel groups at a
+// time; one best-key update per block.
+constexpr int kCombineQ = 2;
+constexpr int kCombineWin = 256 * 4 * kCombineQ;
+
 template <int NACC>
 __device__ __forceinline__ void combine_body(const CombineParams& p, int64_t blk) {
-  const int64_t w0 = (blk * 256 + threadIdx.x) * 4;
+  constexpr int GB = NACC <= 2 ? 4 : 2;              // channel groups per batch of loads
   unsigned long long key = 0ull;
-  if (w0 < p.nwin) {
-    uint4 m[NACC];
+  int64_t w[kCombineQ];
+  uint4 m[kCombineQ][NACC];
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) m[a] = make_uint4(0u, 0u, 0u, 0u);
-    for (int g = 0; g < p.ngroups; ++g) {
-      uint4 v[NACC];
+  for (int q = 0; q < kCombineQ; ++q) {
+    w[q] = blk * kCombineWin + ((int64_t)q * 256 + threadIdx.x) * 4;
 #pragma unroll
-      for (int a = 0; a < NACC; ++a) {
-        const int64_t o = ((int64_t)g * NACC + a) * p.pstride + w0;
-        const u32x2_v h = *(const __attribute__((address_space(1))) u32x2_v*)gbl(p.part + o);
-        v[a] = make_uint4(h[0] & 0xFFFFu, h[0] >> 16, h[1] & 0xFFFFu, h[1] >> 16);
-      }
+    for (int a = 0; a < NACC; ++a) m[q][a] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  for (int g0 = 0; g0 < p.ngroups; g0 += GB) {
+    u32x2_v h[GB][kCombineQ][NACC];
 #pragma unroll
-      for (int a = 0; a < NACC; ++a)
-        m[a] = make_uint4(m[a].x + v[a].x, m[a].y + v[a].y, m[a].z + v[a].z, m[a].w + v[a].w);
-    }
-    // sum_j |T_j - C_j| = 2A - 2 sum_j min(T_j, C_j), exact in integers
+    for (int u = 0; u < GB; ++u)
+#pragma unroll
+      for (int q = 0; q < kCombineQ; ++q)
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+          const int64_t o = ((int64_t)(g0 + u) * NACC + a) * p.pstride + w[q];
+          h[u][q][a] = (g0 + u < p.ngroups && w[q] < p.nwin)
+                           ? *(const __attribute__((address_space(1))) u32x2_v*)gbl(p.part + o)
+                           : u32x2_v{0u, 0u};
+        }
+#pragma unroll
+    for (int u = 0; u < GB; ++u)
+#pragma unroll
+      for (int q = 0; q < kCombineQ; ++q)
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+          const u32x2_v v = h[u][q][a];
+          m[q][a] = make_uint4(m[q][a].x + (v[0] & 0xFFFFu), m[q][a].y + (v[0] >> 16),
+                               m[q][a].z + (v[1] & 0xFFFFu), m[q][a].w + (v[1] >> 16));
+        }
+  }
+#pragma unroll
+  for (int q = 0; q < kCombineQ; ++q) {
+    if (w[q] >= p.nwin) continue;
+    // the L1 terms, exact in integers
     float sc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       float s = 0.f;
 #pragma unroll
       for (int a = 0; a < NACC; ++a) {
-        const uint32_t mi = i == 0 ? m[a].x : i == 1 ? m[a].y : i == 2 ? m[a].z : m[a].w;
-        s = fmaf(p.wt[a], (float)(p.area2[a] - 2 * (int)mi), s);
+        const uint32_t mi = i == 0 ? m[q][a].x : i == 1 ? m[q][a].y : i == 2 ? m[q][a].z : m[q][a].w;
+        s = fmaf(p.wt[a], (float)(p.area2[a] + p.cmul[a] * (int)mi), s);
       }
       sc[i] = -s;
     }
-    const int nv = (int)min((int64_t)4, p.nwin - w0);
+    const int nv = (int)min((int64_t)4, p.nwin - w[q]);
     if (nv == 4 && p.vec_out) {
-      *(__attribute__((address_space(1))) f32x4_v*)gbl(p.heatmap + w0) = f32x4_v{sc[0], sc[1], sc[2], sc[3]};
+      *(__attribute__((address_space(1))) f32x4_v*)gbl(p.heatmap + w[q]) = f32x4_v{sc[0], sc[1], sc[2], sc[3]};
     } else {
-      for (int i = 0; i < nv; ++i) gbl(p.heatmap)[w0 + i] = sc[i];
+      for (int i = 0; i < nv; ++i) gbl(p.heatmap)[w[q] + i] = sc[i];
     }
     for (int i = 0; i < nv; ++i) {
-      const unsigned long long k2 = best_key(sc[i], (uint32_t)(w0 + i));
+      const unsigned long long k2 = best_key(sc[i], (uint32_t)(w[q] + i));
       key = k2 > key ? k2 : key;
     }
   }
@@ -504,6 +558,7 @@ struct TilePlan {
   bool ok;
   bool uni;           // every bin has one weight: two sums
   int kg;             // channels per block (16 or 32)
+  bool sad;           // blocks sum |T_j - C_j| (every stored sum < 2^16)
   int txw;
   int nacc;
   uint32_t cmask[kMaxCls];
@@ -512,19 +567,15 @@ struct TilePlan {
 };
 
 // Tiles are as wide as the LDS rows allow (at most kTXW windows, at least 32).
-// wide: 32-channel blocks where they are allowed (single-pair launches with
-// a 3 x 3 grid: on the 1024 x 1024, k = 128 match they score 15% faster; in
-// batches of small tiles, and with 2 x 2 grids whose 32-channel blocks hold
-// one block per compute unit, the 16-channel blocks measured faster).
+// wide: 32-channel blocks where the grid allows them (G <= 3; they hold 4 G
+// rows of LDS histograms and prefixes, 142 KB at G = 3).
 TilePlan plan_tile(const DeviceTemplate& t, bool wide = false) {
   TilePlan pl{};
   if (!t.grid.valid) return pl;
   const int G = t.grid.g;
   const int NF = 1 + G * G;
   if (G < 1 || G > 4 || t.geom.kpad % 16 || t.n_filters != NF) return pl;
-  // 32-channel blocks hold 4 G rows of LDS histograms and prefixes (142 KB
-  // at G = 3)
-  pl.kg = (wide && G == 3 && t.geom.kpad % 32 == 0) ? 32 : 16;
+  pl.kg = (wide && G <= 3 && t.geom.kpad % 32 == 0) ? 32 : 16;
   int maxband = 0;
   for (int b = 0; b < G; ++b) maxband = std::max(maxband, t.grid.ye[b + 1] - t.grid.ye[b]);
   pl.txw = std::min(kTXW, kColsMax + 1 - t.w);
@@ -551,9 +602,18 @@ TilePlan plan_tile(const DeviceTemplate& t, bool wide = false) {
     if (f > 0) pl.cmask[cls[f]] |= 1u << f;
   }
   if ((int64_t)t.w * t.h > 65535) return pl;   // 16-bit partial sums
+  // a group's sum of |T_j - C_j| over a stored sum's filters is at most
+  // twice their area: 16 bits hold it unless the template is large
+  pl.sad = true;
+  for (int a = 0; a < pl.nacc; ++a) pl.sad = pl.sad && pl.area2[a] <= 65535;
   pl.ok = true;
   return pl;
 }
+
+// The default block width of a single pair: 32-channel blocks where the grid
+// allows them (on 1024 x 1024 maps they scored 2 x 2 and 3 x 3 grids 2-20%
+// faster than 16-channel blocks); batches default to 16-channel blocks.
+bool default_wide(const DeviceTemplate& t) { return t.grid.valid && t.grid.g <= 3; }
 
 // Kernel arguments of one pair's tile and combine kernels.
 struct PairTables {
@@ -562,6 +622,7 @@ struct PairTables {
   int G;
   bool uni;
   int kg;
+  bool sad;
   int ny;
   int64_t ncblk;   // combine blocks (0: the tile kernel forms the scores)
 };
@@ -596,7 +657,8 @@ void make_pair(const DeviceTemplate& t, const TilePlan& pl, const uint8_t* label
   tp.ng = t.geom.kpad / pl.kg;
   for (int a = 0; a < kMaxAcc; ++a) {
     tp.wt[a] = pl.wt[a];
-    tp.area2[a] = pl.area2[a];
+    tp.area2[a] = pl.sad ? 0 : pl.area2[a];
+    tp.cmul[a] = pl.sad ? 1 : -2;
   }
   tp.heatmap = heatmap;
   tp.best = best;
@@ -604,6 +666,7 @@ void make_pair(const DeviceTemplate& t, const TilePlan& pl, const uint8_t* label
   o->G = G;
   o->uni = pl.uni;
   o->kg = pl.kg;
+  o->sad = pl.sad;
   o->ny = (oh + tp.tyw - 1) / tp.tyw;
   CombineParams& cp = o->cp;
   cp = CombineParams{};
@@ -614,11 +677,12 @@ void make_pair(const DeviceTemplate& t, const TilePlan& pl, const uint8_t* label
   cp.ngroups = tp.ng;
   for (int a = 0; a < kMaxAcc; ++a) {
     cp.wt[a] = pl.wt[a];
-    cp.area2[a] = pl.area2[a];
+    cp.area2[a] = pl.sad ? 0 : pl.area2[a];
+    cp.cmul[a] = pl.sad ? 1 : -2;
   }
   cp.heatmap = heatmap;
   cp.best = best;
-  o->ncblk = tp.ng > 1 ? (cp.nwin + 1023) / 1024 : 0;
+  o->ncblk = tp.ng > 1 ? (cp.nwin + kCombineWin - 1) / kCombineWin : 0;
 }
 
 size_t partial_bytes(const DeviceTemplate& t, const TilePlan& pl, int H, int W) {
@@ -628,23 +692,25 @@ size_t partial_bytes(const DeviceTemplate& t, const TilePlan& pl, int H, int W) 
   return (size_t)ng * pl.nacc * ((nwin + 3) / 4 * 4) * 2;
 }
 
-template <int G, bool UNI, int KG>
+template <int G, bool UNI, int KG, bool SAD>
 hipError_t go_tile(const TileParams& tp, int ny, hipStream_t s) {
   const dim3 grid((unsigned)tp.nx, (unsigned)ny, (unsigned)tp.ng);
-  hipLaunchKernelGGL((score_tile_kernel<G, UNI, KG>), grid, dim3(kTXW * (KG / 8)), 0, s, tp);
+  hipLaunchKernelGGL((score_tile_kernel<G, UNI, KG, SAD>), grid, dim3(kTXW * (KG / 8)), 0, s, tp);
   return hipGetLastError();
 }
 
-template <int G, bool UNI, int KG>
+template <int G, bool UNI, int KG, bool SAD>
 hipError_t go_tile_b(const TileParams* tab, const uint32_t* blk, uint32_t nblk, hipStream_t s) {
-  hipLaunchKernelGGL((score_tile_batch_kernel<G, UNI, KG>), dim3(nblk), dim3(kTXW * (KG / 8)), 0, s, tab, blk);
+  hipLaunchKernelGGL((score_tile_batch_kernel<G, UNI, KG, SAD>), dim3(nblk), dim3(kTXW * (KG / 8)), 0, s, tab,
+                     blk);
   return hipGetLastError();
 }
 
-// One pair (tab == nullptr) or a batch.  32-channel blocks for G <= 3 only.
-hipError_t go_tile_any(int G, bool uni, int kg, const TileParams& tp, int ny, const TileParams* tab,
+template <bool SAD>
+hipError_t go_tile_sad(int G, bool uni, int kg, const TileParams& tp, int ny, const TileParams* tab,
                        const uint32_t* blk, uint32_t nblk, hipStream_t s) {
-#define VQ_TILE(g, u, k) return tab ? go_tile_b<g, u, k>(tab, blk, nblk, s) : go_tile<g, u, k>(tp, ny, s)
+#define VQ_TILE(g, u, k) \
+  return tab ? go_tile_b<g, u, k, SAD>(tab, blk, nblk, s) : go_tile<g, u, k, SAD>(tp, ny, s)
   if (kg == 32) {
     switch (G * 2 + (uni ? 1 : 0)) {
       case 2: VQ_TILE(1, false, 32);
@@ -669,6 +735,13 @@ hipError_t go_tile_any(int G, bool uni, int kg, const TileParams& tp, int ny, co
     default: return hipErrorInvalidValue;
   }
 #undef VQ_TILE
+}
+
+// One pair (tab == nullptr) or a batch.  32-channel blocks for G <= 3 only.
+hipError_t go_tile_any(int G, bool uni, int kg, bool sad, const TileParams& tp, int ny, const TileParams* tab,
+                       const uint32_t* blk, uint32_t nblk, hipStream_t s) {
+  return sad ? go_tile_sad<true>(G, uni, kg, tp, ny, tab, blk, nblk, s)
+             : go_tile_sad<false>(G, uni, kg, tp, ny, tab, blk, nblk, s);
 }
 
 // Static LDS of a tile block: histograms and prefixes of G * KG / 8 rows,
@@ -720,16 +793,17 @@ size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W) {
 
 hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out) {
   const DeviceTemplate& t = *a.t;
-  TilePlan pl = plan_tile(t, true);
+  const bool wide = a.kgsel == 0 ? default_wide(t) : a.kgsel == 2;
+  TilePlan pl = plan_tile(t, wide);
   if (!pl.ok) return hipErrorInvalidConfiguration;
   if (partial_bytes(t, pl, a.H, a.W) > 0 && !a.partials) return hipErrorInvalidValue;
   // tile height from the caller (autotuned) or the default
-  const int tyw = a.tyw > 0 ? a.tyw : fused_default_tyw(t, a.H, a.W, a.n_cu);
+  const int tyw = a.tyw > 0 ? a.tyw : fused_default_tyw(t, a.H, a.W, a.n_cu, wide);
   PairTables pt;
   make_pair(t, pl, a.labels, a.H, a.W, tyw, (uint16_t*)a.partials, a.heatmap, a.best, &pt);
   if (lds_bytes_out) *lds_bytes_out = tile_lds_bytes(pt.G, pt.uni, pt.kg);
   timing_begin(K_SCORE_FUSED);
-  hipError_t e = go_tile_any(pt.G, pt.uni, pt.kg, pt.tp, pt.ny, nullptr, nullptr, 0, s);
+  hipError_t e = go_tile_any(pt.G, pt.uni, pt.kg, pt.sad, pt.tp, pt.ny, nullptr, nullptr, 0, s);
   timing_end(K_SCORE_FUSED);
   if (e != hipSuccess || pt.ncblk == 0) return e;
   timing_begin(K_SCORE_COMBINE);
@@ -738,7 +812,7 @@ hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_byt
   return e;
 }
 
-bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, ScoreBatchPlan* out) {
+bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, ScoreBatchPlan* out, bool wide) {
   out->blob.clear();
   out->launches.clear();
   out->part_bytes = 0;
@@ -746,7 +820,7 @@ bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, Scor
   std::vector<TilePlan> pls(items.size());
   for (size_t i = 0; i < items.size(); ++i) {
     const ScoreBatchItem& it = items[i];
-    pls[i] = plan_tile(*it.t);
+    pls[i] = plan_tile(*it.t, wide);
     if (!pls[i].ok || it.tyw < 1) return false;
     const size_t pb = partial_bytes(*it.t, pls[i], it.H, it.W);
     uint16_t* pp = part ? (uint16_t*)((char*)part + out->part_bytes) : nullptr;
@@ -768,12 +842,13 @@ bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, Scor
   };
   for (int kg : {32, 16})
   for (int G = 1; G <= 4; ++G)
+  for (int sad = 1; sad >= 0; --sad)
     for (int u = 0; u < 2; ++u) {
       std::vector<TileParams> tab;
       std::vector<uint32_t> blk;
       for (size_t i : order) {
         PairTables& pt = pts[i];
-        if (pt.G != G || pt.uni != (u == 1) || pt.kg != kg) continue;
+        if (pt.G != G || pt.uni != (u == 1) || pt.kg != kg || pt.sad != (sad == 1)) continue;
         pt.tp.b0 = (uint32_t)blk.size();
         const int64_t nb = (int64_t)pt.tp.nx * pt.ny * pt.tp.ng;
         if ((int64_t)blk.size() + nb > 0x7FFFFFFF) return false;
@@ -786,6 +861,7 @@ bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, Scor
       l.G = G;
       l.uni = u;
       l.kg = kg;
+      l.sad = sad;
       l.tab_off = put(tab.data(), tab.size() * sizeof(TileParams));
       l.blk_off = put(blk.data(), blk.size() * 4);
       l.nblk = (uint32_t)blk.size();
@@ -820,8 +896,8 @@ hipError_t launch_score_batch(const ScoreBatchPlan& pl, const uint8_t* d_blob, h
     hipError_t e;
     if (l.kind == 0) {
       timing_begin(K_SCORE_FUSED);
-      e = go_tile_any(l.G, l.uni != 0, l.kg, TileParams{}, 0, (const TileParams*)(d_blob + l.tab_off), blk,
-                      l.nblk, s);
+      e = go_tile_any(l.G, l.uni != 0, l.kg, l.sad != 0, TileParams{}, 0,
+                      (const TileParams*)(d_blob + l.tab_off), blk, l.nblk, s);
       timing_end(K_SCORE_FUSED);
     } else {
       timing_begin(K_SCORE_COMBINE);
@@ -836,6 +912,10 @@ hipError_t launch_score_batch(const ScoreBatchPlan& pl, const uint8_t* d_blob, h
 
 bool fused_supported(const DeviceTemplate& t) { return plan_tile(t).ok; }
 
+bool fused_wide_allowed(const DeviceTemplate& t) { return plan_tile(t, true).kg == 32; }
+
+bool fused_default_wide(const DeviceTemplate& t) { return default_wide(t); }
+
 int fused_groups(const DeviceTemplate& t) {
   const TilePlan pl = plan_tile(t);
   return pl.ok ? t.geom.kpad / pl.kg : t.geom.kpad / 16;
@@ -843,8 +923,8 @@ int fused_groups(const DeviceTemplate& t) {
 
 // Tiles fill whole rounds of the blocks resident per compute unit (at least
 // 8 rows).
-int fused_default_tyw(const DeviceTemplate& t, int H, int W, int n_cu) {
-  TilePlan pl = plan_tile(t, true);
+int fused_default_tyw(const DeviceTemplate& t, int H, int W, int n_cu, bool wide) {
+  TilePlan pl = plan_tile(t, wide);
   if (!pl.ok) return 8;
   const int ow = W - t.w + 1, oh = H - t.h + 1;
   const int nx = (ow + pl.txw - 1) / std::max(pl.txw, 1);

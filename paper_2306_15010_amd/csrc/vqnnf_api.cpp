@@ -45,6 +45,9 @@ vqnnf_status ok() { return VQNNF_OK; }
 
 constexpr int kCtxMagic = 0x51CE7001;
 constexpr int kTplMagic = 0x7E3B1A7E;
+// tuned score tile choice: window rows per tile, this bit set for 32-channel
+// tile blocks
+constexpr int kScoreWide = 1 << 16;
 
 struct Buffer {
   void* p = nullptr;
@@ -97,8 +100,9 @@ struct vqnnf_ctx {
   Buffer b_tab;        // argument tables (re-score, then score)
   std::vector<uint8_t> b_tab_host;     // what b_tab holds
   void* b_tab_at = nullptr;            // ... at this allocation
-  std::map<std::vector<int>, int> btyw_cache;   // batch shapes -> window rows per tile
-  // autotuned window rows per score tile, by shape (w, h, g, kpad, H, W, uniform bins)
+  std::map<std::vector<int>, int> btyw_cache;   // batch shapes -> score tile choice
+  // autotuned score tile choice (window rows per tile, kScoreWide), by shape
+  // (w, h, g, kpad, H, W, uniform bins)
   bool autotune = true;
   bool capturing = false;
   std::map<std::vector<int>, int> tyw_cache;
@@ -813,23 +817,37 @@ vqnnf_status enqueue_score(vqnnf_ctx* c, const vqnnf_template* t, const uint8_t*
     bool uni = true;
     for (int f = 2; f < d.n_filters; ++f) uni = uni && d.weights[f] == d.weights[1];
     const std::vector<int> key = {d.w, d.h, d.grid.g, d.geom.kpad, H, W, uni ? 1 : 0};
+    // a tile choice: window rows per tile, plus kScoreWide for 32-channel
+    // blocks (untuned: the default block width and height)
+    auto set_choice = [&](int v) {
+      a.tyw = v & (kScoreWide - 1);
+      a.kgsel = (v & kScoreWide) ? 2 : 1;
+    };
     auto it = c->tyw_cache.find(key);
     if (it != c->tyw_cache.end()) {
-      a.tyw = it->second;
+      set_choice(it->second);
     } else if (tune && c->autotune && !c->capturing) {
-      // time each candidate tile height twice on this very call (every run
-      // writes the same heatmap and key), keep the fastest for the shape
+      // time each candidate block width and tile height twice on this very
+      // call (every run writes the same heatmap and key), keep the fastest
+      // for the shape
       const int oh = H - d.h + 1;
-      const int def = fused_default_tyw(d, H, W, c->n_cu);
-      std::vector<int> cand = {def};
-      for (int v : {16, 32, 64, 128, 256})
-        if (v <= oh && std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
+      std::vector<int> cand;
+      int def = 0;
+      for (int wide : {0, 1}) {
+        if (wide && !fused_wide_allowed(d)) continue;
+        const int flag = wide ? kScoreWide : 0;
+        const int dv = fused_default_tyw(d, H, W, c->n_cu, wide != 0) | flag;
+        if ((wide != 0) == fused_default_wide(d)) def = dv;
+        cand.push_back(dv);
+        for (int v : {16, 32, 64, 128, 256})
+          if (v <= oh && std::find(cand.begin(), cand.end(), v | flag) == cand.end()) cand.push_back(v | flag);
+      }
       set_timing_hook(nullptr);
       std::vector<hipEvent_t> ev(2 * cand.size());
       for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
       for (int rep = 0; rep < 2; ++rep)
         for (size_t ci = 0; ci < cand.size(); ++ci) {
-          a.tyw = cand[ci];
+          set_choice(cand[ci]);
           if (rep == 1) HIP_TRY(hipEventRecord(ev[2 * ci], c->stream));
           HIP_TRY(launch_score_fused(a, c->stream, &lds));
           if (rep == 1) HIP_TRY(hipEventRecord(ev[2 * ci + 1], c->stream));
@@ -1894,12 +1912,13 @@ std::vector<int> batch_shape_key(const std::vector<ScoreBatchItem>& items, int n
   return key;
 }
 
-// Builds the batched score tables for window rows `tyw` (partial sums in
-// b_part) and appends them to blob at a 256-byte boundary; returns the offset.
-vqnnf_status plan_batch_score(vqnnf_ctx* c, std::vector<ScoreBatchItem> items, int tyw, ScoreBatchPlan& pl,
+// Builds the batched score tables for a tile choice (window rows per tile,
+// kScoreWide for 32-channel blocks; partial sums in b_part) and appends them
+// to blob at a 256-byte boundary; returns the offset.
+vqnnf_status plan_batch_score(vqnnf_ctx* c, std::vector<ScoreBatchItem> items, int choice, ScoreBatchPlan& pl,
                               std::vector<uint8_t>& blob, size_t* off) {
-  for (ScoreBatchItem& it : items) it.tyw = tyw;
-  if (!plan_score_batch(items, c->b_part.p, &pl))
+  for (ScoreBatchItem& it : items) it.tyw = choice & (kScoreWide - 1);
+  if (!plan_score_batch(items, c->b_part.p, &pl, (choice & kScoreWide) != 0))
     return fail(VQNNF_EINVAL, "batched score: a pair's bank or size is outside the on-chip kernel's range");
   *off = (blob.size() + 255) / 256 * 256;
   blob.resize(*off + pl.blob.size());
@@ -2048,12 +2067,18 @@ vqnnf_status vqnnf_match_batched(vqnnf_ctx* c, int32_t n, const vqnnf_template* 
     return ok();
   };
   if ((s = prepare_tables())) return s;
-  // Times each candidate tile height on this very call (every run writes the
-  // same heatmaps and keys) and keeps the fastest for the batch's shapes.
+  // Times each candidate block width and tile height on this very call (every
+  // run writes the same heatmaps and keys) and keeps the fastest for the
+  // batch's shapes.
   auto tune_score = [&]() -> vqnnf_status {
     std::vector<int> cand = {tyw};
-    for (int v : {16, 32, 64, 128, 256})
-      if (std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
+    bool any_wide = false;
+    for (const ScoreBatchItem& it : fw.score) any_wide = any_wide || fused_wide_allowed(*it.t);
+    for (int flag : {0, kScoreWide}) {
+      if (flag && !any_wide) continue;
+      for (int v : {16, 32, 64, 128, 256})
+        if (std::find(cand.begin(), cand.end(), v | flag) == cand.end()) cand.push_back(v | flag);
+    }
     std::vector<ScoreBatchPlan> pls(cand.size());
     std::vector<uint8_t> cblob;
     std::vector<size_t> offs(cand.size());

@@ -276,6 +276,8 @@ struct ScoreArgs {
   void* partials;              // on-chip path: per channel group partial sums
   int n_cu;                    // compute units (tile sizing)
   int tyw;                     // on-chip path: window rows per tile, 0 = default sizing
+  int kgsel;                   // on-chip path: channels per tile block, 0 = default rule,
+                               // 1 = 16, 2 = 32 where the grid allows
 };
 hipError_t launch_score_fused(const ScoreArgs& a, hipStream_t s, size_t* lds_bytes_out);
 hipError_t launch_score_integral(const ScoreArgs& a, hipStream_t s);
@@ -295,6 +297,7 @@ struct ScoreBatchItem {
 struct ScoreBatchLaunch {
   int kind;                    // 0 tile, 1 combine
   int G, uni, kg, nacc;        // kg: channels per tile block
+  int sad;                     // tile blocks sum |T_j - C_j|
   size_t tab_off, blk_off;     // byte offsets into the table blob
   uint32_t nblk;
 };
@@ -305,16 +308,23 @@ struct ScoreBatchPlan {
 };
 // Plans the launches with the partial sums placed in `part` (nullptr: sizes
 // only).  False when a pair's bank is not on-chip or a size overflows.
-bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, ScoreBatchPlan* out);
+// wide: 32-channel tile blocks for the pairs whose grid allows them.
+bool plan_score_batch(const std::vector<ScoreBatchItem>& items, void* part, ScoreBatchPlan* out,
+                      bool wide = false);
 // d_blob: a device copy of plan.blob.
 hipError_t launch_score_batch(const ScoreBatchPlan& plan, const uint8_t* d_blob, hipStream_t s);
 // True when the on-chip score kernel can take this template's bank.
 bool fused_supported(const DeviceTemplate& t);
+// The on-chip score can use 32-channel tile blocks for this template; and
+// whether a single pair uses them by default.
+bool fused_wide_allowed(const DeviceTemplate& t);
+bool fused_default_wide(const DeviceTemplate& t);
 int fused_groups(const DeviceTemplate& t);   // channel groups of the tile score
 // Scratch bytes of the on-chip path's per-channel-group partial sums.
 size_t fused_partial_bytes(const DeviceTemplate& t, int H, int W);
-// Default window rows per tile of the on-chip score for this shape.
-int fused_default_tyw(const DeviceTemplate& t, int H, int W, int n_cu);
+// Default window rows per tile of the on-chip score for this shape and
+// block width.
+int fused_default_tyw(const DeviceTemplate& t, int H, int W, int n_cu, bool wide);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
 
 // k-means of one template's points on the device (all buffers device).
