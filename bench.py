@@ -27,11 +27,17 @@ METRIC = "query px/s for VQ-NNF assign+filter+score, BF16-refined vs FP32, label
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
-# 32-bit vector lane-ops per second: 256 CUs x 128 lanes per clock x 2.4 GHz =
-# 78.6 T, the FP32 vector peak (157.3 TFLOP/s) with an FMA as one lane-op.
-# (A low-dimensional assignment kernel of plain FP32 subtract/FMA measured
-# 39 T lane-ops/s, above what 64 lanes per clock per CU would allow.)
-ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# LDS read bandwidth: 256 bytes per clock per CU x 256 CUs x 2.4 GHz = 157.3
+# TB/s (gfx950 doubles the 128 B/clock of earlier CDNA LDS; a conflict-free
+# ds_read_b128 loop over the whole chip measured 114 TB/s = 186 B per clock
+# per CU, more than 128 could deliver)
+LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12
+# vector ALU issue: two wave64 instructions per clock per CU (4 SIMDs, a
+# full-rate 32-bit operation takes 2 clocks) = 256 x 128 lanes x 2.4 GHz =
+# 78.6 T lane-ops/s, the FP32 vector peak of 157.3 TFLOP/s with an FMA as one
+# lane-op (a chip-wide loop of independent v_fma_f32 measured 1.62 wave
+# instructions per clock per CU; v_sad_u16 issues at half that rate)
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -45,7 +51,34 @@ def workload_desc(name, wl):
             f"full+{t.grid}x{t.grid} bank")
 
 
-def kernel_roofline(name, avg_ms, n_pix, D, qbytes, k, terms, n_win, n_f):
+def score_lds_bytes(H, W, w, h, g, kpad):
+    """Bytes the on-chip score tile kernel moves through LDS for one (template,
+    map) pair: per window row of a tile and 8 channels, the g band prefix rows
+    (nseg segments of 7 columns, 16-byte entries) are read from the column
+    histograms and written (2 x 16 B per entry), and every window reads
+    g(g+1) 16-byte taps.  Tile widths follow the kernel's plan (at most 256
+    windows, balanced over the map); the block width and tile height do not
+    change the total."""
+    kSL, kNSeg = 7, 53
+    ow, oh = W - w + 1, H - h + 1
+    txw_max = min(256, kSL * kNSeg - kSL + 1 - w)
+    nx = -(-ow // txw_max)
+    txw = -(-ow // nx)
+    total = 0
+    for bx in range(nx):
+        txv = min(txw, ow - bx * txw)
+        nseg = (txv + w - 1) // kSL + 1
+        total += oh * (kpad // 8) * (g * nseg * kSL * 32 + txv * g * (g + 1) * 16)
+    return total
+
+
+def kpad_of(k):
+    """Padded codebook size: blocks of 16 codewords, rounded to 1-4, 8 or 16 blocks."""
+    kb = (k + 15) // 16
+    return 16 * (8 if 4 < kb <= 8 else 16 if kb > 8 else kb)
+
+
+def kernel_roofline(name, avg_ms, n_pix, D, qbytes, k, terms, lds_bytes=None):
     """Algorithmic work of one launch of `name` and the bound it is held to."""
     s = avg_ms / 1e3
     if name in ("assign_bf16_refined", "assign_fp32_plain"):
@@ -54,12 +87,10 @@ def kernel_roofline(name, avg_ms, n_pix, D, qbytes, k, terms, n_win, n_f):
         return {"bound": "hbm", "achieved": by / s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": by / s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": by,
                 "mfma_tflops": 2.0 * n_pix * k * D * terms / s / 1e12}
-    if name == "score_partial":
-        # per window, filter and channel: |T - C| and its accumulation (2 ops)
-        # plus the box count from the integral-image taps (3 ops)
-        ops = n_win * n_f * k * 5
-        return {"bound": "alu", "achieved": ops / s / 1e12, "peak": ALU_PEAK_TOPS,
-                "unit": "Tops/s", "frac": ops / s / 1e12 / ALU_PEAK_TOPS, "algorithmic_ops": ops}
+    if name == "score_partial" and lds_bytes:
+        ach = lds_bytes / s / 1e12
+        return {"bound": "lds", "achieved": ach, "peak": LDS_PEAK_TBS, "unit": "TB/s",
+                "frac": ach / LDS_PEAK_TBS, "algorithmic_bytes": lds_bytes}
     return None
 
 
@@ -114,6 +145,29 @@ def read_probe(n_bytes=1 << 30, reps=3):
         a.sum()
     torch.cuda.synchronize()
     print(json.dumps({"read_probe_bytes": n_bytes, "reps": reps}), flush=True)
+
+
+def peak_probe():
+    """Chip-wide throughput probes (bench_probe.hip): wave64 VALU instructions
+    per clock per CU for v_add_u32, v_sad_u16 and v_fma_f32, and LDS bytes read
+    per clock per CU with conflict-free ds_read_b128, at the 2.4 GHz peak clock."""
+    import ctypes
+    import torch
+    torch.cuda.init()
+    lib = ctypes.CDLL(os.path.join(ROOT, "bench_probe.so"))
+    lib.bench_probe_run.argtypes = [ctypes.POINTER(ctypes.c_double)]
+    out = (ctypes.c_double * 5)()
+    rc = lib.bench_probe_run(out)
+    if rc:
+        raise RuntimeError(f"bench_probe_run: HIP error {rc}")
+    ncu = out[4]
+    per_clock = lambda v: v / (ncu * 2.4e9)
+    print(json.dumps({"compute_units": int(ncu),
+                      "valu_wave_instr_per_cu_clock": {"v_add_u32": per_clock(out[0]),
+                                                       "v_sad_u16": per_clock(out[1]),
+                                                       "v_fma_f32": per_clock(out[2])},
+                      "lds_read_tbs": out[3] / 1e12, "lds_read_bytes_per_cu_clock": per_clock(out[3])}),
+          flush=True)
 
 
 def secondary(name, ctx, B, synth, steps):
@@ -194,8 +248,8 @@ def paper_bank_leg(ctx, B, t, fm, qm, steps, torch):
     if "score_bank" in avg:
         ops = bank_ops_per_window(bank, t.k) * oh * ow
         ach = ops / (avg["score_bank"] * 1e-3) / 1e12
-        out["score_bank_roofline"] = {"bound": "alu", "achieved": ach, "peak": ALU_PEAK_TOPS,
-                                      "unit": "Tops/s", "frac": ach / ALU_PEAK_TOPS,
+        out["score_bank_roofline"] = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
+                                      "unit": "Tops/s", "frac": ach / VALU_PEAK_TOPS,
                                       "ops_per_window": bank_ops_per_window(bank, t.k)}
     if "integral_main" in avg:
         # weighted banks read the integral image mod 2^16: 2 bytes per entry
@@ -399,6 +453,15 @@ def batched_leg(workload, scale_down, steps, warmup, ctx, B, synth, torch, with_
         roof = {"bound": "mfma", "achieved": ach, "peak": 2500.0, "unit": "TFLOP/s", "frac": ach / 2500.0,
                 "traffic": None, "kernel": "assign_multi", "algorithmic_flop": alg,
                 "executed_tflops": 2.0 * ach, "kernel_ms_per_batch": ms_am}
+    # the batch's tile score, held to the LDS bound
+    score_roof = None
+    if "score_partial" in kt and kt["score_partial"][0] > 0:
+        lds = sum(score_lds_bytes(qm.H, qm.W, t.data.shape[1], t.data.shape[0], t.grid, kpad_of(t.k))
+                  for qm, row in zip(wl.maps, wl.templates) for t in row)
+        ach = lds / (kt["score_partial"][1] / 1e3) / 1e12
+        score_roof = {"bound": "lds", "achieved": ach, "peak": LDS_PEAK_TBS, "unit": "TB/s",
+                      "frac": ach / LDS_PEAK_TBS, "algorithmic_bytes": lds,
+                      "kernel_ms_per_batch": kt["score_partial"][1]}
     value = pair_px / (ms_graph / 1e3)
     res = {
         "metric": METRIC, "value": value, "unit": "px/s", "n_gpus": 1, "steps": steps,
@@ -410,6 +473,7 @@ def batched_leg(workload, scale_down, steps, warmup, ctx, B, synth, torch, with_
                    "global_batch": len(tpls), "pair_pixels": pair_px, "map_pixels": map_px,
                    "prec": "bf16_refined"},
         "roofline": roof,
+        "score_roofline": score_roof,
         "cpu_baseline": cpu,
         "map_px_per_s": map_px / (ms_graph / 1e3),
         "graph_batch_ms": ms_graph, "eager_batch_ms": ms_eager, "sequential_ms": ms_seq,
@@ -528,6 +592,8 @@ def main():
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--read-probe", action="store_true",
                     help="only run a read-only pass over 1 GiB (counter calibration)")
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="only run the VALU issue and LDS bandwidth probes (bench_probe.so)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path would shard "
@@ -546,6 +612,9 @@ def main():
         return
     if args.read_probe:
         read_probe()
+        return
+    if args.peak_probe:
+        peak_probe()
         return
     if args.workload in ("c4", "c5"):
         # the full batches need more scratch than the default cap (re-score
@@ -608,8 +677,8 @@ def main():
     kernels = {k: {"launches": v[0], "avg_ms": v[1] / max(1, v[0])} for k, v in kt.items()}
     per_step = {k: v[1] / args.steps for k, v in kt.items()}
     dom = max(per_step, key=per_step.get)
-    n_f = 1 + t.grid * t.grid
-    roof = kernel_roofline(dom, kernels[dom]["avg_ms"], n_pix, D, qbytes, t.k, 2, oh * ow, n_f)
+    lds = score_lds_bytes(qm.H, qm.W, w, h, t.grid, kpad_of(t.k))
+    roof = kernel_roofline(dom, kernels[dom]["avg_ms"], n_pix, D, qbytes, t.k, 2, lds)
     roof = dict(roof) if roof else {}
     roof["kernel"] = dom
     roof["duration_source"] = (f"HIP events on the context stream around each launch, mean of "
@@ -618,7 +687,7 @@ def main():
     roof["traffic"] = measured_traffic(dom, args.workload)
     others = {}
     for k2 in kernels:
-        r2 = kernel_roofline(k2, kernels[k2]["avg_ms"], n_pix, D, qbytes, t.k, 2, oh * ow, n_f)
+        r2 = kernel_roofline(k2, kernels[k2]["avg_ms"], n_pix, D, qbytes, t.k, 2, lds)
         if r2:
             others[k2] = {"frac": round(r2["frac"], 4), "achieved": round(r2["achieved"], 2),
                           "unit": r2["unit"], "bound": r2["bound"]}
