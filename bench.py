@@ -149,14 +149,16 @@ def read_probe(n_bytes=1 << 30, reps=3):
 
 def peak_probe():
     """Chip-wide throughput probes (bench_probe.hip): wave64 VALU instructions
-    per clock per CU for v_add_u32, v_sad_u16 and v_fma_f32, and LDS bytes read
-    per clock per CU with conflict-free ds_read_b128, at the 2.4 GHz peak clock."""
+    per clock per CU for v_add_u32, v_sad_u16 and v_fma_f32, LDS bytes read per
+    clock per CU with conflict-free ds_read_b128 (both at the 2.4 GHz peak
+    clock), and the dense matrix-core rates of the BF16 and block-scaled FP8
+    instructions."""
     import ctypes
     import torch
     torch.cuda.init()
     lib = ctypes.CDLL(os.path.join(ROOT, "bench_probe.so"))
     lib.bench_probe_run.argtypes = [ctypes.POINTER(ctypes.c_double)]
-    out = (ctypes.c_double * 5)()
+    out = (ctypes.c_double * 7)()
     rc = lib.bench_probe_run(out)
     if rc:
         raise RuntimeError(f"bench_probe_run: HIP error {rc}")
@@ -166,7 +168,9 @@ def peak_probe():
                       "valu_wave_instr_per_cu_clock": {"v_add_u32": per_clock(out[0]),
                                                        "v_sad_u16": per_clock(out[1]),
                                                        "v_fma_f32": per_clock(out[2])},
-                      "lds_read_tbs": out[3] / 1e12, "lds_read_bytes_per_cu_clock": per_clock(out[3])}),
+                      "lds_read_tbs": out[3] / 1e12, "lds_read_bytes_per_cu_clock": per_clock(out[3]),
+                      "mfma_dense_tflops": {"bf16_16x16x32": out[5] / 1e12,
+                                            "fp8_e4m3_scaled_16x16x128": out[6] / 1e12}}),
           flush=True)
 
 

@@ -342,6 +342,9 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
     for (int a = 0; a < NACC; ++a) acc[a] = 0u;
     if (xl < txv) {
       uint32_t full[4] = {0u, 0u, 0u, 0u};
+      // uniform bins: one sum per channel pair, added at the end, so the
+      // G*G*4 terms form four independent chains instead of one
+      uint32_t bins[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int b = 0; b < G; ++b) {
         uint4 hv[G + 1];
@@ -352,14 +355,21 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
 #pragma unroll
           for (int a = 0; a < G; ++a) {
             const uint32_t bin = comp(hv[a + 1], s) - comp(hv[a], s);
-            const int ai = UNI ? 1 : 1 + b * G + a;
-            acc[ai] = term(bin, T[1 + b * G + a][s], acc[ai]);
+            if constexpr (UNI) {
+              bins[s] = term(bin, T[1 + b * G + a][s], bins[s]);
+            } else {
+              const int ai = 1 + b * G + a;
+              acc[ai] = term(bin, T[1 + b * G + a][s], acc[ai]);
+            }
           }
           full[s] += comp(hv[G], s) - comp(hv[0], s);
         }
       }
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc[0] = term(full[s], T[0][s], acc[0]);
+      if constexpr (UNI) acc[1] = (bins[0] + bins[1]) + (bins[2] + bins[3]);
+      uint32_t f01 = term(full[0], T[0][0], 0u), f23 = term(full[2], T[0][2], 0u);
+      f01 = term(full[1], T[0][1], f01);
+      f23 = term(full[3], T[0][3], f23);
+      acc[0] = f01 + f23;
       if (pq >= 1) {
         uint32_t o[NOUT];
         merge(o);
