@@ -5,22 +5,18 @@
 // window with top-left (x, y) has counts
 //   C_j = P[y+Y1][x+X1] - P[y+Y0][x+X1] - P[y+Y1][x+X0] + P[y+Y0][x+X0],
 // Alg. 2's dilation filter of a single bin (taps at the bin's corners with
-// weights [[1,-1],[-1,1]]).  The score is -sum_f w_f * sum_j |T_f,j - C_f,j|.
-// Since a window bin and the template bin have the same area A,
-//   sum_j |T_j - C_j| = 2*A - 2*sum_j min(T_j, C_j),
-// which lets two channels share one packed 16-bit min and add.
+// weights [[1,-1],[-1,1]]).  The score is -sum_f w_f * sum_j |T_f,j - C_f,j|,
+// summed two channels at a time with v_sad_u16 (or, where twice a filter
+// area overflows 16 bits, as 2*A - 2*sum_j min(T_j, C_j), since a window bin
+// and the template bin have the same area A).
 //
 // score_fused: the benchmark bank (full window + g x g grid) straight from
-// the labels.  A block owns 128 x 16 (or 64 x 16) windows.  For the current window row y
-// it keeps, per grid row-band b (rows [y+Y_b, y+Y_b+1)) and per column c of
-// the 128 + w - 1 columns it touches, the band's column histogram Q_b[c]
-// (uint8 x k in LDS; label values are clamped to the padded channel range
-// so an out-of-range label can never address outside LDS).  Moving to row y+1 only changes two labels per band and
-// column.  A per-channel prefix along the columns gives
+// the labels, tile by tile (below): per grid row-band b and column c the
+// band's column histogram Q_b[c] and its prefix along the columns
 //   H_b[c] = P[y+Y_b+1][x0+c] - P[y+Y_b][x0+c] - (same at column x0),
-// the difference of two integral-image rows, and the bin counts of window x
-// are H_b[x+X_a+1] - H_b[x+X_a].  The prefix runs over channel chunks so that
-// H fits in LDS next to Q.
+// the difference of two integral-image rows, so the bin counts of window x
+// are H_b[x+X_a+1] - H_b[x+X_a].  Moving to window row y+1 changes two
+// labels per band and column.
 //
 // score_integral: any indicator bank, reading the taps from a precomputed
 // integral image (vqnnf_filter's output).
@@ -85,15 +81,15 @@ __device__ __forceinline__ void block_max_to(unsigned long long key, unsigned lo
 //   1. one wave per (band, pair group) row rebuilds its prefix: lane s sums
 //      segment s (kSL columns, kept in registers), a DPP scan of the segment
 //      totals gives the offsets, the lane writes its segment of H;
-//   2. every thread scores one window against four channel pairs,
-//      accumulating sum_j min(T_j, C_j) with v_dot2_u32_u16, while the
-//      column threads move Q down to the next row (two labels per band and
-//      column change).
-// Bins of equal weight share one sum.  With one channel group the tile
-// kernel forms eq. 2 and the argmax itself; otherwise the integer sums of
-// the group are written per window as 16-bit words (a sum is at most the
-// window area, and template sides are at most 255) and a second kernel adds
-// the groups, forms eq. 2 and the argmax.
+//   2. every thread scores one window against four channel pairs and hands
+//      its sums to LDS, while the column threads move Q down to the next row
+//      (two labels per band and column change).
+// The previous row's sums are added over the pair groups and stored during
+// phase 1 by the waves that have no prefix row.  Bins of equal weight share
+// one sum.  With one channel group the tile kernel forms eq. 2 and the
+// argmax itself; otherwise the integer sums of the group are written per
+// window as 16-bit words (at most twice the window area, kept below 2^16)
+// and a second kernel adds the groups, forms eq. 2 and the argmax.
 constexpr int kSL = 7;                 // columns per prefix segment (odd: a wave's lanes hit distinct banks)
 constexpr int kNSeg = 53;              // segments per row (<= 64 lanes)
 constexpr int kHS = kSL * kNSeg;       // LDS row length in 16-byte entries
@@ -189,7 +185,7 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
   static_assert(kColsMax + 1 <= kST, "one column per thread");
   __shared__ uint4 Qs[NR][kHS];
   __shared__ uint4 Hs[NR][kHS];
-  __shared__ uint16_t red[kPQ - 1][NOUT][kTXW];      // pair groups 1..kPQ-1: sums (<= w*h < 2^16)
+  __shared__ uint16_t red[kPQ][NOUT][kTXW];          // every pair group's sums of the row (< 2^16)
   const auto labs = gbl(p.labels);
   const auto t16 = gbl(p.t16);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -283,16 +279,17 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
       }
     }
   };
-  // pair group 0 adds the other pair groups' sums and stores them, or with
-  // one channel group forms the score itself
-  auto store_row = [&](int yy) {
+  // window x of row yy: adds the pair groups' sums from LDS and stores them,
+  // or with one channel group forms the score itself
+  auto store_one = [&](int yy, int x) {
     uint32_t v[NOUT];
-    merge(v);
 #pragma unroll
-    for (int g2 = 0; g2 < kPQ - 1; ++g2)
+    for (int a = 0; a < NOUT; ++a) v[a] = red[0][a][x];
 #pragma unroll
-      for (int a = 0; a < NOUT; ++a) v[a] += red[g2][a][xl];
-    const int64_t win = (int64_t)yy * p.ow + x0 + xl;
+    for (int g2 = 1; g2 < kPQ; ++g2)
+#pragma unroll
+      for (int a = 0; a < NOUT; ++a) v[a] += red[g2][a][x];
+    const int64_t win = (int64_t)yy * p.ow + x0 + x;
     float s = 0.f;
 #pragma unroll
     for (int a = 0; a < NOUT; ++a) {
@@ -310,6 +307,13 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
       const unsigned long long k2 = best_key(sc, (uint32_t)win);
       key = k2 > key ? k2 : key;
     }
+  };
+  // the row's stores go to the waves without a prefix row (they are idle
+  // while the prefix rows are rebuilt), or to every wave when all have one
+  constexpr int NW = kST / 64;
+  constexpr int SW = NW > NR ? NR : 0;               // first storing wave
+  auto store_row = [&](int yy) {
+    for (int x = tid - SW * 64; x >= 0 && x < txv; x += kST - SW * 64) store_one(yy, x);
   };
   for (int dy = 0; dy < tyv; ++dy) {
     const int y = y0 + dy;
@@ -335,7 +339,7 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
         for (int i = 0; i < kSL; ++i) Hs[wv][c0 + i] = add4(off, loc[i]);
       }
     }
-    if (dy > 0 && pq == 0 && xl < txv) store_row(y - 1);
+    if (dy > 0) store_row(y - 1);
     __syncthreads();   // H at row y complete
     // ---- phase 2: score window xl against pairs 4*pq .. 4*pq + 3 of the group
 #pragma unroll
@@ -370,12 +374,10 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
       f01 = term(full[1], T[0][1], f01);
       f23 = term(full[3], T[0][3], f23);
       acc[0] = f01 + f23;
-      if (pq >= 1) {
-        uint32_t o[NOUT];
-        merge(o);
+      uint32_t o[NOUT];
+      merge(o);
 #pragma unroll
-        for (int a = 0; a < NOUT; ++a) red[pq - 1][a][xl] = (uint16_t)o[a];
-      }
+      for (int a = 0; a < NOUT; ++a) red[pq][a][xl] = (uint16_t)o[a];
     }
     // ---- vertical update of Q to row y + 1, then prefetch for row y + 2
     if (dy + 1 < tyv && tid < cols) {
@@ -391,7 +393,7 @@ __device__ __forceinline__ void score_tile_body(const TileParams& p, int bx, int
     }
   }
   __syncthreads();
-  if (pq == 0 && xl < txv) store_row(y0 + tyv - 1);
+  store_row(y0 + tyv - 1);
   if (p.ng == 1) block_max_n<kST / 64>(key, p.best);
 }
 
@@ -755,10 +757,10 @@ hipError_t go_tile_any(int G, bool uni, int kg, bool sad, const TileParams& tp, 
 }
 
 // Static LDS of a tile block: histograms and prefixes of G * KG / 8 rows,
-// plus the pair groups' hand-over sums.
+// plus every pair group's sums of a row.
 size_t tile_lds_bytes(int G, bool uni, int kg) {
   const int pq = kg / 8;
-  return (size_t)2 * G * pq * kHS * 16 + (size_t)(pq - 1) * (uni ? 2 : kMaxAcc) * kTXW * 2;
+  return (size_t)2 * G * pq * kHS * 16 + (size_t)pq * (uni ? 2 : kMaxAcc) * kTXW * 2;
 }
 
 // Tile blocks resident per compute unit (160 KB of LDS, 2048 threads).
