@@ -52,6 +52,33 @@ __device__ __forceinline__ void merge_top2(float& v1, int& j1, float& v2, float 
 }
 
 
+// Branch-free form of merge_top2 (every lane takes the same path).
+__device__ __forceinline__ void merge_top2_sel(float& v1, int& j1, float& v2, float o1, int oj1, float o2) {
+  const bool take = o1 < v1 || (o1 == v1 && oj1 < j1);
+  const float nv2 = take ? fminf(v1, o2) : fminf(v2, o1);
+  v1 = take ? o1 : v1;
+  j1 = take ? oj1 : j1;
+  v2 = nv2;
+}
+
+// Lane l's partner value x[l ^ 16] and x[l ^ 32] for a full wave, with
+// gfx950's row swaps (v_permlane16_swap: odd 16-lane rows of the first
+// operand with even rows of the second; v_permlane32_swap: upper half of the
+// first with lower half of the second) instead of an LDS permute.  Called
+// with both operands equal, the first result holds the rows / half that
+// moved into the first operand, the second those that moved out of it.
+__device__ __forceinline__ uint32_t lane_xor16(uint32_t x, int lane) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  return (lane & 16) ? r[0] : r[1];
+}
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t x, int lane) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return (lane & 32) ? r[0] : r[1];
+}
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int m, int lane) {
+  return m == 16 ? lane_xor16(x, lane) : lane_xor32(x, lane);
+}
+
 constexpr int kWPB = 8;
 
 

@@ -379,7 +379,8 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       // best (first index on ties) and second-best score of this lane's
-      // codewords, in ascending index order, without branches
+      // codewords, in ascending index order, without branches: the second
+      // best is the median of (best, second, new) before the best moves
       float v1 = 3.4e38f, v2 = 3.4e38f;
       int j1 = 0;
 #pragma unroll
@@ -388,17 +389,19 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
         for (int i = 0; i < 4; ++i) {
           const float v = acc[mb][nb][i];
           const bool better = v < v1;
-          v2 = fminf(v2, fmaxf(v1, v));
+          v2 = __builtin_amdgcn_fmed3f(v1, v2, v);
           j1 = better ? 16 * mb + 4 * g + i : j1;
-          v1 = better ? v : v1;
+          v1 = fminf(v1, v);
         }
       float q2 = qn2[nb];
+      // merge over the four lane groups (lanes 16 and 32 apart)
 #pragma unroll
       for (int m = 16; m <= 32; m <<= 1) {
-        const float o1 = __shfl_xor(v1, m), o2 = __shfl_xor(v2, m);
-        const int oj = __shfl_xor(j1, m);
-        merge_top2(v1, j1, v2, o1, oj, o2);
-        q2 += __shfl_xor(q2, m);
+        const float o1 = __uint_as_float(lane_xor(__float_as_uint(v1), m, lane));
+        const float o2 = __uint_as_float(lane_xor(__float_as_uint(v2), m, lane));
+        const int oj = (int)lane_xor((uint32_t)j1, m, lane);
+        merge_top2_sel(v1, j1, v2, o1, oj, o2);
+        q2 += __uint_as_float(lane_xor(__float_as_uint(q2), m, lane));
       }
       // upper bound of ||q||: FP32 sum of squares error, then sqrt rounding
       const float nq = sqrtf(q2 * (1.0f + (float)(p.D + 8) * 0x1.0p-23f)) * (1.0f + 0x1.0p-20f);
@@ -421,12 +424,12 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
             if (acc[mb][nb][i] - v1 <= thr) mw[mb >> 1] |= 1u << (16 * (mb & 1) + 4 * g + i);
 #pragma unroll
         for (int w = 0; w < MW; ++w) {
-          mw[w] |= __shfl_xor(mw[w], 16);
-          mw[w] |= __shfl_xor(mw[w], 32);
+          mw[w] |= lane_xor16(mw[w], lane);
+          mw[w] |= lane_xor32(mw[w], lane);
         }
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(p.wl_count, (uint32_t)__popcll(bal));
-        base = __builtin_amdgcn_readfirstlane(__shfl(base, 0));
+        base = __builtin_amdgcn_readfirstlane(base);   // lane 0's: every lane is active here
         if (fl) {
           // resources based at the wave's first slot (64-bit pointer
           // arithmetic), so the 32-bit offsets stay below 64 entries
