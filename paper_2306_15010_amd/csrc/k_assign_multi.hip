@@ -179,8 +179,8 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       float q2 = qn2[nb];
-      q2 += __shfl_xor(q2, 16);
-      q2 += __shfl_xor(q2, 32);
+      q2 += __uint_as_float(lane_xor16(__float_as_uint(q2), lane));
+      q2 += __uint_as_float(lane_xor32(__float_as_uint(q2), lane));
       const float nq = sqrtf(q2 * (1.0f + (float)(p.D + 8) * 0x1.0p-23f)) * (1.0f + 0x1.0p-20f);
       const int64_t pix = tile * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
       const bool owner = (g == 0) && (pix < mpix);
@@ -196,15 +196,16 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
           for (int i = 0; i < 4; ++i) {
             const float v = acc[mb][nb][i];
             const bool better = v < v1;
-            v2 = fminf(v2, fmaxf(v1, v));
+            v2 = __builtin_amdgcn_fmed3f(v1, v2, v);   // second best before the best moves
             j1 = better ? 16 * (mb - sg * SB) + 4 * g + i : j1;
-            v1 = better ? v : v1;
+            v1 = fminf(v1, v);
           }
 #pragma unroll
         for (int m = 16; m <= 32; m <<= 1) {
-          const float o1 = __shfl_xor(v1, m), o2 = __shfl_xor(v2, m);
-          const int oj = __shfl_xor(j1, m);
-          merge_top2(v1, j1, v2, o1, oj, o2);
+          const float o1 = __uint_as_float(lane_xor(__float_as_uint(v1), m, lane));
+          const float o2 = __uint_as_float(lane_xor(__float_as_uint(v2), m, lane));
+          const int oj = (int)lane_xor((uint32_t)j1, m, lane);
+          merge_top2_sel(v1, j1, v2, o1, oj, o2);
         }
         const float thr = (o.a0 + nq * (o.a1 + nq * o.a2)) * (1.0f + 0x1.0p-18f);
         const bool flagged = (v2 - v1) <= thr;
@@ -224,12 +225,12 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
             }
 #pragma unroll
           for (int w = 0; w < MW; ++w) {
-            mw[w] |= __shfl_xor(mw[w], 16);
-            mw[w] |= __shfl_xor(mw[w], 32);
+            mw[w] |= lane_xor16(mw[w], lane);
+            mw[w] |= lane_xor32(mw[w], lane);
           }
           uint32_t base = 0;
           if (lane == 0) base = atomicAdd(o.wl_count, (uint32_t)__popcll(bal));
-          base = __builtin_amdgcn_readfirstlane(__shfl(base, 0));
+          base = __builtin_amdgcn_readfirstlane(base);   // lane 0's: every lane is active here
           if (fl) {
             // resources based at the wave's first slot, offsets below 64 entries
             const uint32_t r = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
