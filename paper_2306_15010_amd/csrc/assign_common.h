@@ -38,21 +38,10 @@ __device__ __forceinline__ f32x4_t mfma_bf16(uint4 a, uint4 b, f32x4_t c) {
                                                  __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
 }
 
+
 // Top-2 merge of (best value, best index, second value) triples; ties in the
 // best value keep the lower index and make the second equal to the best.
-__device__ __forceinline__ void merge_top2(float& v1, int& j1, float& v2, float o1, int oj1,
-                                           float o2) {
-  if (o1 < v1 || (o1 == v1 && oj1 < j1)) {
-    v2 = fminf(v1, o2);
-    v1 = o1;
-    j1 = oj1;
-  } else {
-    v2 = fminf(v2, o1);
-  }
-}
-
-
-// Branch-free form of merge_top2 (every lane takes the same path).
+// Branch-free: every lane takes the same path.
 __device__ __forceinline__ void merge_top2_sel(float& v1, int& j1, float& v2, float o1, int oj1, float o2) {
   const bool take = o1 < v1 || (o1 == v1 && oj1 < j1);
   const float nv2 = take ? fminf(v1, o2) : fminf(v2, o1);
