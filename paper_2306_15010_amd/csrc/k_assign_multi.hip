@@ -20,6 +20,23 @@
 namespace vqnnf {
 
 constexpr int kMultiKB = 8;   // codeword blocks per pass
+
+// The launch's tables (maps, passes, outputs) are written before the launch
+// and only read by it: read through the constant address space, so that
+// they come in as scalar loads (counted apart from the vector-memory
+// requests in flight) instead of vector loads whose use would wait for the
+// next tile's query and codebook requests as well.
+template <typename T>
+__device__ __forceinline__ T ld_const(const T* base, int64_t i) {
+  static_assert(sizeof(T) % 4 == 0, "dword-sized table entries");
+  const __attribute__((address_space(4))) uint32_t* w = (const __attribute__((address_space(4))) uint32_t*)(base + i);
+  uint32_t d[sizeof(T) / 4];
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = w[k];
+  T v;
+  __builtin_memcpy(&v, d, sizeof(T));
+  return v;
+}
 static_assert(kWPB * 4 * 16 == kMultiTilePx, "tile of the fused launch");
 
 // SG: the codebook fragments of block mb + 1 are read from LDS while the
@@ -167,7 +184,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
   auto finish_sb = [&](auto sb_tag, int64_t tile, int pass) {
     constexpr int SB = decltype(sb_tag)::value;
     constexpr int MW = (SB + 1) / 2;               // candidate mask words per template
-    const MultiPass ps = mpasses[pass];
+    const MultiPass ps = ld_const(mpasses, pass);
 #pragma unroll
     for (int mb = 0; mb < KB; ++mb) {
       const f32x4_t c0 = *(const f32x4_t*)(cn_s + (pass * KB + mb) * 16 + 4 * g);
@@ -187,7 +204,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
 #pragma unroll
       for (int sg = 0; sg < KB / SB; ++sg) {
         if (sg >= ps.n_seg) break;
-        const MultiOut o = mouts[ps.tmpl0 + sg];
+        const MultiOut o = ld_const(mouts, ps.tmpl0 + sg);
         float v1 = 3.4e38f, v2 = 3.4e38f;
         int j1 = 0;
 #pragma unroll
@@ -245,7 +262,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
     }
   };
   auto finish = [&](int64_t tile, int pass) {
-    const int sb = mpasses[pass].sb;
+    const int sb = ld_const(mpasses, pass).sb;
     if (sb == 8) finish_sb(std::integral_constant<int, 8>{}, tile, pass);
     else if (sb == 4) finish_sb(std::integral_constant<int, 4>{}, tile, pass);
     else if (sb == 2) finish_sb(std::integral_constant<int, 2>{}, tile, pass);
@@ -256,10 +273,10 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
   int m = 0;
   for (int a = 0, b = p.n_maps - 1; a < b;) {
     const int c = (a + b + 1) / 2;
-    if (p.maps[c].tile0 <= lo) a = c, m = c; else b = c - 1;
+    if (ld_const(p.maps, c).tile0 <= lo) a = c, m = c; else b = c - 1;
   }
   for (int64_t t0 = lo; t0 < hi; ++m) {
-    const MultiMap& mm = p.maps[m];
+    const MultiMap mm = ld_const(p.maps, m);
     mq = (const char*)mm.q;
     mstride = mm.stride;
     mpix = mm.n_pix;
