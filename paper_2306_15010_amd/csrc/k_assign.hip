@@ -391,7 +391,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_refined_kernel(KParams p) {
           const bool better = v < v1;
           v2 = __builtin_amdgcn_fmed3f(v1, v2, v);
           j1 = better ? 16 * mb + 4 * g + i : j1;
-          v1 = fminf(v1, v);
+          v1 = better ? v : v1;
         }
       float q2 = qn2[nb];
       // merge over the four lane groups (lanes 16 and 32 apart)
