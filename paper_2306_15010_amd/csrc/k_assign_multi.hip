@@ -113,11 +113,15 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
 
   f32x4_t acc[KB][NB];
   float qn2[NB];
-  auto reset = [&]() {
+  // a pass's accumulators start at ||c_j||^2 (one more addend of the FP32
+  // sum, which the error bound counts), so the epilogue has nothing to add
+  auto reset = [&](int pass) {
 #pragma unroll
-    for (int mb = 0; mb < KB; ++mb)
+    for (int mb = 0; mb < KB; ++mb) {
+      const f32x4_t c0 = *(const f32x4_t*)(cn_s + (pass * KB + mb) * 16 + 4 * g);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = c0;
+    }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) qn2[nb] = 0.f;
   };
@@ -185,14 +189,6 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
     constexpr int SB = decltype(sb_tag)::value;
     constexpr int MW = (SB + 1) / 2;               // candidate mask words per template
     const MultiPass ps = ld_const(mpasses, pass);
-#pragma unroll
-    for (int mb = 0; mb < KB; ++mb) {
-      const f32x4_t c0 = *(const f32x4_t*)(cn_s + (pass * KB + mb) * 16 + 4 * g);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[mb][nb][i] = c0[i] + acc[mb][nb][i];
-    }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       float q2 = qn2[nb];
@@ -290,6 +286,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
     // norms of the map's passes (the previous map's epilogues are done)
     __syncthreads();
     for (int i = threadIdx.x; i < npass * 16 * KB; i += NT) cn_s[i] = mm.cnorm[i];
+    __syncthreads();   // the first pass's accumulators start from these norms
     const char* tb = set_tile(first, end, first);
     dma_cb(0, st0);
     load_q(tb, 0, qa);
@@ -299,7 +296,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
     for (int64_t tile = first; tile < end; ++tile) {
       const char* tb_next = tb;
       for (int pass = 0; pass < npass; ++pass) {
-        reset();
+        reset(pass);
         for (int gi = 0; gi < ngr; gi += 2) {
           const int gs = pass * ngr + gi;            // global group of the even step
           const bool last_g = gi + 2 == ngr;         // last pair of the pass
