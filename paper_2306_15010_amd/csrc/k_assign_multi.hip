@@ -189,18 +189,25 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
     constexpr int SB = decltype(sb_tag)::value;
     constexpr int MW = (SB + 1) / 2;               // candidate mask words per template
     const MultiPass ps = ld_const(mpasses, pass);
+    // upper bound of ||q|| per pixel block (shared by the pass's templates)
+    float nqs[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       float q2 = qn2[nb];
       q2 += __uint_as_float(lane_xor16(__float_as_uint(q2), lane));
       q2 += __uint_as_float(lane_xor32(__float_as_uint(q2), lane));
-      const float nq = sqrtf(q2 * (1.0f + (float)(p.D + 8) * 0x1.0p-23f)) * (1.0f + 0x1.0p-20f);
-      const int64_t pix = tile * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
-      const bool owner = (g == 0) && (pix < mpix);
+      nqs[nb] = sqrtf(q2 * (1.0f + (float)(p.D + 8) * 0x1.0p-23f)) * (1.0f + 0x1.0p-20f);
+    }
+    // templates outer, pixel blocks inner: one table read per template
 #pragma unroll
-      for (int sg = 0; sg < KB / SB; ++sg) {
-        if (sg >= ps.n_seg) break;
-        const MultiOut o = ld_const(mouts, ps.tmpl0 + sg);
+    for (int sg = 0; sg < KB / SB; ++sg) {
+      if (sg >= ps.n_seg) break;
+      const MultiOut o = ld_const(mouts, ps.tmpl0 + sg);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float nq = nqs[nb];
+        const int64_t pix = tile * TILE + (int64_t)wave * NB * 16 + 16 * nb + n;
+        const bool owner = (g == 0) && (pix < mpix);
         float v1 = 3.4e38f, v2 = 3.4e38f;
         int j1 = 0;
 #pragma unroll
