@@ -123,6 +123,15 @@ def test_argument_errors_on_host_context():
     assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q8ok, B.VQNNF_PREC_FP8_REFINED, lab)) == B.VQNNF_ENOTSUP
     q_null = B.FMap(None, B.VQNNF_BF16, 32, 32, 4, 4, None)
     assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q_null, 1, lab)) == B.VQNNF_EINVAL
+    # empty maps and maps at the size cap (H*W < 2^31, so 32-bit pixel
+    # indices and worklist offsets cannot wrap) are rejected before any device call
+    for Hh, Ww in ((0, 32), (32, 0), (65536, 32768)):
+        q_e = B.FMap(0x1000, B.VQNNF_BF16, Hh, Ww, 4, 4, None)
+        assert _status_of(lambda: B.vqnnf_assign(ctx, tpl, q_e, 1, lab)) == B.VQNNF_EINVAL
+        assert _status_of(lambda: B.vqnnf_match(ctx, tpl, q_e, 1, FakeTensor(0x3000))) == B.VQNNF_EINVAL
+    assert "2^31" in B.last_error()
+    assert _status_of(lambda: B.vqnnf_score(ctx, tpl, lab, 0, 32, FakeTensor(0x3000))) == B.VQNNF_EINVAL
+    assert _status_of(lambda: B.vqnnf_score(ctx, tpl, lab, 65536, 32768, FakeTensor(0x3000))) == B.VQNNF_EINVAL
     # template larger than the map
     q_small = B.FMap(0x1000, B.VQNNF_BF16, 7, 32, 4, 4, None)
     assert _status_of(lambda: B.vqnnf_match(ctx, tpl, q_small, 1, FakeTensor(0x3000))) == B.VQNNF_EINVAL
