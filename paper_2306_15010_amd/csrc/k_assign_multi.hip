@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
             const bool better = v < v1;
             v2 = __builtin_amdgcn_fmed3f(v1, v2, v);   // second best before the best moves
             j1 = better ? 16 * (mb - sg * SB) + 4 * g + i : j1;
-            v1 = fminf(v1, v);
+            v1 = better ? v : v1;                      // a select: no NaN canonicalisation
           }
 #pragma unroll
         for (int m = 16; m <= 32; m <<= 1) {
