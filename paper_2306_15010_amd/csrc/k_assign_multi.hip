@@ -217,9 +217,10 @@ __global__ __launch_bounds__(kWPB * 64) void assign_multi_kernel(MultiParams p) 
             const float v = acc[mb][nb][i];
             const bool better = v < v1;
             v2 = __builtin_amdgcn_fmed3f(v1, v2, v);   // second best before the best moves
-            j1 = better ? 16 * (mb - sg * SB) + 4 * g + i : j1;
+            j1 = better ? 16 * (mb - sg * SB) + i : j1;   // a constant operand; the lane's 4*g below
             v1 = better ? v : v1;                      // a select: no NaN canonicalisation
           }
+        j1 += 4 * g;
 #pragma unroll
         for (int m = 16; m <= 32; m <<= 1) {
           const float o1 = __uint_as_float(lane_xor(__float_as_uint(v1), m, lane));
