@@ -2,7 +2,7 @@
 
   * Every schedule of the refined assignment kernel gives the same labels
     and re-score worklist (so the same final labels), equal to the oracle's
-    on sampled pixels (determinism across tuner choices).
+    on sampled pixels (results do not depend on the tuner's choice).
   * The first refined call of a shape class tunes the schedule and the first
     match of a shape tunes the score tile height; with a tune file both land
     in it, and a new context reading the file tunes nothing again (the file
